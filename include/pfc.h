@@ -1,0 +1,244 @@
+/*
+ * pfc.h -- C ABI of the MI355X (gfx950) solver for the second-order
+ * convex-splitting finite-difference scheme of the 3D phase field crystal
+ * (PFC) equation, solved by FAS nonlinear multigrid.
+ *
+ * Paper: Dong, Feng, Wang, Wise, Zhang, "Convergence analysis and numerical
+ * implementation of a second order numerical scheme for the three-dimensional
+ * phase field crystal equation" (arXiv:1611.06288).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid (Section 2): cubic periodic box of side L, n cells per axis, spacing
+ *   h = L/n, cell-centred values at ((i+1/2)h, (j+1/2)h, (k+1/2)h), 0-based.
+ * Field layout: one FP64 array of n^3 values, C order [k][j][i] (x fastest).
+ *   A "triple" is three such arrays stored back to back, [3][n][n][n], in the
+ *   order (phi, mu, omega) of the unknown u of (eqn:dis-nonlinear-system).
+ * Pointers: every field pointer is a DEVICE pointer on the device that was
+ *   current when the handle was created; scalars returned to the caller
+ *   (norms, energies, step info) are HOST pointers.  The caller owns all
+ *   field buffers; the handle owns its multigrid hierarchy and scratch.
+ * Streams: all work is enqueued on the hipStream_t given at creation (NULL =
+ *   the default stream).  Entry points that return host scalars synchronise
+ *   that stream before returning; the others return without waiting.
+ * Aliasing: inputs declared const are never written.  Outputs may not alias
+ *   inputs unless stated.
+ * Errors: every function returns a pfc_status and never aborts; on error the
+ *   outputs are unspecified unless stated; pfc_last_error() gives a message.
+ * Threading: a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef PFC_H
+#define PFC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pfc_status;
+#define PFC_OK 0
+#define PFC_ERR_INVALID_ARG 1   /* bad size, parameter or NULL pointer          */
+#define PFC_ERR_NOT_CONVERGED 2 /* max_cycles reached; last iterate returned     */
+#define PFC_ERR_NONFINITE 3     /* residual became NaN or Inf                    */
+#define PFC_ERR_HIP 4           /* a HIP runtime call failed                     */
+#define PFC_ERR_OOM 5           /* device or pinned-host allocation failed       */
+
+#define PFC_FP64 0      /* every kernel in FP64                                  */
+#define PFC_MIXED 1     /* FP32 multigrid cycle inside FP64 defect correction    */
+
+#define PFC_CYCLE_V 0
+#define PFC_CYCLE_F 1
+
+#define PFC_LIN_NEWTON 0  /* pointwise Newton linearisation of the cubic term    */
+#define PFC_LIN_PICARD 1  /* the Picard linearisation written in Section 5       */
+
+/* Parameters of the problem statement (Sections 2, 3, 5 and 6): grid n^3,
+ * box side L, epsilon, time step (tau in Section 3, s in Section 6), residual
+ * tolerance, smoothing counts nu1/nu2 of Algorithm algorithm:FAS. */
+typedef struct {
+    int32_t n;          /* cells per axis; n = 2^k (k >= 2) or 3*2^k (k >= 1)  */
+    int32_t nu1;        /* pre-smoothing sweeps, >= 0                          */
+    int32_t nu2;        /* post-smoothing sweeps, >= 0 (nu1 + nu2 >= 1)        */
+    int32_t max_cycles; /* cap on cycles per time step, >= 1                   */
+    int32_t cycle;      /* PFC_CYCLE_V or PFC_CYCLE_F                          */
+    int32_t lin;        /* PFC_LIN_NEWTON or PFC_LIN_PICARD                    */
+    int32_t precision;  /* PFC_FP64 or PFC_MIXED                               */
+    int32_t reserved;   /* must be 0                                           */
+    double L;           /* box side, > 0                                       */
+    double eps;         /* epsilon of the PFC energy (energy-PFC)              */
+    double dt;          /* time step, > 0                                      */
+    double tol;         /* stop when max-norm of S - N(u) (3 components) <= tol */
+} pfc_config;
+
+/* Per-step report.  res0: residual max-norm before the first cycle;
+ * res_final: after the last; cycles: cycles taken (0 if the guess already
+ * met the tolerance). */
+typedef struct {
+    int32_t cycles;
+    int32_t status;
+    double res0;
+    double res_final;
+} pfc_step_info;
+
+typedef struct pfc_handle pfc_handle;
+
+/* Creates a solver for one grid size.  Allocates the multigrid hierarchy
+ * (levels n, n/2, ... down to 3 or 4, Section 5) on the current device.
+ * stream: a hipStream_t (may be NULL).  Errors: INVALID_ARG for n not of the
+ * form 2^k (k >= 2) or 3*2^k (k >= 1), L <= 0, dt <= 0, tol < 0, nu1 or nu2
+ * < 0, nu1+nu2 == 0, max_cycles < 1, unknown enum values, Picard with MIXED;
+ * OOM; HIP. */
+pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out);
+pfc_status pfc_destroy(pfc_handle *h);
+pfc_status pfc_set_stream(pfc_handle *h, void *stream);
+/* Number of multigrid levels and the size n_l of level l (l = 0 finest). */
+int32_t pfc_num_levels(const pfc_handle *h);
+int32_t pfc_level_size(const pfc_handle *h, int32_t level);
+
+/* First-step guess for (mu, omega) from phi0 (n^3 each):
+ *   omega = Delta_h phi0,
+ *   mu = phi0^3 + (1-eps) phi0 + 2 Delta_h phi0 + Delta_h^2 phi0,
+ * the discrete chemical potential of (equation-PFC); with it a constant
+ * phi0 is an exact fixed point of the step (zero cycles). */
+pfc_status pfc_init_guess(pfc_handle *h, const double *phi0, double *mu, double *omega);
+
+/* One time step of scheme (1.10) in the form (2nd scheme-PFC-s1..s3) with
+ * mobility M = 1: given phi^{k-1} = phi_prev and phi^k = phi_cur, computes
+ * phi^{k+1} = phi_next, mu^{k+1/2} and omega^{k+1/2}.  mu and omega are read
+ * as the initial guess and overwritten with the result; the phi guess is
+ * phi_cur.  The FAS cycle of Algorithm algorithm:FAS (V or F per the config)
+ * repeats until max|S - N(u)| <= tol, tested before each cycle.
+ * For the bootstrap step pass phi_prev == phi_cur.  phi_next must not alias
+ * phi_prev or phi_cur.  info (host, nullable) receives the report.
+ * Returns NOT_CONVERGED after max_cycles cycles (outputs hold the last
+ * iterate, info filled) and NONFINITE if the residual is NaN/Inf.
+ * Synchronises the stream (one 8-byte residual read-back per cycle). */
+pfc_status pfc_step(pfc_handle *h, const double *phi_prev, const double *phi_cur,
+                    double *phi_next, double *mu, double *omega, pfc_step_info *info);
+
+/* Exactly one FP64 multigrid cycle (Algorithm algorithm:FAS, one pass of its
+ * loop body at the finest level) on a caller-supplied iterate.
+ * u3: triple [3][n^3] (in/out); f3: triple, right-hand side S at the finest
+ * level (scheme-PFC-s1..s3 or any other); phi_cur: phi^k, n^3 (enters N).
+ * res_after (host, nullable): max|f3 - N(u3)| after the cycle. Synchronises
+ * if res_after is non-NULL. */
+pfc_status pfc_fas_vcycle(pfc_handle *h, double *u3, const double *f3,
+                          const double *phi_cur, double *res_after);
+
+/* Discrete energy (PFC energy-discrete-1) and mass of phi (n^3):
+ *   out[0] = F_h(phi) = 1/4|phi|_4^4 + (1-eps)/2 |phi|_2^2 - |grad_h phi|_2^2
+ *            + 1/2 |Delta_h phi|_2^2,
+ *   out[1] = out[0] + 1/2 |grad_h(phi - phi_prev)|_2^2 (the modified energy of
+ *            Proposition prop:hu09; equals out[0] if phi_prev is NULL),
+ *   out[2] = h^3 sum phi.
+ * out is a host array of 3 doubles.  Sums are reduced in a fixed order
+ * (bitwise reproducible).  Synchronises. */
+pfc_status pfc_energy(pfc_handle *h, const double *phi, const double *phi_prev, double *out);
+
+/* Adjoint of one time step (the implicit-function theorem applied to
+ * G(u; phi^k, phi^{k-1}, eps) = N(u) - S = 0 of scheme-PFC-o/s).
+ * Given phi_prev = phi^{k-1}, phi_cur = phi^k, phi_next = phi^{k+1} (the
+ * converged step) and gbar_next = dLoss/dphi^{k+1} (n^3 each), solves
+ * J^T lambda = (gbar_next, 0, 0) with J = dN/du at u = (phi^{k+1}, ., .) by
+ * linear multigrid with a transposed red-black point smoother to
+ * max-norm residual <= adj_tol, then ACCUMULATES
+ *   gbar_cur  += -(dG/dphi^k)^T lambda,
+ *   gbar_prev += -(dG/dphi^{k-1})^T lambda,
+ *   geps[0]   += -(dG/deps)^T lambda        (geps: DEVICE pointer, 1 double).
+ * gbar_cur and gbar_prev may be the same buffer (bootstrap step).
+ * cycles (host, nullable) receives the linear cycles used.  Synchronises. */
+pfc_status pfc_adjoint_step(pfc_handle *h, const double *phi_prev, const double *phi_cur,
+                            const double *phi_next, const double *gbar_next,
+                            double *gbar_cur, double *gbar_prev, double *geps,
+                            double adj_tol, int32_t *cycles);
+
+/* ---------------------------------------------------------------------------
+ * Kernel-level entry points (single multigrid building blocks).  They act on
+ * level `level` of the handle's hierarchy (size n_l = pfc_level_size, spacing
+ * h_l = L/n_l) and exist so that each kernel can be checked on its own.
+ * ------------------------------------------------------------------------- */
+
+/* Source S of (scheme-PFC-s1..s3) at the finest level: f3 = triple
+ * (phi^k, (1-eps)/2 phi^k + 3 Delta_h phi^k - Delta_h phi^{k-1}, Delta_h phi^k / 2). */
+pfc_status pfc_source(pfc_handle *h, const double *phi_prev, const double *phi_cur, double *f3);
+
+/* r3 = f3 - N_l(u3) with N of (scheme-PFC-o1..o3), M = 1, at level l
+ * (phk = phi^k on that level).  r3 may be NULL; maxnorm (host, nullable)
+ * receives max|r| over the three components.  Synchronises if maxnorm. */
+pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const double *f3,
+                        const double *phk, double *r3, double *maxnorm);
+
+/* One red-black half-sweep (Section 5 smoothing scheme, red-black order) of
+ * colour `colour` ((i+j+k) mod 2) at level l, in place on u3. */
+pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3,
+                      const double *f3, const double *phk);
+
+/* Coarsening I_l^{l+1} of `ncomp` consecutive fields: coarse cell = mean of
+ * its 8 children.  fine: ncomp x n_l^3; coarse: ncomp x n_{l+1}^3. */
+pfc_status pfc_restrict(pfc_handle *h, int32_t level, const double *fine, double *coarse,
+                        int32_t ncomp);
+
+/* Interpolation I_{l+1}^l added in place: fine += P(coarse_v - coarse_ubar),
+ * cell-centred trilinear (weights 3/4, 1/4 per axis), periodic; ncomp
+ * consecutive fields.  coarse_ubar may be NULL (then fine += P coarse_v). */
+pfc_status pfc_prolong_add(pfc_handle *h, int32_t level, const double *coarse_v,
+                           const double *coarse_ubar, double *fine, int32_t ncomp);
+
+/* Exact solve of N_c(u3) = f3 on the coarsest level (Newton's method, dense
+ * LU with partial pivoting; the "solve" step of Algorithm algorithm:FAS).
+ * u3 holds the start iterate and receives the solution.  iters (host,
+ * nullable) receives the Newton iteration count.  Synchronises if iters. */
+pfc_status pfc_coarse_solve(pfc_handle *h, double *u3, const double *f3, const double *phk,
+                            int32_t *iters);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent simulations (own n, L, eps, dt) advanced
+ * together, every kernel of a cycle launched once for all instances.
+ * ------------------------------------------------------------------------- */
+typedef struct pfc_batch pfc_batch;
+
+/* Creates a batch of `count` instances with configs cfgs[0..count-1] (each
+ * valid for pfc_create; precision must be FP64; all share nu1, nu2, cycle,
+ * lin and tol of cfgs[0]). */
+pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream, pfc_batch **out);
+pfc_status pfc_batch_destroy(pfc_batch *b);
+/* Loads instance i's state: phi_prev, phi_cur, mu, omega (n_i^3 each, device). */
+pfc_status pfc_batch_set_state(pfc_batch *b, int32_t i, const double *phi_prev,
+                               const double *phi_cur, const double *mu, const double *omega);
+/* Reads instance i's state back (phi_prev, phi_cur, mu, omega; device). */
+pfc_status pfc_batch_get_state(pfc_batch *b, int32_t i, double *phi_prev, double *phi_cur,
+                               double *mu, double *omega);
+/* Advances every instance by `steps` time steps.  infos (host, nullable):
+ * count*steps entries, instance-major. */
+pfc_status pfc_batch_run(pfc_batch *b, int32_t steps, pfc_step_info *infos);
+
+/* ---------------------------------------------------------------------------
+ * Instrumentation
+ * ------------------------------------------------------------------------- */
+#define PFC_KERNEL_SMOOTH0 0     /* finest-level smoothing sweep launches       */
+#define PFC_KERNEL_RESIDUAL0 1   /* finest-level residual + coarsening          */
+#define PFC_KERNEL_PROLONG0 2    /* finest-level interpolation + correction     */
+#define PFC_KERNEL_NORM0 3       /* finest-level residual max-norm              */
+#define PFC_KERNEL_COARSE 4      /* coarsest-level solve                        */
+#define PFC_KERNEL_COUNT 5
+/* When enabled, HIP events bracket each launch of the listed kernels on the
+ * handle's stream and their durations are accumulated at every host
+ * synchronisation point of the handle. */
+pfc_status pfc_timing_enable(pfc_handle *h, int32_t on);
+/* launches and total milliseconds accumulated for `kernel` since the last
+ * reset; bytes_per_launch: the kernel's algorithmic HBM bytes per launch at
+ * the finest level (0 if not defined). */
+pfc_status pfc_timing_get(pfc_handle *h, int32_t kernel, int64_t *launches, double *total_ms,
+                          double *bytes_per_launch);
+pfc_status pfc_timing_reset(pfc_handle *h);
+
+const char *pfc_status_string(pfc_status s);
+/* Message of the last error on this handle (or of the last failed create if
+ * h is NULL).  Valid until the next call on the handle. */
+const char *pfc_last_error(const pfc_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFC_H */

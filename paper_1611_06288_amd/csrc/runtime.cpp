@@ -1,0 +1,588 @@
+// Host runtime of the PFC multigrid solver: handle, level hierarchy, cycle
+// driver, time step, instrumentation and the C ABI of include/pfc.h.
+//
+// Algorithm (Section 5, Algorithm algorithm:FAS, with these readings): the
+// loop "while residual > tolerance" runs at the finest level only and tests
+// max|S - N(u)| over the three components before each cycle; a recursive call
+// performs one cycle; the coarse right-hand side is N_{l+1}(I u) + I r; the
+// coarse correction is I(v - I u); red-black colour (i+j+k) mod 2, colour 0
+// first in every sweep; the coarsest level (n = 3 or 4) is solved by Newton's
+// method.
+#include "pfc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pfc_internal.h"
+#include "runtime_internal.h"
+
+using namespace pfc;
+
+namespace {
+thread_local std::string g_create_error;
+}  // namespace
+
+namespace pfc {
+
+bool level_sizes(int n, std::vector<int> &out) {
+    out.clear();
+    if (n < 4 || (n & 1)) return false;
+    int m = n;
+    out.push_back(m);
+    while ((m & 1) == 0 && m / 2 >= 3) {
+        m /= 2;
+        out.push_back(m);
+    }
+    return m == 3 || m == 4;
+}
+
+std::string validate_config(const pfc_config *c) {
+    if (!c) return "config is NULL";
+    std::vector<int> sizes;
+    if (!level_sizes(c->n, sizes))
+        return "n must be 2^k (k >= 2) or 3*2^k (k >= 1), got " + std::to_string(c->n);
+    if (!(c->L > 0) || !std::isfinite(c->L)) return "L must be > 0";
+    if (!(c->dt > 0) || !std::isfinite(c->dt)) return "dt must be > 0";
+    if (!(c->tol >= 0) || !std::isfinite(c->tol)) return "tol must be >= 0";
+    if (!std::isfinite(c->eps)) return "eps must be finite";
+    if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 + c->nu2 < 1) return "nu1, nu2 >= 0 with nu1 + nu2 >= 1";
+    if (c->max_cycles < 1) return "max_cycles must be >= 1";
+    if (c->cycle != PFC_CYCLE_V && c->cycle != PFC_CYCLE_F) return "unknown cycle type";
+    if (c->lin != PFC_LIN_NEWTON && c->lin != PFC_LIN_PICARD) return "unknown linearisation";
+    if (c->precision != PFC_FP64 && c->precision != PFC_MIXED) return "unknown precision";
+    if (c->precision == PFC_MIXED && c->lin != PFC_LIN_NEWTON)
+        return "the mixed-precision form uses Newton linearisation only";
+    if (c->reserved != 0) return "reserved must be 0";
+    return "";
+}
+
+// Dense Lap and Lap^3 (column-major, n^3 x n^3) on the coarsest level.
+void coarse_matrices(int n, double h, std::vector<double> &l1, std::vector<double> &l3) {
+    const int P = n * n * n;
+    auto id = [n](int i, int j, int k) {
+        i = (i + n) % n;
+        j = (j + n) % n;
+        k = (k + n) % n;
+        return (k * n + j) * n + i;
+    };
+    std::vector<double> A((size_t)P * P, 0.0);  // row-major A[r*P + c]
+    const double w = 1.0 / (h * h);
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const int r = id(i, j, k);
+                const int nb[6] = {id(i + 1, j, k), id(i - 1, j, k), id(i, j + 1, k),
+                                   id(i, j - 1, k), id(i, j, k + 1), id(i, j, k - 1)};
+                for (int q = 0; q < 6; ++q) A[(size_t)r * P + nb[q]] += w;
+                A[(size_t)r * P + r] -= 6.0 * w;
+            }
+    std::vector<double> A2((size_t)P * P, 0.0), A3((size_t)P * P, 0.0);
+    for (int r = 0; r < P; ++r)
+        for (int m = 0; m < P; ++m) {
+            const double v = A[(size_t)r * P + m];
+            if (v == 0.0) continue;
+            for (int c = 0; c < P; ++c) A2[(size_t)r * P + c] += v * A[(size_t)m * P + c];
+        }
+    for (int r = 0; r < P; ++r)
+        for (int m = 0; m < P; ++m) {
+            const double v = A2[(size_t)r * P + m];
+            if (v == 0.0) continue;
+            for (int c = 0; c < P; ++c) A3[(size_t)r * P + c] += v * A[(size_t)m * P + c];
+        }
+    l1.assign((size_t)P * P, 0.0);
+    l3.assign((size_t)P * P, 0.0);
+    for (int r = 0; r < P; ++r)
+        for (int c = 0; c < P; ++c) {
+            l1[(size_t)c * P + r] = A[(size_t)r * P + c];
+            l3[(size_t)c * P + r] = A3[(size_t)r * P + c];
+        }
+}
+
+}  // namespace pfc
+
+// ------------------------------------------------------------- handle
+
+static pfc_status fail(pfc_handle *H, pfc_status st, const std::string &msg) {
+    if (H)
+        H->err = msg;
+    else
+        g_create_error = msg;
+    return st;
+}
+
+static pfc_status hip_fail(pfc_handle *H, hipError_t e, const char *what) {
+    return fail(H, PFC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(H, expr)                                            \
+    do {                                                            \
+        hipError_t e_ = (expr);                                     \
+        if (e_ != hipSuccess) return hip_fail((H), e_, #expr);      \
+    } while (0)
+
+template <typename T>
+static bool dalloc(pfc_handle *H, T **p, size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return false;
+    H->allocs.push_back(q);
+    *p = (T *)q;
+    return true;
+}
+
+static pfc::OpParams op_of(const pfc_handle *H, int l) {
+    return pfc::OpParams{H->lev[l].n, H->lev[l].h2inv, H->cfg.dt, H->cfg.eps};
+}
+
+// ------------------------------------------------------------ timing
+
+void pfc_handle::begin_timed(int kind, int level) {
+    cur_event = -1;
+    if (!timing || kind < 0) return;
+    if (kind != PFC_KERNEL_COARSE && level != 0) return;
+    hipEvent_t a, b;
+    if (pool.size() >= 2) {
+        a = pool.back();
+        pool.pop_back();
+        b = pool.back();
+        pool.pop_back();
+    } else {
+        if (hipEventCreate(&a) != hipSuccess) return;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return;
+        }
+    }
+    (void)hipEventRecord(a, stream);
+    pending.push_back(TimedLaunch{kind, a, b});
+    cur_event = (int)pending.size() - 1;
+}
+
+void pfc_handle::end_timed() {
+    if (cur_event < 0) return;
+    (void)hipEventRecord(pending[cur_event].b, stream);
+    cur_event = -1;
+}
+
+void pfc_handle::collect_timings() {
+    for (auto &t : pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            t_count[t.kind] += 1;
+            t_ms[t.kind] += ms;
+        }
+        pool.push_back(t.a);
+        pool.push_back(t.b);
+    }
+    pending.clear();
+}
+
+pfc_handle::~pfc_handle() {
+    for (auto &t : pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+    for (void *p : allocs) (void)hipFree(p);
+    if (h_pin) (void)hipHostFree(h_pin);
+}
+
+// ----------------------------------------------------- FP64 multigrid
+
+namespace pfc {
+
+static void sweep64(pfc_handle *H, int l) {
+    Level &A = H->lev[l];
+    const pfc::OpParams op = op_of(H, l);
+    for (int colour = 0; colour < 2; ++colour) {
+        H->begin_timed(PFC_KERNEL_SMOOTH0, l);
+        launch_smooth<double, false>(H->stream, op, colour, H->cfg.lin == PFC_LIN_PICARD, A.u,
+                                     cst(A.f), A.phk, nullptr);
+        H->end_timed();
+    }
+}
+
+void cycle64(pfc_handle *H, int l, bool fcycle) {
+    Level &A = H->lev[l];
+    if (l == H->nlev - 1) {
+        H->begin_timed(PFC_KERNEL_COARSE, l);
+        launch_coarse<double, false>(H->stream, op_of(H, l), A.u, cst(A.f), A.phk, nullptr,
+                                     H->lap1, H->lap3, H->d_iters);
+        H->end_timed();
+        return;
+    }
+    Level &B = H->lev[l + 1];
+    for (int s = 0; s < H->cfg.nu1; ++s) sweep64(H, l);
+    H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
+    launch_resid_restrict<double, false>(H->stream, op_of(H, l), cst(A.u), cst(A.f), A.phk,
+                                         nullptr, B.ubar, B.f);
+    H->end_timed();
+    launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f, B.u, B.phk, nullptr);
+    cycle64(H, l + 1, fcycle);
+    if (fcycle) cycle64(H, l + 1, false);
+    H->begin_timed(PFC_KERNEL_PROLONG0, l);
+    launch_prolong<double>(H->stream, B.n, cst(B.u), cst(B.ubar), A.u);
+    H->end_timed();
+    for (int s = 0; s < H->cfg.nu2; ++s) sweep64(H, l);
+}
+
+void restrict_phk(pfc_handle *H) {
+    for (int l = 0; l + 1 < H->nlev; ++l)
+        launch_restrict<double>(H->stream, H->lev[l].n, H->lev[l].phk, H->lev[l + 1].phk);
+}
+
+// Residual max-norm at the finest level (r.a may be null).  Synchronises.
+pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out) {
+    Level &A = H->lev[0];
+    H->begin_timed(PFC_KERNEL_NORM0, 0);
+    const int cnt = launch_resid_max<double, false>(H->stream, op_of(H, 0), cst(A.u), cst(A.f),
+                                                    A.phk, nullptr, r, H->partial);
+    H->end_timed();
+    launch_max_final(H->stream, H->partial, cnt, H->d_scal);
+    HIP_TRY(H, hipGetLastError());
+    HIP_TRY(H, hipMemcpyAsync(H->h_pin, H->d_scal, sizeof(double), hipMemcpyDeviceToHost,
+                              H->stream));
+    HIP_TRY(H, hipStreamSynchronize(H->stream));
+    H->collect_timings();
+    *out = H->h_pin[0];
+    return PFC_OK;
+}
+
+}  // namespace pfc
+
+// ------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char *pfc_status_string(pfc_status s) {
+    switch (s) {
+        case PFC_OK: return "ok";
+        case PFC_ERR_INVALID_ARG: return "invalid argument";
+        case PFC_ERR_NOT_CONVERGED: return "not converged within max_cycles";
+        case PFC_ERR_NONFINITE: return "residual is not finite";
+        case PFC_ERR_HIP: return "HIP runtime error";
+        case PFC_ERR_OOM: return "out of memory";
+        default: return "unknown status";
+    }
+}
+
+const char *pfc_last_error(const pfc_handle *h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
+    if (!out) return fail(nullptr, PFC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    const std::string why = validate_config(cfg);
+    if (!why.empty()) return fail(nullptr, PFC_ERR_INVALID_ARG, why);
+    pfc_handle *H = new pfc_handle();
+    H->cfg = *cfg;
+    H->stream = (hipStream_t)stream;
+    if (hipGetDevice(&H->device) != hipSuccess) {
+        delete H;
+        return fail(nullptr, PFC_ERR_HIP, "hipGetDevice failed");
+    }
+    std::vector<int> sizes;
+    level_sizes(cfg->n, sizes);
+    H->nlev = (int)sizes.size();
+    bool ok = true;
+    for (int l = 0; l < H->nlev; ++l) {
+        Level &A = H->lev[l];
+        A.n = sizes[l];
+        A.h = cfg->L / A.n;
+        A.h2inv = 1.0 / (A.h * A.h);
+        A.P = (size_t)A.n * A.n * A.n;
+        if (l == 0) continue;  // finest level buffers are bound per call
+        double *u, *f, *ub;
+        ok = ok && dalloc(H, &u, 3 * A.P) && dalloc(H, &f, 3 * A.P) && dalloc(H, &ub, 3 * A.P) &&
+             dalloc(H, &A.phk, A.P);
+        if (!ok) break;
+        A.u = Tri<double>{u, u + A.P, u + 2 * A.P};
+        A.f = Tri<double>{f, f + A.P, f + 2 * A.P};
+        A.ubar = Tri<double>{ub, ub + A.P, ub + 2 * A.P};
+    }
+    const size_t P0 = H->lev[0].P;
+    double *f0 = nullptr;
+    ok = ok && dalloc(H, &f0, 3 * P0);
+    if (ok) H->f0 = Tri<double>{f0, f0 + P0, f0 + 2 * P0};
+    ok = ok && dalloc(H, &H->partial, (P0 + kBlock - 1) / kBlock + 16);
+    ok = ok && dalloc(H, &H->d_scal, 16) && dalloc(H, &H->d_iters, 4);
+    ok = ok && dalloc(H, &H->energy_part, (size_t)6 * pfc::energy_blocks(cfg->n) + 16);
+    // coarsest-level matrices
+    const Level &C = H->lev[H->nlev - 1];
+    std::vector<double> l1, l3;
+    pfc::coarse_matrices(C.n, C.h, l1, l3);
+    ok = ok && dalloc(H, &H->lap1, l1.size()) && dalloc(H, &H->lap3, l3.size());
+    if (ok && hipHostMalloc((void **)&H->h_pin, 64 * sizeof(double), 0) != hipSuccess) {
+        H->h_pin = nullptr;
+        ok = false;
+    }
+    if (!ok) {
+        delete H;
+        return fail(nullptr, PFC_ERR_OOM, "device or pinned allocation failed");
+    }
+    if (hipMemcpy(H->lap1, l1.data(), l1.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(H->lap3, l3.data(), l3.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        delete H;
+        return fail(nullptr, PFC_ERR_HIP, "upload of coarse matrices failed");
+    }
+    if (cfg->precision == PFC_MIXED) {
+        const pfc_status st = pfc::mixed_init(H);
+        if (st != PFC_OK) {
+            g_create_error = H->err;
+            delete H;
+            return st;
+        }
+    }
+    *out = H;
+    return PFC_OK;
+}
+
+pfc_status pfc_destroy(pfc_handle *h) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+    return PFC_OK;
+}
+
+pfc_status pfc_set_stream(pfc_handle *h, void *stream) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    h->stream = (hipStream_t)stream;
+    return PFC_OK;
+}
+
+int32_t pfc_num_levels(const pfc_handle *h) { return h ? h->nlev : 0; }
+
+int32_t pfc_level_size(const pfc_handle *h, int32_t level) {
+    if (!h || level < 0 || level >= h->nlev) return 0;
+    return h->lev[level].n;
+}
+
+pfc_status pfc_init_guess(pfc_handle *h, const double *phi0, double *mu, double *omega) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!phi0 || !mu || !omega) return fail(h, PFC_ERR_INVALID_ARG, "NULL field pointer");
+    launch_init_guess(h->stream, op_of(h, 0), phi0, mu, omega);
+    HIP_TRY(h, hipGetLastError());
+    return PFC_OK;
+}
+
+pfc_status pfc_step(pfc_handle *h, const double *phi_prev, const double *phi_cur, double *phi_next,
+                    double *mu, double *omega, pfc_step_info *info) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!phi_prev || !phi_cur || !phi_next || !mu || !omega)
+        return fail(h, PFC_ERR_INVALID_ARG, "NULL field pointer");
+    if (phi_next == phi_cur || phi_next == phi_prev)
+        return fail(h, PFC_ERR_INVALID_ARG, "phi_next aliases an input");
+    if (h->cfg.precision == PFC_MIXED)
+        return pfc::mixed_step(h, phi_prev, phi_cur, phi_next, mu, omega, info);
+    Level &A = h->lev[0];
+    HIP_TRY(h, hipMemcpyAsync(phi_next, phi_cur, A.P * sizeof(double), hipMemcpyDeviceToDevice,
+                              h->stream));
+    launch_source(h->stream, op_of(h, 0), phi_cur, phi_prev, h->f0);
+    A.u = Tri<double>{phi_next, mu, omega};
+    A.f = h->f0;
+    A.phk = const_cast<double *>(phi_cur);
+    restrict_phk(h);
+    HIP_TRY(h, hipGetLastError());
+    int c = 0;
+    double rho = 0, rho0 = 0;
+    pfc_status status = PFC_OK;
+    for (;;) {
+        const pfc_status st = resid_norm64(h, Tri<double>{nullptr, nullptr, nullptr}, &rho);
+        if (st != PFC_OK) return st;
+        if (c == 0) rho0 = rho;
+        if (!std::isfinite(rho)) {
+            status = PFC_ERR_NONFINITE;
+            break;
+        }
+        if (rho <= h->cfg.tol) break;
+        if (c == h->cfg.max_cycles) {
+            status = PFC_ERR_NOT_CONVERGED;
+            break;
+        }
+        cycle64(h, 0, h->cfg.cycle == PFC_CYCLE_F);
+        ++c;
+    }
+    if (info) {
+        info->cycles = c;
+        info->status = status;
+        info->res0 = rho0;
+        info->res_final = rho;
+    }
+    if (status != PFC_OK) fail(h, status, pfc_status_string(status));
+    return status;
+}
+
+pfc_status pfc_fas_vcycle(pfc_handle *h, double *u3, const double *f3, const double *phi_cur,
+                          double *res_after) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!u3 || !f3 || !phi_cur) return fail(h, PFC_ERR_INVALID_ARG, "NULL field pointer");
+    Level &A = h->lev[0];
+    const size_t P = A.P;
+    A.u = Tri<double>{u3, u3 + P, u3 + 2 * P};
+    double *f = const_cast<double *>(f3);
+    A.f = Tri<double>{f, f + P, f + 2 * P};
+    A.phk = const_cast<double *>(phi_cur);
+    restrict_phk(h);
+    cycle64(h, 0, h->cfg.cycle == PFC_CYCLE_F);
+    HIP_TRY(h, hipGetLastError());
+    if (res_after) {
+        const pfc_status st = resid_norm64(h, Tri<double>{nullptr, nullptr, nullptr}, res_after);
+        if (st != PFC_OK) return st;
+    }
+    return PFC_OK;
+}
+
+pfc_status pfc_energy(pfc_handle *h, const double *phi, const double *phi_prev, double *out) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!phi || !out) return fail(h, PFC_ERR_INVALID_ARG, "NULL pointer");
+    const Level &A = h->lev[0];
+    launch_energy(h->stream, A.n, A.h, h->cfg.eps, phi, phi_prev, h->energy_part, h->d_scal);
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipMemcpyAsync(h->h_pin, h->d_scal, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out[0] = h->h_pin[0];
+    out[1] = h->h_pin[1];
+    out[2] = h->h_pin[2];
+    return PFC_OK;
+}
+
+// ---------------------------------------------- kernel-level entry points
+
+static bool level_ok(const pfc_handle *h, int level) { return level >= 0 && level < h->nlev; }
+
+pfc_status pfc_source(pfc_handle *h, const double *phi_prev, const double *phi_cur, double *f3) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!phi_prev || !phi_cur || !f3) return fail(h, PFC_ERR_INVALID_ARG, "NULL pointer");
+    const size_t P = h->lev[0].P;
+    launch_source(h->stream, op_of(h, 0), phi_cur, phi_prev, Tri<double>{f3, f3 + P, f3 + 2 * P});
+    HIP_TRY(h, hipGetLastError());
+    return PFC_OK;
+}
+
+pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const double *f3,
+                        const double *phk, double *r3, double *maxnorm) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!level_ok(h, level) || !u3 || !f3 || !phk) return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
+    const size_t P = h->lev[level].P;
+    Tri<const double> u{u3, u3 + P, u3 + 2 * P}, f{f3, f3 + P, f3 + 2 * P};
+    Tri<double> r{nullptr, nullptr, nullptr};
+    if (r3) r = Tri<double>{r3, r3 + P, r3 + 2 * P};
+    const int cnt = launch_resid_max<double, false>(h->stream, op_of(h, level), u, f, phk, nullptr,
+                                                    r, h->partial);
+    launch_max_final(h->stream, h->partial, cnt, h->d_scal);
+    HIP_TRY(h, hipGetLastError());
+    if (maxnorm) {
+        HIP_TRY(h, hipMemcpyAsync(h->h_pin, h->d_scal, sizeof(double), hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        *maxnorm = h->h_pin[0];
+    }
+    return PFC_OK;
+}
+
+pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3, const double *f3,
+                      const double *phk) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!level_ok(h, level) || (colour != 0 && colour != 1) || !u3 || !f3 || !phk ||
+        (h->lev[level].n & 1))
+        return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
+    const size_t P = h->lev[level].P;
+    launch_smooth<double, false>(h->stream, op_of(h, level), colour,
+                                 h->cfg.lin == PFC_LIN_PICARD, Tri<double>{u3, u3 + P, u3 + 2 * P},
+                                 Tri<const double>{f3, f3 + P, f3 + 2 * P}, phk, nullptr);
+    HIP_TRY(h, hipGetLastError());
+    return PFC_OK;
+}
+
+pfc_status pfc_restrict(pfc_handle *h, int32_t level, const double *fine, double *coarse,
+                        int32_t ncomp) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!level_ok(h, level) || level + 1 >= h->nlev || !fine || !coarse || ncomp < 1)
+        return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
+    const size_t Pf = h->lev[level].P, Pc = h->lev[level + 1].P;
+    for (int c = 0; c < ncomp; ++c)
+        launch_restrict<double>(h->stream, h->lev[level].n, fine + c * Pf, coarse + c * Pc);
+    HIP_TRY(h, hipGetLastError());
+    return PFC_OK;
+}
+
+pfc_status pfc_prolong_add(pfc_handle *h, int32_t level, const double *coarse_v,
+                           const double *coarse_ubar, double *fine, int32_t ncomp) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!level_ok(h, level) || level + 1 >= h->nlev || !coarse_v || !fine ||
+        (ncomp != 1 && ncomp != 3))
+        return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
+    const size_t Pf = h->lev[level].P, Pc = h->lev[level + 1].P;
+    const int nc = h->lev[level + 1].n;
+    if (ncomp == 3) {
+        Tri<const double> ub{nullptr, nullptr, nullptr};
+        if (coarse_ubar) ub = Tri<const double>{coarse_ubar, coarse_ubar + Pc, coarse_ubar + 2 * Pc};
+        launch_prolong<double>(h->stream, nc, Tri<const double>{coarse_v, coarse_v + Pc, coarse_v + 2 * Pc},
+                               ub, Tri<double>{fine, fine + Pf, fine + 2 * Pf});
+    } else {
+        launch_prolong<double>(h->stream, nc, Tri<const double>{coarse_v, nullptr, nullptr},
+                               Tri<const double>{coarse_ubar, nullptr, nullptr},
+                               Tri<double>{fine, nullptr, nullptr});
+    }
+    HIP_TRY(h, hipGetLastError());
+    return PFC_OK;
+}
+
+pfc_status pfc_coarse_solve(pfc_handle *h, double *u3, const double *f3, const double *phk,
+                            int32_t *iters) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!u3 || !f3 || !phk) return fail(h, PFC_ERR_INVALID_ARG, "NULL pointer");
+    const int l = h->nlev - 1;
+    const size_t P = h->lev[l].P;
+    launch_coarse<double, false>(h->stream, op_of(h, l), Tri<double>{u3, u3 + P, u3 + 2 * P},
+                                 Tri<const double>{f3, f3 + P, f3 + 2 * P}, phk, nullptr, h->lap1,
+                                 h->lap3, h->d_iters);
+    HIP_TRY(h, hipGetLastError());
+    if (iters) {
+        HIP_TRY(h, hipMemcpyAsync(h->h_pin, h->d_iters, sizeof(int), hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        std::memcpy(iters, h->h_pin, sizeof(int));
+    }
+    return PFC_OK;
+}
+
+// ------------------------------------------------------- instrumentation
+
+pfc_status pfc_timing_enable(pfc_handle *h, int32_t on) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    h->timing = on != 0;
+    return PFC_OK;
+}
+
+pfc_status pfc_timing_reset(pfc_handle *h) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(h->stream);
+    h->collect_timings();
+    for (int k = 0; k < PFC_KERNEL_COUNT; ++k) {
+        h->t_count[k] = 0;
+        h->t_ms[k] = 0;
+    }
+    return PFC_OK;
+}
+
+pfc_status pfc_timing_get(pfc_handle *h, int32_t kernel, int64_t *launches, double *total_ms,
+                          double *bytes_per_launch) {
+    if (!h || kernel < 0 || kernel >= PFC_KERNEL_COUNT) return PFC_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(h->stream);
+    h->collect_timings();
+    if (launches) *launches = h->t_count[kernel];
+    if (total_ms) *total_ms = h->t_ms[kernel];
+    if (bytes_per_launch) *bytes_per_launch = pfc::algorithmic_bytes(h, kernel);
+    return PFC_OK;
+}
+
+}  // extern "C"

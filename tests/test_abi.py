@@ -1,0 +1,68 @@
+"""Host-side checks of the C-ABI library (no GPU work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1611_06288_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+char\s*\*|pfc_status|int32_t)\s*(pfc_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("pfc_step", "pfc_fas_vcycle", "pfc_energy", "pfc_adjoint_step", "pfc_create",
+                 "pfc_destroy", "pfc_batch_run"):
+        assert must in names
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("HIP library not built")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the ctypes table covers exactly the declared functions
+    assert sorted(_lib.SIGNATURES) == declared_functions()
+
+
+def test_status_strings_and_create_errors_without_gpu_work():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("HIP library not built")
+    L = _lib.lib()
+    assert L.pfc_status_string(0) == b"ok"
+    assert b"converged" in L.pfc_status_string(2)
+    cfg = _lib.PfcConfig(n=10, nu1=2, nu2=2, max_cycles=10, cycle=0, lin=0, precision=0, reserved=0,
+                         L=10.0, eps=0.1, dt=0.1, tol=1e-10)
+    h = ctypes.c_void_p()
+    # validation happens before any device call
+    assert L.pfc_create(ctypes.byref(cfg), None, ctypes.byref(h)) == _lib.PFC_ERR_INVALID_ARG
+    assert b"3*2^k" in L.pfc_last_error(None)
+    for field, bad in (("n", 7), ("dt", 0.0), ("L", -1.0), ("tol", -1.0), ("nu1", -1),
+                       ("max_cycles", 0), ("cycle", 5), ("precision", 9)):
+        c = _lib.PfcConfig.from_buffer_copy(cfg)
+        c.n = 16
+        setattr(c, field, bad)
+        assert L.pfc_create(ctypes.byref(c), None, ctypes.byref(h)) == _lib.PFC_ERR_INVALID_ARG, field
+    c = _lib.PfcConfig.from_buffer_copy(cfg)
+    c.n, c.precision, c.lin = 16, _lib.PFC_MIXED, _lib.PFC_LIN_PICARD
+    assert L.pfc_create(ctypes.byref(c), None, ctypes.byref(h)) == _lib.PFC_ERR_INVALID_ARG
+    assert L.pfc_step(None, None, None, None, None, None, None) == _lib.PFC_ERR_INVALID_ARG
+
+
+def test_solver_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    from paper_1611_06288_amd import Solver
+    with pytest.raises(RuntimeError):
+        Solver(16, 16.0, 0.1, 0.1)
