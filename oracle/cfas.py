@@ -53,6 +53,7 @@ def lib():
         L.orc_step.restype = i
         L.orc_initial_guess.argtypes = [i, d, d, _dp, _dp, _dp]
         L.orc_energy.argtypes = [i, d, d, _dp, _dp, _dp]
+        L.orc_num_threads.restype = i
         _lib = L
     return _lib
 
@@ -66,6 +67,11 @@ def _p(a: Optional[np.ndarray]):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    """OpenMP threads used by the oracle's parallel loops."""
+    return lib().orc_num_threads()
 
 
 def num_levels(n: int) -> int:

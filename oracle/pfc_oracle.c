@@ -557,3 +557,16 @@ void orc_energy(int n, double h, double eps, const double *phi, const double *ph
     out[1] = F + 0.5 * h3 * t[4];
     out[2] = h3 * t[5];
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -115,24 +115,33 @@ def polycrystal_phi0(n: int, L: float, n_crystals: int, seed: int,
     g = rng(seed)
     h = L / n
     phi = mean + noise * g.uniform(-1.0, 1.0, size=(n, n, n))
-    z, y, x = cell_centres(n, L)
+    coord = (np.arange(n, dtype=np.float64) + 0.5) * h
     R = radius_cells * h
     for _ in range(n_crystals):
         c = g.uniform(0.0, L, size=3)                 # (cx, cy, cz)
         rot = _rotation_from_quaternion(g.standard_normal(4))
-        dx = x - c[0]
-        dy = y - c[1]
-        dz = z - c[2]
-        dx -= L * np.round(dx / L)
-        dy -= L * np.round(dy / L)
-        dz -= L * np.round(dz / L)
+        # candidate cells: the sphere's bounding box, wrapped (every cell
+        # within the radius is in it); the formula is evaluated only there
+        idx = []
+        for ax in range(3):
+            lo = int(math.floor((c[ax] - R) / h)) - 1
+            hi = int(math.ceil((c[ax] + R) / h)) + 2
+            idx.append(np.unique(np.arange(lo, hi) % n))
+        ix, iy, iz = idx
+        dx = (coord[ix] - c[0])[None, None, :]
+        dy = (coord[iy] - c[1])[None, :, None]
+        dz = (coord[iz] - c[2])[:, None, None]
+        dx = dx - L * np.round(dx / L)
+        dy = dy - L * np.round(dy / L)
+        dz = dz - L * np.round(dz / L)
         inside = dx * dx + dy * dy + dz * dz <= R * R
         px = rot[0, 0] * dx + rot[0, 1] * dy + rot[0, 2] * dz
         py = rot[1, 0] * dx + rot[1, 1] * dy + rot[1, 2] * dz
         pz = rot[2, 0] * dx + rot[2, 1] * dy + rot[2, 2] * dz
         cx, cy, cz = np.cos(q * px), np.cos(q * py), np.cos(q * pz)
         crystal = mean + amp * (cx * cy + cx * cz + cy * cz)
-        phi = np.where(inside, crystal, phi)
+        sub = phi[np.ix_(iz, iy, ix)]
+        phi[np.ix_(iz, iy, ix)] = np.where(inside, crystal, sub)
     return np.ascontiguousarray(phi)
 
 
