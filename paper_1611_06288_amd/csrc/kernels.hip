@@ -2,20 +2,53 @@
 // second-order PFC scheme (arXiv:1611.06288, Sections 2, 3 and 5).
 //
 // Every kernel is a 7-point stencil, a transfer or a reduction: memory bound,
-// no matrix-core work.  One thread per grid point (or per point of one
-// red-black colour, or per coarse cell) on 256-thread workgroups; workgroup
-// ids are remapped so that each of the 8 XCDs receives a contiguous range of
-// z-planes (neighbouring planes share halo lines in that XCD's L2).
+// no matrix-core work.  Smoothed levels store each field colour-split (all
+// points of colour 0 = (i+j+k) even, then all of colour 1), so a red-black
+// half-sweep streams only the colour it updates plus the other colour's three
+// fields: 44 bytes per grid point instead of the ~80 an interleaved layout
+// drags through the caches.  Threads walk the storage order (coalesced);
+// workgroup ids are remapped so each of the 8 XCDs gets a contiguous range of
+// z-planes, whose neighbours then meet in that XCD's L2.
 //
-// Storage type T is double (FP64 path) or float (mixed-precision cycle);
-// all operator arithmetic and the pointwise 3x3 solve run in FP64.
+// Storage type T is double (FP64 path) or float (the correction cycle of the
+// mixed-precision form); operator arithmetic and the pointwise 3x3 solve run
+// in FP64 in both.
 #include "pfc_internal.h"
 
 #include <math.h>
 
 namespace pfc {
 
-// ------------------------------------------------------------------ helpers
+// ------------------------------------------------------------------ layout
+
+Div make_div(int d) {
+    Div r{0, 0};
+    if (d % 3 == 0) {
+        r.three = 1;
+        d /= 3;
+    }
+    while (d > 1) {
+        d >>= 1;
+        ++r.shift;
+    }
+    return r;
+}
+
+Lay make_lay(int n, bool split) {
+    Lay l;
+    l.n = n;
+    l.split = split ? 1 : 0;
+    l.dn = make_div(n);
+    l.dh = make_div(split ? n / 2 : 1);
+    return l;
+}
+
+static unsigned blocks_for(size_t count) { return (unsigned)((count + kBlock - 1) / kBlock); }
+
+static unsigned reduce_blocks(size_t count) {
+    const size_t b = (count + kBlock - 1) / kBlock;
+    return (unsigned)(b < (size_t)kMaxReduceBlocks ? b : (size_t)kMaxReduceBlocks);
+}
 
 __device__ __forceinline__ unsigned xcd_block() {
     const unsigned nb = gridDim.x, b = blockIdx.x;
@@ -27,36 +60,100 @@ __device__ __forceinline__ unsigned xcd_block() {
 __device__ __forceinline__ int wrap_p(int i, int n) { return i == n - 1 ? 0 : i + 1; }
 __device__ __forceinline__ int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 
-__device__ __forceinline__ size_t lin(int n, int i, int j, int k) {
-    return ((size_t)k * (size_t)n + (size_t)j) * (size_t)n + (size_t)i;
+__device__ __forceinline__ size_t npts(const Lay &L) { return (size_t)L.n * L.n * L.n; }
+
+// Storage offset of point (i, j, k).
+__device__ __forceinline__ size_t sidx(const Lay &L, int i, int j, int k) {
+    const size_t n = (size_t)L.n;
+    if (!L.split) return ((size_t)k * n + (size_t)j) * n + (size_t)i;
+    const size_t H = n * n * n / 2;
+    return (size_t)((i + j + k) & 1) * H + ((size_t)k * n + (size_t)j) * (n >> 1) + (size_t)(i >> 1);
 }
 
-// Offsets of the six face neighbours of (i, j, k), periodic.
-struct Nbrs {
-    size_t c, xp, xm, yp, ym, zp, zm;
+// Grid point stored at offset t.
+__device__ __forceinline__ void decode(const Lay &L, unsigned t, int &i, int &j, int &k) {
+    const int n = L.n;
+    if (!L.split) {
+        const unsigned row = L.dn.q(t);
+        i = (int)(t - row * (unsigned)n);
+        k = (int)L.dn.q(row);
+        j = (int)(row - (unsigned)k * (unsigned)n);
+        return;
+    }
+    const unsigned H = (unsigned)((size_t)n * n * n / 2);
+    const int c = t >= H ? 1 : 0;
+    const unsigned r = t - (c ? H : 0u);
+    const unsigned hn = (unsigned)(n >> 1);
+    const unsigned row = L.dh.q(r);
+    const int m = (int)(r - row * hn);
+    k = (int)L.dn.q(row);
+    j = (int)(row - (unsigned)k * (unsigned)n);
+    i = 2 * m + ((c + j + k) & 1);
+}
+
+// Grid point number t in natural (x fastest) order, whatever the storage.
+__device__ __forceinline__ void decode_nat(const Lay &L, unsigned t, int &i, int &j, int &k) {
+    const unsigned row = L.dn.q(t);
+    i = (int)(t - row * (unsigned)L.n);
+    k = (int)L.dn.q(row);
+    j = (int)(row - (unsigned)k * (unsigned)L.n);
+}
+
+// 32-bit storage offset (every level has at most 2^30 points).
+__device__ __forceinline__ unsigned sidx32(const Lay &L, int i, int j, int k) {
+    const unsigned n = (unsigned)L.n;
+    if (!L.split) return ((unsigned)k * n + (unsigned)j) * n + (unsigned)i;
+    const unsigned H = n * n * n / 2;
+    return ((unsigned)((i + j + k) & 1)) * H + ((unsigned)k * n + (unsigned)j) * (n >> 1) +
+           (unsigned)(i >> 1);
+}
+
+// A point and its six face neighbours, periodic, as 32-bit offsets.
+struct Off {
+    unsigned c, xp, xm, yp, ym, zp, zm;
 };
 
-__device__ __forceinline__ Nbrs nbrs(int n, int i, int j, int k) {
-    Nbrs q;
-    q.c = lin(n, i, j, k);
-    q.xp = lin(n, wrap_p(i, n), j, k);
-    q.xm = lin(n, wrap_m(i, n), j, k);
-    q.yp = lin(n, i, wrap_p(j, n), k);
-    q.ym = lin(n, i, wrap_m(j, n), k);
-    q.zp = lin(n, i, j, wrap_p(k, n));
-    q.zm = lin(n, i, j, wrap_m(k, n));
+__device__ __forceinline__ Off offs(const Lay &L, int i, int j, int k) {
+    const int n = L.n;
+    const int im = wrap_m(i, n), ip = wrap_p(i, n), jm = wrap_m(j, n), jp = wrap_p(j, n),
+              km = wrap_m(k, n), kp = wrap_p(k, n);
+    Off q;
+    const unsigned un = (unsigned)n;
+    if (!L.split) {
+        const unsigned row = (unsigned)k * un + (unsigned)j;
+        q.c = row * un + (unsigned)i;
+        q.xm = row * un + (unsigned)im;
+        q.xp = row * un + (unsigned)ip;
+        q.ym = ((unsigned)k * un + (unsigned)jm) * un + (unsigned)i;
+        q.yp = ((unsigned)k * un + (unsigned)jp) * un + (unsigned)i;
+        q.zm = ((unsigned)km * un + (unsigned)j) * un + (unsigned)i;
+        q.zp = ((unsigned)kp * un + (unsigned)j) * un + (unsigned)i;
+        return q;
+    }
+    const unsigned hn = un >> 1, H = un * un * hn;
+    const unsigned colour = (unsigned)((i + j + k) & 1);
+    const unsigned oc = (colour ^ 1u) * H;
+    const unsigned row = (unsigned)k * un + (unsigned)j;
+    const unsigned m = (unsigned)(i >> 1);
+    q.c = colour * H + row * hn + m;
+    q.xm = oc + row * hn + (unsigned)(im >> 1);
+    q.xp = oc + row * hn + (unsigned)(ip >> 1);
+    q.ym = oc + ((unsigned)k * un + (unsigned)jm) * hn + m;
+    q.yp = oc + ((unsigned)k * un + (unsigned)jp) * hn + m;
+    q.zm = oc + ((unsigned)km * un + (unsigned)j) * hn + m;
+    q.zp = oc + ((unsigned)kp * un + (unsigned)j) * hn + m;
     return q;
 }
 
 template <typename T>
-__device__ __forceinline__ double nsum(const T *v, const Nbrs &q) {
+__device__ __forceinline__ double nsum(const T *__restrict__ v, const Off &q) {
     return ((double)v[q.xp] + (double)v[q.xm]) + ((double)v[q.yp] + (double)v[q.ym]) +
            ((double)v[q.zp] + (double)v[q.zm]);
 }
 
 // Cubic term of the chemical potential in its second-order form,
 // g(x; a) = 1/4 (x + a)(x^2 + a^2), a = phi^kappa (Section 5, N2).
-// DELTA: the correction form G(e) = g(b + e; a) - g(b; a) expanded without
+// DELTA: the correction form G(e) = g(b + e; a) - g(b; a), expanded without
 // cancellation, b the base iterate.
 template <bool DELTA>
 struct Cubic;
@@ -89,55 +186,70 @@ struct Cubic<true> {
 //     phi + A mu             = r1     A = 6 tau/h^2, r1 = f1 + tau S_mu/h^2
 //    -c phi + mu + B omega   = r2     B = 6/h^2,     r2 = f2 + S_om/h^2 + (lin.)
 //     Dd phi + omega         = r3     Dd = 3/h^2,    r3 = f3 + S_phi/(2h^2)
-// with c the linearised slope of the cubic term; eliminating omega and mu
-// gives phi = (r1 - A r2 + A B r3) / (1 + A (c + B Dd)).
+// c is the linearised slope of the cubic term; eliminating omega and mu gives
+// phi = (r1 - A r2 + A B r3) / (1 + A (c + B Dd)).
+// One thread per point of colour `colour` (colour-split storage only).
 template <typename T, bool DELTA>
 __global__ __launch_bounds__(kBlock) void k_smooth(OpParams op, int colour, int picard, Tri<T> u,
                                                    Tri<const T> f, const T *__restrict__ phk,
                                                    const T *__restrict__ base) {
-    const int n = op.n, half = n >> 1;
-    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
-    const size_t total = (size_t)half * n * n;
-    if (t >= total) return;
-    const int m = (int)(t % half);
-    const size_t rest = t / half;
-    const int j = (int)(rest % n);
-    const int k = (int)(rest / n);
-    const int i = 2 * m + ((j + k + colour) & 1);
-    const Nbrs q = nbrs(n, i, j, k);
+    const Lay &L = op.lay;
+    const int n = L.n, hn = n >> 1;
+    const unsigned H = (unsigned)((size_t)n * n * n / 2);
+    const unsigned t = xcd_block() * kBlock + threadIdx.x;
+    if (t >= H) return;
+    const unsigned row = L.dh.q(t);
+    const int m = (int)(t - row * (unsigned)hn);
+    const int k = (int)L.dn.q(row);
+    const int j = (int)(row - (unsigned)k * (unsigned)n);
+    const int p = (colour + j + k) & 1;  // x parity of this point
+    // other colour: same row for x-neighbours, same m for y/z neighbours
+    const size_t oc = (size_t)(colour ^ 1) * H;
+    const size_t own = (size_t)colour * H + t;
+    const size_t rbase = oc + (size_t)row * hn;
+    const size_t xm = rbase + (p ? m : (m == 0 ? hn - 1 : m - 1));
+    const size_t xp = rbase + (p ? (m == hn - 1 ? 0 : m + 1) : m);
+    const size_t ym = oc + ((size_t)k * n + wrap_m(j, n)) * hn + m;
+    const size_t yp = oc + ((size_t)k * n + wrap_p(j, n)) * hn + m;
+    const size_t zm = oc + ((size_t)wrap_m(k, n) * n + j) * hn + m;
+    const size_t zp = oc + ((size_t)wrap_p(k, n) * n + j) * hn + m;
 
-    const double smu = nsum(u.b, q), som = nsum(u.c, q), sphi = nsum(u.a, q);
-    const double phin = u.a[q.c], a = phk[q.c];
-    const double b = DELTA ? (double)base[q.c] : 0.0;
+    const double smu = ((double)u.b[xp] + (double)u.b[xm]) + ((double)u.b[yp] + (double)u.b[ym]) +
+                       ((double)u.b[zp] + (double)u.b[zm]);
+    const double som = ((double)u.c[xp] + (double)u.c[xm]) + ((double)u.c[yp] + (double)u.c[ym]) +
+                       ((double)u.c[zp] + (double)u.c[zm]);
+    const double sphi = ((double)u.a[xp] + (double)u.a[xm]) + ((double)u.a[yp] + (double)u.a[ym]) +
+                        ((double)u.a[zp] + (double)u.a[zm]);
+    const double phin = u.a[own], a = phk[own];
+    const double b = DELTA ? (double)base[own] : 0.0;
     const double h2inv = op.h2inv, tau = op.tau, lin_c = 0.5 * (1.0 - op.eps);
     double c, r2;
     if (!DELTA && picard) {
         const double qq = 0.25 * (phin * phin + a * a);
         c = qq + lin_c;
-        r2 = (double)f.b[q.c] + som * h2inv + qq * a;
+        r2 = (double)f.b[own] + som * h2inv + qq * a;
     } else {
         const double gp = Cubic<DELTA>::dg(phin, a, b);
         c = gp + lin_c;
-        r2 = (double)f.b[q.c] + som * h2inv + (Cubic<DELTA>::g(phin, a, b) - gp * phin);
+        r2 = (double)f.b[own] + som * h2inv + (Cubic<DELTA>::g(phin, a, b) - gp * phin);
     }
-    const double r1 = (double)f.a[q.c] + tau * smu * h2inv;
-    const double r3 = (double)f.c[q.c] + 0.5 * sphi * h2inv;
+    const double r1 = (double)f.a[own] + tau * smu * h2inv;
+    const double r3 = (double)f.c[own] + 0.5 * sphi * h2inv;
     const double A = 6.0 * tau * h2inv, B = 6.0 * h2inv, Dd = 3.0 * h2inv;
     const double phi = (r1 - A * r2 + A * B * r3) / (1.0 + A * (c + B * Dd));
     const double om = r3 - Dd * phi;
     const double mu = r2 + c * phi - B * om;
-    u.a[q.c] = (T)phi;
-    u.b[q.c] = (T)mu;
-    u.c[q.c] = (T)om;
+    u.a[own] = (T)phi;
+    u.b[own] = (T)mu;
+    u.c[own] = (T)om;
 }
 
 template <typename T, bool DELTA>
 void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
                    Tri<const T> f, const T *phk, const T *base) {
-    const size_t total = (size_t)(op.n / 2) * op.n * op.n;
-    const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_smooth<T, DELTA>), dim3(blocks), dim3(kBlock), 0, s, op, colour, picard,
-                       u, f, phk, base);
+    const size_t H = npts_host(op.lay) / 2;
+    hipLaunchKernelGGL((k_smooth<T, DELTA>), dim3(blocks_for(H)), dim3(kBlock), 0, s, op, colour,
+                       picard, u, f, phk, base);
 }
 
 // ------------------------------------------------------------ residual
@@ -147,7 +259,7 @@ void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tr
 template <typename T, bool DELTA>
 __device__ __forceinline__ void resid_at(const OpParams &op, const Tri<const T> &u,
                                          const Tri<const T> &f, const T *phk, const T *base,
-                                         const Nbrs &q, double &r1, double &r2, double &r3) {
+                                         const Off &q, double &r1, double &r2, double &r3) {
     const double phi = u.a[q.c], mu = u.b[q.c], om = u.c[q.c];
     const double lmu = (nsum(u.b, q) - 6.0 * mu) * op.h2inv;
     const double lom = (nsum(u.c, q) - 6.0 * om) * op.h2inv;
@@ -163,16 +275,18 @@ __device__ __forceinline__ unsigned long long abs_bits(double v) {
     return (unsigned long long)__double_as_longlong(v) & 0x7fffffffffffffffull;
 }
 
-// Block max of non-negative IEEE bit patterns (NaN sorts above +Inf).
+__device__ __forceinline__ unsigned long long umax(unsigned long long a, unsigned long long b) {
+    return a > b ? a : b;
+}
+
+// Block max of non-negative IEEE bit patterns (NaN sorts above +Inf, so a
+// NaN residual is never lost).
 __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v) {
     __shared__ unsigned long long red[kBlock];
     red[threadIdx.x] = v;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            const unsigned long long o = red[threadIdx.x + w];
-            if (o > red[threadIdx.x]) red[threadIdx.x] = o;
-        }
+        if ((int)threadIdx.x < w) red[threadIdx.x] = umax(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
     return red[0];
@@ -183,16 +297,13 @@ __global__ __launch_bounds__(kBlock) void k_resid_max(OpParams op, Tri<const T> 
                                                       const T *__restrict__ phk,
                                                       const T *__restrict__ base, Tri<T> r,
                                                       unsigned long long *partial) {
-    const int n = op.n;
-    const unsigned blk = xcd_block();
-    const size_t t = (size_t)blk * kBlock + threadIdx.x;
-    const size_t total = (size_t)n * n * n;
+    const Lay &L = op.lay;
+    const unsigned total = (unsigned)npts(L);
     unsigned long long m = 0;
-    if (t < total) {
-        const int i = (int)(t % n);
-        const int j = (int)((t / n) % n);
-        const int k = (int)(t / ((size_t)n * n));
-        const Nbrs q = nbrs(n, i, j, k);
+    for (unsigned t = xcd_block() * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock) {
+        int i, j, k;
+        decode(L, t, i, j, k);
+        const Off q = offs(L, i, j, k);
         double r1, r2, r3;
         resid_at<T, DELTA>(op, u, f, phk, base, q, r1, r2, r3);
         if (r.a) {
@@ -200,124 +311,100 @@ __global__ __launch_bounds__(kBlock) void k_resid_max(OpParams op, Tri<const T> 
             r.b[q.c] = (T)r2;
             r.c[q.c] = (T)r3;
         }
-        m = abs_bits(r1);
-        const unsigned long long m2 = abs_bits(r2), m3 = abs_bits(r3);
-        if (m2 > m) m = m2;
-        if (m3 > m) m = m3;
+        m = umax(m, umax(abs_bits(r1), umax(abs_bits(r2), abs_bits(r3))));
     }
     m = block_max_u64(m);
-    if (threadIdx.x == 0) partial[blk] = m;
+    if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
 template <typename T, bool DELTA>
 int launch_resid_max(hipStream_t s, const OpParams &op, Tri<const T> u, Tri<const T> f,
                      const T *phk, const T *base, Tri<T> r, unsigned long long *partial) {
-    const size_t total = (size_t)op.n * op.n * op.n;
-    const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
+    const unsigned blocks = reduce_blocks(npts_host(op.lay));
     hipLaunchKernelGGL((k_resid_max<T, DELTA>), dim3(blocks), dim3(kBlock), 0, s, op, u, f, phk,
                        base, r, partial);
     return (int)blocks;
 }
 
-__global__ __launch_bounds__(1024) void k_max_final(const unsigned long long *partial, int count,
-                                                    double *out) {
-    __shared__ unsigned long long red[1024];
+__global__ __launch_bounds__(kBlock) void k_max_final(const unsigned long long *partial, int count,
+                                                      double *out) {
     unsigned long long m = 0;
-    for (int b = threadIdx.x; b < count; b += 1024)
-        if (partial[b] > m) m = partial[b];
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w && red[threadIdx.x + w] > red[threadIdx.x])
-            red[threadIdx.x] = red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = __longlong_as_double((long long)red[0]);
+    for (int b = threadIdx.x; b < count; b += kBlock) m = umax(m, partial[b]);
+    m = block_max_u64(m);
+    if (threadIdx.x == 0) out[0] = __longlong_as_double((long long)m);
 }
 
 void launch_max_final(hipStream_t s, const unsigned long long *partial, int count, double *out) {
-    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(1024), 0, s, partial, count, out);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, partial, count, out);
 }
 
 // ------------------------------------------------ residual + coarsening
 //
-// One thread per coarse cell: residual at the 8 children, then the coarse
+// One thread per coarse cell: residual at its 8 children, then the coarse
 // cell's restricted residual I r and restricted iterate I u (8-child means).
 template <typename T, bool DELTA>
-__global__ __launch_bounds__(kBlock) void k_resid_restrict(OpParams op, Tri<const T> u,
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(OpParams op, Lay LC, Tri<const T> u,
                                                            Tri<const T> f,
                                                            const T *__restrict__ phk,
                                                            const T *__restrict__ base,
                                                            Tri<T> ubar_c, Tri<T> rr_c) {
-    const int nf = op.n, nc = nf >> 1;
-    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
-    const size_t total = (size_t)nc * nc * nc;
-    if (t >= total) return;
-    const int I = (int)(t % nc);
-    const int J = (int)((t / nc) % nc);
-    const int K = (int)(t / ((size_t)nc * nc));
+    // coarse cells in natural order, so that consecutive threads read
+    // consecutive fine offsets of each colour
+    const unsigned tn = xcd_block() * kBlock + threadIdx.x;
+    if (tn >= (unsigned)npts(LC)) return;
+    int I, J, K;
+    decode_nat(LC, tn, I, J, K);
+    const unsigned t = sidx32(LC, I, J, K);
     double s1 = 0, s2 = 0, s3 = 0, ua = 0, ub = 0, uc = 0;
-#pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                const Nbrs q = nbrs(nf, 2 * I + cx, 2 * J + cy, 2 * K + cz);
-                double r1, r2, r3;
-                resid_at<T, DELTA>(op, u, f, phk, base, q, r1, r2, r3);
-                s1 += r1;
-                s2 += r2;
-                s3 += r3;
-                ua += (double)u.a[q.c];
-                ub += (double)u.b[q.c];
-                uc += (double)u.c[q.c];
-            }
-    const size_t o = lin(nc, I, J, K);
-    rr_c.a[o] = (T)(0.125 * s1);
-    rr_c.b[o] = (T)(0.125 * s2);
-    rr_c.c[o] = (T)(0.125 * s3);
-    ubar_c.a[o] = (T)(0.125 * ua);
-    ubar_c.b[o] = (T)(0.125 * ub);
-    ubar_c.c[o] = (T)(0.125 * uc);
+#pragma unroll 1
+    for (int ch = 0; ch < 8; ++ch) {
+        const Off q = offs(op.lay, 2 * I + (ch & 1), 2 * J + ((ch >> 1) & 1), 2 * K + (ch >> 2));
+        double r1, r2, r3;
+        resid_at<T, DELTA>(op, u, f, phk, base, q, r1, r2, r3);
+        s1 += r1;
+        s2 += r2;
+        s3 += r3;
+        ua += (double)u.a[q.c];
+        ub += (double)u.b[q.c];
+        uc += (double)u.c[q.c];
+    }
+    rr_c.a[t] = (T)(0.125 * s1);
+    rr_c.b[t] = (T)(0.125 * s2);
+    rr_c.c[t] = (T)(0.125 * s3);
+    ubar_c.a[t] = (T)(0.125 * ua);
+    ubar_c.b[t] = (T)(0.125 * ub);
+    ubar_c.c[t] = (T)(0.125 * uc);
 }
 
 template <typename T, bool DELTA>
-void launch_resid_restrict(hipStream_t s, const OpParams &op, Tri<const T> u, Tri<const T> f,
-                           const T *phk, const T *base, Tri<T> ubar_c, Tri<T> rr_c) {
-    const size_t nc = op.n / 2;
-    const size_t total = nc * nc * nc;
-    const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_resid_restrict<T, DELTA>), dim3(blocks), dim3(kBlock), 0, s, op, u, f,
-                       phk, base, ubar_c, rr_c);
+void launch_resid_restrict(hipStream_t s, const OpParams &op, const Lay &coarse, Tri<const T> u,
+                           Tri<const T> f, const T *phk, const T *base, Tri<T> ubar_c, Tri<T> rr_c) {
+    hipLaunchKernelGGL((k_resid_restrict<T, DELTA>), dim3(blocks_for(npts_host(coarse))),
+                       dim3(kBlock), 0, s, op, coarse, u, f, phk, base, ubar_c, rr_c);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_restrict(int nf, const T *__restrict__ fine,
+__global__ __launch_bounds__(kBlock) void k_restrict(Lay LF, Lay LC, const T *__restrict__ fine,
                                                      T *__restrict__ coarse) {
-    const int nc = nf >> 1;
-    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
-    const size_t total = (size_t)nc * nc * nc;
-    if (t >= total) return;
-    const int I = (int)(t % nc);
-    const int J = (int)((t / nc) % nc);
-    const int K = (int)(t / ((size_t)nc * nc));
+    const unsigned tn = xcd_block() * kBlock + threadIdx.x;
+    if (tn >= (unsigned)npts(LC)) return;
+    int I, J, K;
+    decode_nat(LC, tn, I, J, K);
+    const unsigned t = sidx32(LC, I, J, K);
     double s = 0;
 #pragma unroll
     for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
         for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-            for (int cx = 0; cx < 2; ++cx) s += (double)fine[lin(nf, 2 * I + cx, 2 * J + cy, 2 * K + cz)];
-    coarse[lin(nc, I, J, K)] = (T)(0.125 * s);
+            for (int cx = 0; cx < 2; ++cx) s += (double)fine[sidx32(LF, 2 * I + cx, 2 * J + cy, 2 * K + cz)];
+    coarse[t] = (T)(0.125 * s);
 }
 
 template <typename T>
-void launch_restrict(hipStream_t s, int nf, const T *fine, T *coarse) {
-    const size_t nc = nf / 2;
-    const size_t total = nc * nc * nc;
-    const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_restrict<T>), dim3(blocks), dim3(kBlock), 0, s, nf, fine, coarse);
+void launch_restrict(hipStream_t s, const Lay &fine, const Lay &coarse, const T *fine_v, T *coarse_v) {
+    hipLaunchKernelGGL((k_restrict<T>), dim3(blocks_for(npts_host(coarse))), dim3(kBlock), 0, s,
+                       fine, coarse, fine_v, coarse_v);
 }
 
 // ------------------------------------------------------- tau correction
@@ -328,125 +415,127 @@ template <typename T, bool DELTA>
 __global__ __launch_bounds__(kBlock) void k_tau(OpParams op, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                                                 const T *__restrict__ phk,
                                                 const T *__restrict__ base) {
-    const int n = op.n;
-    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
-    const size_t total = (size_t)n * n * n;
-    if (t >= total) return;
-    const int i = (int)(t % n);
-    const int j = (int)((t / n) % n);
-    const int k = (int)(t / ((size_t)n * n));
-    const Nbrs q = nbrs(n, i, j, k);
-    const double phi = ubar.a[q.c], mu = ubar.b[q.c], om = ubar.c[q.c];
+    const Lay &L = op.lay;
+    const unsigned t = xcd_block() * kBlock + threadIdx.x;
+    if (t >= (unsigned)npts(L)) return;
+    int i, j, k;
+    decode(L, t, i, j, k);
+    const Off q = offs(L, i, j, k);
+    const double phi = ubar.a[t], mu = ubar.b[t], om = ubar.c[t];
     const double lmu = (nsum(ubar.b, q) - 6.0 * mu) * op.h2inv;
     const double lom = (nsum(ubar.c, q) - 6.0 * om) * op.h2inv;
     const double lphi = (nsum(ubar.a, q) - 6.0 * phi) * op.h2inv;
-    const double a = phk[q.c];
-    const double b = DELTA ? (double)base[q.c] : 0.0;
+    const double a = phk[t];
+    const double b = DELTA ? (double)base[t] : 0.0;
     const double n1 = phi - op.tau * lmu;
     const double n2 = mu - Cubic<DELTA>::g(phi, a, b) - 0.5 * (1.0 - op.eps) * phi - lom;
     const double n3 = om - 0.5 * lphi;
-    f.a[q.c] = (T)((double)f.a[q.c] + n1);
-    f.b[q.c] = (T)((double)f.b[q.c] + n2);
-    f.c[q.c] = (T)((double)f.c[q.c] + n3);
-    u.a[q.c] = ubar.a[q.c];
-    u.b[q.c] = ubar.b[q.c];
-    u.c[q.c] = ubar.c[q.c];
+    f.a[t] = (T)((double)f.a[t] + n1);
+    f.b[t] = (T)((double)f.b[t] + n2);
+    f.c[t] = (T)((double)f.c[t] + n3);
+    u.a[t] = ubar.a[t];
+    u.b[t] = ubar.b[t];
+    u.c[t] = ubar.c[t];
 }
 
 template <typename T, bool DELTA>
 void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                 const T *phk, const T *base) {
-    const size_t total = (size_t)opc.n * opc.n * opc.n;
-    const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_tau<T, DELTA>), dim3(blocks), dim3(kBlock), 0, s, opc, ubar, f, u, phk,
-                       base);
+    hipLaunchKernelGGL((k_tau<T, DELTA>), dim3(blocks_for(npts_host(opc.lay))), dim3(kBlock), 0, s,
+                       opc, ubar, f, u, phk, base);
 }
 
 // ------------------------------------------------- interpolation + correction
 //
-// fine += P (v - ubar) (ubar may be null; fine.b null: one field only):
-// cell-centred trilinear interpolation.  Along one axis
-// fine cell 2I+d (d = 0, 1) takes 3/4 of coarse cell I and 1/4 of cell I-1
-// (d = 0) or I+1 (d = 1), periodic; 3D weights are products.
+// fine += P (v - ubar), cell-centred trilinear: along one axis fine cell 2I+d
+// (d = 0, 1) takes 3/4 of coarse cell I and 1/4 of cell I-1 (d = 0) or I+1
+// (d = 1), periodic; 3D weights are products.  One thread per pair of fine
+// cells (2I, j, k), (2I+1, j, k): they share the 12 coarse cells
+// {I-1, I, I+1} x {J0, J1} x {K0, K1}.  Consecutive threads take consecutive
+// I, so the fine accesses are unit-stride in each colour block.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(int nc, Tri<const T> v, Tri<const T> ubar,
+__global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T> v, Tri<const T> ubar,
                                                     Tri<T> fine) {
-    const int nf = nc << 1;
-    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
-    const size_t total = (size_t)nf * nf * nf;
-    if (t >= total) return;
-    const int i = (int)(t % nf);
-    const int j = (int)((t / nf) % nf);
-    const int k = (int)(t / ((size_t)nf * nf));
-    const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
-    const int I1 = (i & 1) ? wrap_p(I0, nc) : wrap_m(I0, nc);
+    const int nc = LC.n, nf = LF.n;
+    const unsigned t = xcd_block() * kBlock + threadIdx.x;
+    if (t >= (unsigned)nc * (unsigned)nf * (unsigned)nf) return;
+    const unsigned row = LC.dn.q(t);           // (k, j) fine row
+    const int I = (int)(t - row * (unsigned)nc);
+    const int k = (int)LF.dn.q(row);
+    const int j = (int)(row - (unsigned)k * (unsigned)nf);
+    const int J0 = j >> 1, K0 = k >> 1;
     const int J1 = (j & 1) ? wrap_p(J0, nc) : wrap_m(J0, nc);
     const int K1 = (k & 1) ? wrap_p(K0, nc) : wrap_m(K0, nc);
-    const int Is[2] = {I0, I1}, Js[2] = {J0, J1}, Ks[2] = {K0, K1};
-    const double w[2] = {0.75, 0.25};
-    double ea = 0, eb = 0, ec = 0;
+    const int Ix[3] = {wrap_m(I, nc), I, wrap_p(I, nc)};
+    unsigned o[2][2][3];  // [z][y][x]
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int z = 0; z < 2; ++z)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const double ww = w[a] * w[b] * w[c];
-                const size_t o = lin(nc, Is[a], Js[b], Ks[c]);
-                double da = v.a[o];
-                if (ubar.a) da -= (double)ubar.a[o];
-                ea += ww * da;
-                if (fine.b) {
-                    double db = v.b[o], dc = v.c[o];
-                    if (ubar.a) {
-                        db -= (double)ubar.b[o];
-                        dc -= (double)ubar.c[o];
-                    }
-                    eb += ww * db;
-                    ec += ww * dc;
-                }
-            }
-    const size_t o = lin(nf, i, j, k);
-    fine.a[o] = (T)((double)fine.a[o] + ea);
-    if (fine.b) {
-        fine.b[o] = (T)((double)fine.b[o] + eb);
-        fine.c[o] = (T)((double)fine.c[o] + ec);
+            for (int x = 0; x < 3; ++x) o[z][y][x] = sidx32(LC, Ix[x], y ? J1 : J0, z ? K1 : K0);
+    const unsigned f0 = sidx32(LF, 2 * I, j, k), f1 = sidx32(LF, 2 * I + 1, j, k);
+    const int ncomp = fine.b ? 3 : 1;
+#pragma unroll 1
+    for (int comp = 0; comp < ncomp; ++comp) {
+        const T *vv = comp == 0 ? v.a : (comp == 1 ? v.b : v.c);
+        const T *uu = comp == 0 ? ubar.a : (comp == 1 ? ubar.b : ubar.c);
+        T *ff = comp == 0 ? fine.a : (comp == 1 ? fine.b : fine.c);
+        double w[3];  // y/z-interpolated values at x = I-1, I, I+1
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            double e[2][2];
+#pragma unroll
+            for (int z = 0; z < 2; ++z)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    e[z][y] = (double)vv[o[z][y][x]] - (uu ? (double)uu[o[z][y][x]] : 0.0);
+            w[x] = 0.75 * (0.75 * e[0][0] + 0.25 * e[0][1]) + 0.25 * (0.75 * e[1][0] + 0.25 * e[1][1]);
+        }
+        ff[f0] = (T)((double)ff[f0] + (0.75 * w[1] + 0.25 * w[0]));
+        ff[f1] = (T)((double)ff[f1] + (0.75 * w[1] + 0.25 * w[2]));
     }
 }
 
 template <typename T>
-void launch_prolong(hipStream_t s, int nc, Tri<const T> v, Tri<const T> ubar, Tri<T> fine) {
-    const size_t nf = 2 * (size_t)nc;
-    const size_t total = nf * nf * nf;
-    const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_prolong<T>), dim3(blocks), dim3(kBlock), 0, s, nc, v, ubar, fine);
+void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
+                    Tri<const T> ubar, Tri<T> fine_u) {
+    const size_t pairs = (size_t)coarse.n * fine.n * fine.n;
+    hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine, v,
+                       ubar, fine_u);
 }
 
 // ------------------------------------------------------ coarsest solve
 //
-// Newton's method on the coarsest level (n = 3 or 4, P = n^3 <= 64 points),
-// one 64-lane wavefront, lane p owning point p.  omega and mu enter the
-// system linearly, so they are eliminated exactly and Newton runs on phi:
+// Exact solve of N_c(u) = f on the coarsest level (natural layout, n = 3 or
+// 4, P = n^3 <= 64 points), one 64-lane wavefront, lane p owning point p.
+// omega and mu enter linearly and are eliminated exactly:
 //   F(phi) = phi - tau Lap(g(phi) + (1-eps)/2 phi) - tau/2 Lap^3 phi - b = 0,
 //   b = f1 + tau Lap(f2 + Lap f3),
 //   F'(phi) = I - tau Lap diag(g'(phi) + (1-eps)/2) - tau/2 Lap^3,
 // then omega = f3 + Lap phi / 2 and mu = f2 + g(phi) + (1-eps)/2 phi + Lap omega.
-// The Newton iterates in phi are those of Newton on the full 3P system.
-// Each Newton step factorises F' (dense, column-major in LDS) by LU with
-// partial pivoting.  Stops when max|delta| <= 1e-14 max(1, max|phi|) or after
-// 30 iterations.  lap1 / lap3: the P x P matrices of Lap and Lap^3 (column-major).
+// Iteration: phi <- phi - Minv F(phi) with Minv = F'(phi_0)^{-1} kept across
+// calls (chord method); when an iteration contracts by less than 4x, Minv is
+// rebuilt at the current iterate (which makes that step a Newton step).  The
+// inverse comes from Gauss-Jordan elimination with partial pivoting in LDS.
+// Stops when max|update| <= 1e-14 max(1, max|phi|) (or after 60 iterations).
+__device__ __forceinline__ double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 template <typename T, bool DELTA>
 __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const T> f,
                                                const T *__restrict__ phk,
                                                const T *__restrict__ base,
                                                const double *__restrict__ lap1,
-                                               const double *__restrict__ lap3, int *iters) {
-    __shared__ double Jm[64 * 64];
+                                               const double *__restrict__ lap3, double *minv,
+                                               int *valid, int *iters) {
+    __shared__ double A[64 * 64];  // column-major: A[col * P + row]
     __shared__ double vec[64];
-    __shared__ double rhs[64];
-    __shared__ double sol[64];
     __shared__ double dvec[64];
-    const int n = op.n, P = n * n * n;
+    __shared__ int perm[64];
+    const int n = op.lay.n, P = n * n * n;
     const int p = threadIdx.x;
     const bool act = p < P;
     const double h2inv = op.h2inv, tau = op.tau, lc = 0.5 * (1.0 - op.eps);
@@ -454,15 +543,15 @@ __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const 
     int nb[6] = {0, 0, 0, 0, 0, 0};
     if (act) {
         const int i = p % n, j = (p / n) % n, k = p / (n * n);
-        nb[0] = (int)lin(n, wrap_p(i, n), j, k);
-        nb[1] = (int)lin(n, wrap_m(i, n), j, k);
-        nb[2] = (int)lin(n, i, wrap_p(j, n), k);
-        nb[3] = (int)lin(n, i, wrap_m(j, n), k);
-        nb[4] = (int)lin(n, i, j, wrap_p(k, n));
-        nb[5] = (int)lin(n, i, j, wrap_m(k, n));
+        nb[0] = (k * n + j) * n + wrap_p(i, n);
+        nb[1] = (k * n + j) * n + wrap_m(i, n);
+        nb[2] = (k * n + wrap_p(j, n)) * n + i;
+        nb[3] = (k * n + wrap_m(j, n)) * n + i;
+        nb[4] = (wrap_p(k, n) * n + j) * n + i;
+        nb[5] = (wrap_m(k, n) * n + j) * n + i;
     }
+    // Lap of the field held in vec[] at point p (call between barriers)
     auto lap_lds = [&](double own) -> double {
-        // vec[] holds the field; returns Lap at point p
         return ((vec[nb[0]] + vec[nb[1]]) + (vec[nb[2]] + vec[nb[3]]) + (vec[nb[4]] + vec[nb[5]]) -
                 6.0 * own) * h2inv;
     };
@@ -473,48 +562,27 @@ __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const 
     const double F3 = act ? (double)f.c[p] : 0.0;
     double x = act ? (double)u.a[p] : 0.0;
 
-    // b = f1 + tau Lap(f2 + Lap f3)
     vec[p] = F3;
     __syncthreads();
-    double t = act ? lap_lds(F3) : 0.0;
+    const double t3 = act ? lap_lds(F3) : 0.0;
     __syncthreads();
-    vec[p] = F2 + t;
+    vec[p] = F2 + t3;
     __syncthreads();
-    const double bp = F1 + tau * (act ? lap_lds(F2 + t) : 0.0);
+    const double bp = F1 + tau * (act ? lap_lds(F2 + t3) : 0.0);
     __syncthreads();
 
-    int it;
-    for (it = 1; it <= 30; ++it) {
-        const double w = Cubic<DELTA>::g(x, a, bs) + lc * x;
-        const double D = Cubic<DELTA>::dg(x, a, bs) + lc;
-        vec[p] = w;
+    // Builds Minv = F'(x)^{-1} into global memory.
+    auto rebuild = [&]() {
+        dvec[p] = Cubic<DELTA>::dg(x, a, bs) + lc;
         __syncthreads();
-        const double lw = act ? lap_lds(w) : 0.0;
-        __syncthreads();
-        vec[p] = x;
-        __syncthreads();
-        double l1 = act ? lap_lds(x) : 0.0;
-        __syncthreads();
-        vec[p] = l1;
-        __syncthreads();
-        double l2 = act ? lap_lds(l1) : 0.0;
-        __syncthreads();
-        vec[p] = l2;
-        __syncthreads();
-        const double l3 = act ? lap_lds(l2) : 0.0;
-        rhs[p] = act ? -(x - tau * lw - 0.5 * tau * l3 - bp) : 0.0;
-        dvec[p] = D;
-        __syncthreads();
-        if (act) {
-            for (int qc = 0; qc < P; ++qc) {
-                const size_t o = (size_t)qc * P + p;
-                Jm[o] = (qc == p ? 1.0 : 0.0) - tau * lap1[o] * dvec[qc] - 0.5 * tau * lap3[o];
+        if (act)
+            for (int q = 0; q < P; ++q) {
+                const int o = q * P + p;
+                A[o] = (q == p ? 1.0 : 0.0) - tau * lap1[o] * dvec[q] - 0.5 * tau * lap3[o];
             }
-        }
         __syncthreads();
-        // LU with partial pivoting, column by column.
         for (int c = 0; c < P; ++c) {
-            double val = (act && p >= c) ? fabs(Jm[(size_t)c * P + p]) : -1.0;
+            double val = (act && p >= c) ? fabs(A[c * P + p]) : -1.0;
             int id = p;
             for (int off = 32; off > 0; off >>= 1) {
                 const double ov = __shfl_xor(val, off, 64);
@@ -524,46 +592,86 @@ __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const 
                     id = oid;
                 }
             }
-            const int pv = id;
-            if (pv != c) {
-                if (act) {
-                    const double tmp = Jm[(size_t)p * P + c];
-                    Jm[(size_t)p * P + c] = Jm[(size_t)p * P + pv];
-                    Jm[(size_t)p * P + pv] = tmp;
-                }
-                if (p == 0) {
-                    const double tmp = rhs[c];
-                    rhs[c] = rhs[pv];
-                    rhs[pv] = tmp;
+            const int pr = id;
+            if (p == 0) perm[c] = pr;
+            if (pr != c && act) {  // swap rows c and pr; lane p handles column p
+                const double tmp = A[p * P + c];
+                A[p * P + c] = A[p * P + pr];
+                A[p * P + pr] = tmp;
+            }
+            __syncthreads();
+            const double pinv = 1.0 / A[c * P + c];
+            __syncthreads();
+            if (act) A[p * P + c] = (p == c ? 1.0 : A[p * P + c]) * pinv;  // scale pivot row
+            __syncthreads();
+            if (act && p != c) {
+                const double fr = A[c * P + p];
+                for (int q = 0; q < P; ++q) {
+                    const double old = (q == c) ? 0.0 : A[q * P + p];
+                    A[q * P + p] = old - fr * A[q * P + c];
                 }
             }
             __syncthreads();
-            if (act && p > c) {
-                const double lr = Jm[(size_t)c * P + p] / Jm[(size_t)c * P + c];
-                Jm[(size_t)c * P + p] = lr;
-                rhs[p] -= lr * rhs[c];
-                for (int qc = c + 1; qc < P; ++qc) Jm[(size_t)qc * P + p] -= lr * Jm[(size_t)qc * P + c];
+        }
+        for (int c = P - 1; c >= 0; --c) {  // undo the row swaps as column swaps
+            const int pr = perm[c];
+            if (pr != c && act) {
+                const double tmp = A[c * P + p];
+                A[c * P + p] = A[pr * P + p];
+                A[pr * P + p] = tmp;
             }
             __syncthreads();
         }
-        for (int c = P - 1; c >= 0; --c) {
-            if (p == c) sol[c] = rhs[c] / Jm[(size_t)c * P + c];
-            __syncthreads();
-            if (act && p < c) rhs[p] -= Jm[(size_t)c * P + p] * sol[c];
-            __syncthreads();
-        }
-        const double d = act ? sol[p] : 0.0;
-        x += d;
-        double dm = fabs(d), xm = fabs(x);
-        for (int off = 32; off > 0; off >>= 1) {
-            dm = fmax(dm, __shfl_xor(dm, off, 64));
-            xm = fmax(xm, __shfl_xor(xm, off, 64));
-        }
+        if (act)
+            for (int q = 0; q < P; ++q) minv[q * P + p] = A[q * P + p];
         __syncthreads();
-        if (!(dm == dm)) break;  // NaN: give up, the residual test reports it
-        if (dm <= 1e-14 * fmax(1.0, xm)) break;
+    };
+
+    bool fresh = false;
+    if (!*valid) {
+        rebuild();
+        fresh = true;
     }
-    if (it > 30) it = 30;
+    double dprev = 0.0;
+    int it;
+    for (it = 1; it <= 60; ++it) {
+        const double w = Cubic<DELTA>::g(x, a, bs) + lc * x;
+        vec[p] = w;
+        __syncthreads();
+        const double lw = act ? lap_lds(w) : 0.0;
+        __syncthreads();
+        vec[p] = x;
+        __syncthreads();
+        const double l1 = act ? lap_lds(x) : 0.0;
+        __syncthreads();
+        vec[p] = l1;
+        __syncthreads();
+        const double l2 = act ? lap_lds(l1) : 0.0;
+        __syncthreads();
+        vec[p] = l2;
+        __syncthreads();
+        const double l3 = act ? lap_lds(l2) : 0.0;
+        __syncthreads();
+        dvec[p] = act ? (x - tau * lw - 0.5 * tau * l3 - bp) : 0.0;
+        __syncthreads();
+        double d = 0.0;
+        if (act)
+            for (int q = 0; q < P; ++q) d -= minv[q * P + p] * dvec[q];
+        x += d;
+        const double dm = wave_max(fabs(d));
+        const double xm = wave_max(fabs(x));
+        __syncthreads();
+        if (!(dm == dm)) break;
+        if (dm <= 1e-14 * fmax(1.0, xm)) break;
+        if (!fresh && it > 1 && dm > 0.25 * dprev) {
+            rebuild();
+            fresh = true;
+        } else {
+            fresh = false;
+        }
+        dprev = dm;
+    }
+    if (it > 60) it = 60;
     vec[p] = x;
     __syncthreads();
     const double lx = act ? lap_lds(x) : 0.0;
@@ -578,56 +686,57 @@ __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const 
         u.b[p] = (T)mu;
         u.c[p] = (T)om;
     }
-    if (p == 0 && iters) *iters = it;
+    if (p == 0) {
+        *valid = 1;
+        if (iters) *iters = it;
+    }
 }
 
 template <typename T, bool DELTA>
 void launch_coarse(hipStream_t s, const OpParams &op, Tri<T> u, Tri<const T> f, const T *phk,
-                   const T *base, const double *lap1, const double *lap3, int *iters) {
+                   const T *base, const double *lap1, const double *lap3, double *minv, int *,
+                   int *valid, int *iters) {
     hipLaunchKernelGGL((k_coarse<T, DELTA>), dim3(1), dim3(64), 0, s, op, u, f, phk, base, lap1,
-                       lap3, iters);
+                       lap3, minv, valid, iters);
 }
 
 // --------------------------------------------------------------- source
 
-// S of (scheme-PFC-s1..s3): f1 = phk, f2 = (1-eps)/2 phk + 3 Lap phk - Lap phkm1,
+// S of (scheme-PFC-s1..s3) from natural-layout phi^k and phi^{k-1}, written
+// in layout op.lay: f1 = phk, f2 = (1-eps)/2 phk + 3 Lap phk - Lap phkm1,
 // f3 = Lap phk / 2.
-__global__ __launch_bounds__(kBlock) void k_source(OpParams op, const double *__restrict__ phk,
+__global__ __launch_bounds__(kBlock) void k_source(OpParams op, Lay nat, const double *__restrict__ phk,
                                                    const double *__restrict__ phkm1,
                                                    Tri<double> f) {
-    const int n = op.n;
-    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
-    const size_t total = (size_t)n * n * n;
-    if (t >= total) return;
-    const int i = (int)(t % n);
-    const int j = (int)((t / n) % n);
-    const int k = (int)(t / ((size_t)n * n));
-    const Nbrs q = nbrs(n, i, j, k);
+    const unsigned t = xcd_block() * kBlock + threadIdx.x;
+    if (t >= (unsigned)npts(nat)) return;
+    int i, j, k;
+    decode(nat, t, i, j, k);
+    const Off q = offs(nat, i, j, k);
     const double v = phk[q.c];
     const double lk = (nsum(phk, q) - 6.0 * v) * op.h2inv;
     const double lkm1 = (nsum(phkm1, q) - 6.0 * phkm1[q.c]) * op.h2inv;
-    f.a[q.c] = v;
-    f.b[q.c] = 0.5 * (1.0 - op.eps) * v + 3.0 * lk - lkm1;
-    f.c[q.c] = 0.5 * lk;
+    const unsigned o = sidx32(op.lay, i, j, k);
+    f.a[o] = v;
+    f.b[o] = 0.5 * (1.0 - op.eps) * v + 3.0 * lk - lkm1;
+    f.c[o] = 0.5 * lk;
 }
 
 void launch_source(hipStream_t s, const OpParams &op, const double *phk, const double *phkm1,
                    Tri<double> f) {
-    const size_t total = (size_t)op.n * op.n * op.n;
-    const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_source, dim3(blocks), dim3(kBlock), 0, s, op, phk, phkm1, f);
+    const Lay nat = make_lay(op.lay.n, false);
+    hipLaunchKernelGGL(k_source, dim3(blocks_for(npts_host(nat))), dim3(kBlock), 0, s, op, nat, phk,
+                       phkm1, f);
 }
 
 __global__ __launch_bounds__(kBlock) void k_lap(OpParams op, const double *__restrict__ v,
                                                 double *__restrict__ out) {
-    const int n = op.n;
-    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
-    const size_t total = (size_t)n * n * n;
-    if (t >= total) return;
-    const int i = (int)(t % n);
-    const int j = (int)((t / n) % n);
-    const int k = (int)(t / ((size_t)n * n));
-    const Nbrs q = nbrs(n, i, j, k);
+    const Lay &L = op.lay;
+    const unsigned t = xcd_block() * kBlock + threadIdx.x;
+    if (t >= (unsigned)npts(L)) return;
+    int i, j, k;
+    decode(L, t, i, j, k);
+    const Off q = offs(L, i, j, k);
     out[q.c] = (nsum(v, q) - 6.0 * v[q.c]) * op.h2inv;
 }
 
@@ -635,53 +744,73 @@ __global__ __launch_bounds__(kBlock) void k_lap(OpParams op, const double *__res
 __global__ __launch_bounds__(kBlock) void k_init_mu(OpParams op, const double *__restrict__ phi,
                                                     const double *__restrict__ om,
                                                     double *__restrict__ mu) {
-    const int n = op.n;
-    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
-    const size_t total = (size_t)n * n * n;
-    if (t >= total) return;
-    const int i = (int)(t % n);
-    const int j = (int)((t / n) % n);
-    const int k = (int)(t / ((size_t)n * n));
-    const Nbrs q = nbrs(n, i, j, k);
+    const Lay &L = op.lay;
+    const unsigned t = xcd_block() * kBlock + threadIdx.x;
+    if (t >= (unsigned)npts(L)) return;
+    int i, j, k;
+    decode(L, t, i, j, k);
+    const Off q = offs(L, i, j, k);
     const double v = phi[q.c];
     const double l2 = (nsum(om, q) - 6.0 * om[q.c]) * op.h2inv;
     mu[q.c] = v * v * v + (1.0 - op.eps) * v + 2.0 * om[q.c] + l2;
 }
 
-void launch_init_guess(hipStream_t s, const OpParams &op, const double *phi0, double *mu,
+void launch_init_guess(hipStream_t s, const OpParams &nat, const double *phi0, double *mu,
                        double *om) {
-    const size_t total = (size_t)op.n * op.n * op.n;
-    const unsigned blocks = (unsigned)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_lap, dim3(blocks), dim3(kBlock), 0, s, op, phi0, om);
-    hipLaunchKernelGGL(k_init_mu, dim3(blocks), dim3(kBlock), 0, s, op, phi0, om, mu);
+    const unsigned blocks = blocks_for(npts_host(nat.lay));
+    hipLaunchKernelGGL(k_lap, dim3(blocks), dim3(kBlock), 0, s, nat, phi0, om);
+    hipLaunchKernelGGL(k_init_mu, dim3(blocks), dim3(kBlock), 0, s, nat, phi0, om, mu);
+}
+
+// ------------------------------------------------------ layout conversion
+
+template <typename S, typename D, bool TO>
+__global__ __launch_bounds__(kBlock) void k_relayout(Lay L, const S *__restrict__ src,
+                                                     D *__restrict__ dst, int count) {
+    const unsigned t = xcd_block() * kBlock + threadIdx.x;
+    const size_t P = npts(L);
+    if (t >= (unsigned)P) return;
+    int i, j, k;
+    decode(L, t, i, j, k);  // t: storage offset in L
+    const size_t nat = ((size_t)k * L.n + j) * L.n + i;
+    for (int c = 0; c < count; ++c) {
+        if (TO)
+            dst[c * P + t] = (D)src[c * P + nat];
+        else
+            dst[c * P + nat] = (D)src[c * P + t];
+    }
+}
+
+template <typename S, typename D>
+void launch_to_lay(hipStream_t s, const Lay &lay, const S *src, D *dst, int count) {
+    hipLaunchKernelGGL((k_relayout<S, D, true>), dim3(blocks_for(npts_host(lay))), dim3(kBlock), 0,
+                       s, lay, src, dst, count);
+}
+
+template <typename S, typename D>
+void launch_from_lay(hipStream_t s, const Lay &lay, const S *src, D *dst, int count) {
+    hipLaunchKernelGGL((k_relayout<S, D, false>), dim3(blocks_for(npts_host(lay))), dim3(kBlock), 0,
+                       s, lay, src, dst, count);
 }
 
 // --------------------------------------------------------------- energy
 
-constexpr int kEnergyBlocks = 1024;
-
-int energy_blocks(int n) {
-    const size_t total = (size_t)n * n * n;
-    const size_t b = (total + kBlock - 1) / kBlock;
-    return (int)(b < (size_t)kEnergyBlocks ? b : (size_t)kEnergyBlocks);
-}
+int energy_blocks(int n) { return (int)reduce_blocks((size_t)n * n * n); }
 
 // Per-block sums of phi^4, phi^2, (D phi)^2 on the cell's three forward faces
 // (so every face of the periodic grid is counted once), (Lap phi)^2, the same
 // face sum for phi - phi_prev, and phi.  Scaled by h^3 in the final pass.
-__global__ __launch_bounds__(kBlock) void k_energy_part(int n, double hinv, double h2inv,
+__global__ __launch_bounds__(kBlock) void k_energy_part(Lay L, double hinv, double h2inv,
                                                         const double *__restrict__ phi,
                                                         const double *__restrict__ prev,
                                                         double *__restrict__ part) {
     __shared__ double red[6][kBlock];
     double s[6] = {0, 0, 0, 0, 0, 0};
-    const size_t total = (size_t)n * n * n;
-    for (size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * kBlock) {
-        const int i = (int)(t % n);
-        const int j = (int)((t / n) % n);
-        const int k = (int)(t / ((size_t)n * n));
-        const Nbrs q = nbrs(n, i, j, k);
+    const unsigned total = (unsigned)npts(L);
+    for (unsigned t = blockIdx.x * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock) {
+        int i, j, k;
+        decode(L, t, i, j, k);
+        const Off q = offs(L, i, j, k);
         const double v = phi[q.c];
         const double v2 = v * v;
         s[0] += v2 * v2;
@@ -734,12 +863,69 @@ __global__ __launch_bounds__(kBlock) void k_energy_final(const double *__restric
     }
 }
 
-void launch_energy(hipStream_t s, int n, double h, double eps, const double *phi,
+void launch_energy(hipStream_t s, const Lay &nat, double h, double eps, const double *phi,
                    const double *phi_prev, double *partial, double *out3) {
-    const int blocks = energy_blocks(n);
-    hipLaunchKernelGGL(k_energy_part, dim3(blocks), dim3(kBlock), 0, s, n, 1.0 / h, 1.0 / (h * h),
+    const int blocks = energy_blocks(nat.n);
+    hipLaunchKernelGGL(k_energy_part, dim3(blocks), dim3(kBlock), 0, s, nat, 1.0 / h, 1.0 / (h * h),
                        phi, phi_prev, partial);
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s, partial, blocks, h, eps, out3);
+}
+
+// ------------------------------------------------ mixed-precision helpers
+
+__global__ __launch_bounds__(kBlock) void k_add_correction(size_t P, Tri<double> u,
+                                                           Tri<const float> e) {
+    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
+    if (t >= P) return;
+    u.a[t] += (double)e.a[t];
+    u.b[t] += (double)e.b[t];
+    u.c[t] += (double)e.c[t];
+}
+
+void launch_add_correction(hipStream_t s, size_t P, Tri<double> u, Tri<const float> e) {
+    hipLaunchKernelGGL(k_add_correction, dim3(blocks_for(P)), dim3(kBlock), 0, s, P, u, e);
+}
+
+__global__ __launch_bounds__(kBlock) void k_resid_cast(OpParams op, Tri<const double> u,
+                                                       Tri<const double> f,
+                                                       const double *__restrict__ phk,
+                                                       Tri<float> r32, float *__restrict__ base32,
+                                                       unsigned long long *partial) {
+    const Lay &L = op.lay;
+    const unsigned total = (unsigned)npts(L);
+    unsigned long long m = 0;
+    for (unsigned t = xcd_block() * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock) {
+        int i, j, k;
+        decode(L, t, i, j, k);
+        const Off q = offs(L, i, j, k);
+        double r1, r2, r3;
+        resid_at<double, false>(op, u, f, phk, nullptr, q, r1, r2, r3);
+        r32.a[t] = (float)r1;
+        r32.b[t] = (float)r2;
+        r32.c[t] = (float)r3;
+        base32[t] = (float)u.a[t];
+        m = umax(m, umax(abs_bits(r1), umax(abs_bits(r2), abs_bits(r3))));
+    }
+    m = block_max_u64(m);
+    if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+int launch_resid_cast(hipStream_t s, const OpParams &op, Tri<const double> u, Tri<const double> f,
+                      const double *phk, Tri<float> r32, float *base32,
+                      unsigned long long *partial) {
+    const unsigned blocks = reduce_blocks(npts_host(op.lay));
+    hipLaunchKernelGGL(k_resid_cast, dim3(blocks), dim3(kBlock), 0, s, op, u, f, phk, r32, base32,
+                       partial);
+    return (int)blocks;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(float *p, size_t count) {
+    const size_t t = (size_t)xcd_block() * kBlock + threadIdx.x;
+    if (t < count) p[t] = 0.0f;
+}
+
+void launch_zero(hipStream_t s, float *p, size_t count) {
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(count)), dim3(kBlock), 0, s, p, count);
 }
 
 // ------------------------------------------------------ instantiations
@@ -747,9 +933,9 @@ void launch_energy(hipStream_t s, int n, double h, double eps, const double *phi
 #define PFC_INST(T, DELTA)                                                                        \
     template void launch_smooth<T, DELTA>(hipStream_t, const OpParams &, int, int, Tri<T>,        \
                                           Tri<const T>, const T *, const T *);                    \
-    template void launch_resid_restrict<T, DELTA>(hipStream_t, const OpParams &, Tri<const T>,    \
-                                                  Tri<const T>, const T *, const T *, Tri<T>,     \
-                                                  Tri<T>);                                        \
+    template void launch_resid_restrict<T, DELTA>(hipStream_t, const OpParams &, const Lay &,     \
+                                                  Tri<const T>, Tri<const T>, const T *,          \
+                                                  const T *, Tri<T>, Tri<T>);                     \
     template void launch_tau<T, DELTA>(hipStream_t, const OpParams &, Tri<const T>, Tri<T>,       \
                                        Tri<T>, const T *, const T *);                             \
     template int launch_resid_max<T, DELTA>(hipStream_t, const OpParams &, Tri<const T>,          \
@@ -757,15 +943,18 @@ void launch_energy(hipStream_t s, int n, double h, double eps, const double *phi
                                             unsigned long long *);                                \
     template void launch_coarse<T, DELTA>(hipStream_t, const OpParams &, Tri<T>, Tri<const T>,    \
                                           const T *, const T *, const double *, const double *,   \
-                                          int *);
+                                          double *, int *, int *, int *);
 
 PFC_INST(double, false)
 PFC_INST(float, true)
-template void launch_restrict<double>(hipStream_t, int, const double *, double *);
-template void launch_restrict<float>(hipStream_t, int, const float *, float *);
-template void launch_prolong<double>(hipStream_t, int, Tri<const double>, Tri<const double>,
-                                     Tri<double>);
-template void launch_prolong<float>(hipStream_t, int, Tri<const float>, Tri<const float>,
-                                    Tri<float>);
+template void launch_restrict<double>(hipStream_t, const Lay &, const Lay &, const double *, double *);
+template void launch_restrict<float>(hipStream_t, const Lay &, const Lay &, const float *, float *);
+template void launch_prolong<double>(hipStream_t, const Lay &, const Lay &, Tri<const double>,
+                                     Tri<const double>, Tri<double>);
+template void launch_prolong<float>(hipStream_t, const Lay &, const Lay &, Tri<const float>,
+                                    Tri<const float>, Tri<float>);
+template void launch_to_lay<double, double>(hipStream_t, const Lay &, const double *, double *, int);
+template void launch_from_lay<double, double>(hipStream_t, const Lay &, const double *, double *, int);
+template void launch_to_lay<double, float>(hipStream_t, const Lay &, const double *, float *, int);
 
 }  // namespace pfc

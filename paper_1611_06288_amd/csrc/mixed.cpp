@@ -1,0 +1,137 @@
+// Mixed-precision form of the time step: an FP64 defect correction around
+// FP32 multigrid cycles.
+//
+// Outer loop (FP64, finest level): r = S - N(u) and its max-norm; stop when
+// max|r| <= tol.  Otherwise one FAS cycle in FP32 solves for a correction e
+//     N(u + e) - N(u) = r,
+// whose operator is N's linear part acting on e plus the cubic difference
+//     G(e) = g(b + e; phi^k) - g(b; phi^k)
+//          = 1/4 [e (b^2 + (phi^k)^2) + (b + e + phi^k)(2 b e + e^2)],
+// b = phi of the current FP64 iterate rounded to FP32 (restricted to the
+// coarse levels), written without cancellation.  Then u += e in FP64.  The
+// smoother's pointwise 3x3 solve, the residual and all reductions run in
+// FP64 arithmetic; only stored fields of the correction cycle are FP32.
+#include <cmath>
+
+#include "runtime_internal.h"
+
+namespace pfc {
+
+pfc_status mixed_init(pfc_handle *H) {
+    for (int l = 0; l < H->nlev; ++l) {
+        Level32 &A = H->lev32[l];
+        const size_t P = H->lev[l].P;
+        float *e, *f, *eb;
+        const bool ok = dalloc(H, &e, 3 * P) && dalloc(H, &f, 3 * P) && dalloc(H, &eb, 3 * P) &&
+                        dalloc(H, &A.phk, P) && dalloc(H, &A.base, P);
+        if (!ok) return fail(H, PFC_ERR_OOM, "device allocation for the FP32 hierarchy failed");
+        A.e = Tri<float>{e, e + P, e + 2 * P};
+        A.f = Tri<float>{f, f + P, f + 2 * P};
+        A.ebar = Tri<float>{eb, eb + P, eb + 2 * P};
+    }
+    return PFC_OK;
+}
+
+static void sweep32(pfc_handle *H, int l) {
+    Level32 &A = H->lev32[l];
+    const OpParams op = op_of(H, l);
+    for (int colour = 0; colour < 2; ++colour) {
+        H->begin_timed(PFC_KERNEL_SMOOTH0, l);
+        launch_smooth<float, true>(H->stream, op, colour, 0, A.e, cst(A.f), A.phk, A.base);
+        H->end_timed();
+    }
+}
+
+static void cycle32(pfc_handle *H, int l, bool fcycle) {
+    Level32 &A = H->lev32[l];
+    if (l == H->nlev - 1) {
+        H->begin_timed(PFC_KERNEL_COARSE, l);
+        launch_coarse<float, true>(H->stream, op_of(H, l), A.e, cst(A.f), A.phk, A.base, H->lap1,
+                                   H->lap3, H->minv32, nullptr, H->valid32, H->d_iters);
+        H->end_timed();
+        return;
+    }
+    Level32 &B = H->lev32[l + 1];
+    const Lay &LB = H->lev[l + 1].lay;
+    for (int s = 0; s < H->cfg.nu1; ++s) sweep32(H, l);
+    H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
+    launch_resid_restrict<float, true>(H->stream, op_of(H, l), LB, cst(A.e), cst(A.f), A.phk,
+                                       A.base, B.ebar, B.f);
+    H->end_timed();
+    launch_tau<float, true>(H->stream, op_of(H, l + 1), cst(B.ebar), B.f, B.e, B.phk, B.base);
+    cycle32(H, l + 1, fcycle);
+    if (fcycle) cycle32(H, l + 1, false);
+    H->begin_timed(PFC_KERNEL_PROLONG0, l);
+    launch_prolong<float>(H->stream, LB, H->lev[l].lay, cst(B.e), cst(B.ebar), A.e);
+    H->end_timed();
+    for (int s = 0; s < H->cfg.nu2; ++s) sweep32(H, l);
+}
+
+pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_cur,
+                      double *phi_next, double *mu, double *omega, pfc_step_info *info) {
+    Level &A = H->lev[0];
+    Level32 &A32 = H->lev32[0];
+    step_begin(H, phi_prev, phi_cur, mu, omega);
+    launch_to_lay<double, float>(H->stream, A.lay, phi_cur, A32.phk, 1);
+    for (int l = 0; l + 1 < H->nlev; ++l)
+        launch_restrict<float>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev32[l].phk,
+                               H->lev32[l + 1].phk);
+    HIP_TRY(H, hipGetLastError());
+    int c = 0;
+    double rho = 0, rho0 = 0;
+    pfc_status status = PFC_OK;
+    for (;;) {
+        H->begin_timed(PFC_KERNEL_NORM0, 0);
+        const int cnt = launch_resid_cast(H->stream, op_of(H, 0), cst(A.u), cst(A.f), A.phk, A32.f,
+                                          A32.base, H->partial);
+        H->end_timed();
+        const pfc_status st = read_norm(H, cnt, &rho);
+        if (st != PFC_OK) return st;
+        if (c == 0) rho0 = rho;
+        if (!std::isfinite(rho)) {
+            status = PFC_ERR_NONFINITE;
+            break;
+        }
+        if (rho <= H->cfg.tol) break;
+        if (c == H->cfg.max_cycles) {
+            status = PFC_ERR_NOT_CONVERGED;
+            break;
+        }
+        for (int l = 0; l + 1 < H->nlev; ++l)
+            launch_restrict<float>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev32[l].base,
+                                   H->lev32[l + 1].base);
+        launch_zero(H->stream, A32.e.a, 3 * A.P);
+        cycle32(H, 0, H->cfg.cycle == PFC_CYCLE_F);
+        launch_add_correction(H->stream, A.P, A.u, cst(A32.e));
+        ++c;
+    }
+    step_end(H, phi_next, mu, omega);
+    HIP_TRY(H, hipGetLastError());
+    HIP_TRY(H, hipStreamSynchronize(H->stream));
+    if (info) {
+        info->cycles = c;
+        info->status = status;
+        info->res0 = rho0;
+        info->res_final = rho;
+    }
+    if (status != PFC_OK) fail(H, status, pfc_status_string(status));
+    return status;
+}
+
+// Algorithmic HBM bytes per finest-level launch.  A full red-black sweep must
+// read u (3 fields), f (3) and phi^k (1) and write u (3): 80 B per point in
+// FP64; the FP32 correction sweep also reads the base b: 11 values of 4 B =
+// 44 B.  Each half-sweep launch is credited half a sweep.
+double algorithmic_bytes(const pfc_handle *H, int kernel) {
+    const double P = (double)H->lev[0].P;
+    const bool mixed = H->cfg.precision == PFC_MIXED;
+    switch (kernel) {
+        case PFC_KERNEL_SMOOTH0: return (mixed ? 22.0 : 40.0) * P;
+        case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0) * P;
+        case PFC_KERNEL_PROLONG0: return (mixed ? 27.0 : 54.0) * P;
+        case PFC_KERNEL_NORM0: return (mixed ? 72.0 : 56.0) * P;
+        default: return 0.0;
+    }
+}
+
+}  // namespace pfc

@@ -1,5 +1,5 @@
 // Internal interface between the HIP kernels (kernels.hip) and the host
-// runtime (runtime.cpp).  Not part of the public C ABI.
+// runtime.  Not part of the public C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,56 +19,109 @@ struct Tri {
 template <typename T>
 inline Tri<const T> cst(Tri<T> t) { return Tri<const T>{t.a, t.b, t.c}; }
 
+// Division by n = 2^s or 3*2^s without integer divide instructions.
+struct Div {
+    unsigned shift;  // s
+    unsigned three;  // 1 if n = 3*2^s
+    __host__ __device__ unsigned q(unsigned x) const {
+        x >>= shift;
+        return three ? (unsigned)(((unsigned long long)x * 0xAAAAAAABull) >> 33) : x;
+    }
+};
+
+Div make_div(int d);  // host: d must be 2^s or 3*2^s
+
+// Storage of one level's fields.  Natural: C order [k][j][i].  Colour-split
+// (n even): the points of colour c = (i+j+k) mod 2 are stored in block c of
+// size n^3/2, row (k, j) by row, a point at position i >> 1 of its row.
+struct Lay {
+    int n;
+    int split;
+    Div dn;   // division by n
+    Div dh;   // division by n/2 (split only)
+};
+
+Lay make_lay(int n, bool split);
+
+inline size_t npts_host(const Lay &L) { return (size_t)L.n * L.n * L.n; }
+
 // Scalar parameters of one level's operator.
 struct OpParams {
-    int n;         // cells per axis on this level
+    Lay lay;
     double h2inv;  // 1 / h_l^2
     double tau;    // time step
     double eps;    // epsilon
 };
 
 constexpr int kBlock = 256;
+constexpr int kMaxReduceBlocks = 2048;
+constexpr int kMaxN = 1024;
 
-// ---- FP64 / FP32 building blocks (T = double or float; DELTA selects the
-// correction form g(base + e) - g(base) of the cubic term) ----
+// ---- building blocks; T = double or float, DELTA selects the correction
+// form g(base + e) - g(base) of the cubic term ----
 template <typename T, bool DELTA>
 void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
                    Tri<const T> f, const T *phk, const T *base);
 
 template <typename T, bool DELTA>
-void launch_resid_restrict(hipStream_t s, const OpParams &op, Tri<const T> u, Tri<const T> f,
-                           const T *phk, const T *base, Tri<T> ubar_c, Tri<T> rr_c);
+void launch_resid_restrict(hipStream_t s, const OpParams &op, const Lay &coarse, Tri<const T> u,
+                           Tri<const T> f, const T *phk, const T *base, Tri<T> ubar_c, Tri<T> rr_c);
 
 template <typename T>
-void launch_restrict(hipStream_t s, int nf, const T *fine, T *coarse);
+void launch_restrict(hipStream_t s, const Lay &fine, const Lay &coarse, const T *fine_v, T *coarse_v);
 
 template <typename T, bool DELTA>
 void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                 const T *phk, const T *base);
 
+// fine += P (v - ubar); ubar.a may be null; fine.b null: one field only.
 template <typename T>
-void launch_prolong(hipStream_t s, int nc, Tri<const T> v, Tri<const T> ubar, Tri<T> fine);
+void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
+                    Tri<const T> ubar, Tri<T> fine_u);
 
-// Residual r = f - N(u) (r may have null members) and per-block maxima of |r|
-// as IEEE bit patterns; returns the number of partials written.
+// Residual r = f - N(u) (r.a may be null) and per-block maxima of |r| as
+// IEEE bit patterns; returns the number of partials written.
 template <typename T, bool DELTA>
 int launch_resid_max(hipStream_t s, const OpParams &op, Tri<const T> u, Tri<const T> f,
                      const T *phk, const T *base, Tri<T> r, unsigned long long *partial);
 
 void launch_max_final(hipStream_t s, const unsigned long long *partial, int count, double *out);
 
+// Coarsest level (natural layout, n = 3 or 4).  lu/piv: cached factorisation
+// of the Newton matrix (device scratch of 64*64 doubles and 64 ints), reused
+// across calls while *lu_valid is set.
 template <typename T, bool DELTA>
 void launch_coarse(hipStream_t s, const OpParams &op, Tri<T> u, Tri<const T> f, const T *phk,
-                   const T *base, const double *lap1, const double *lap3, int *iters);
+                   const T *base, const double *lap1, const double *lap3, double *lu, int *piv,
+                   int *lu_valid, int *iters);
 
+// Finest-level source from natural-layout phi^k, phi^{k-1} into layout `op.lay`.
 void launch_source(hipStream_t s, const OpParams &op, const double *phk, const double *phkm1,
                    Tri<double> f);
-void launch_init_guess(hipStream_t s, const OpParams &op, const double *phi0, double *mu,
+void launch_init_guess(hipStream_t s, const OpParams &nat, const double *phi0, double *mu,
                        double *om);
 
-// Energy: per-block partial sums (6 per block) then a fixed-order final sum.
+// Layout conversion of `count` consecutive fields between natural and `lay`
+// (with a type cast).
+template <typename S, typename D>
+void launch_to_lay(hipStream_t s, const Lay &lay, const S *src, D *dst, int count);
+template <typename S, typename D>
+void launch_from_lay(hipStream_t s, const Lay &lay, const S *src, D *dst, int count);
+
+// Energy on natural-layout fields: per-block sums, then a fixed-order final sum.
 int energy_blocks(int n);
-void launch_energy(hipStream_t s, int n, double h, double eps, const double *phi,
+void launch_energy(hipStream_t s, const Lay &nat, double h, double eps, const double *phi,
                    const double *phi_prev, double *partial, double *out3);
+
+// ---- mixed-precision helpers (FP64 finest level, FP32 correction) ----
+// u64 += e32 on three fields (same layout, n points each).
+void launch_add_correction(hipStream_t s, size_t P, Tri<double> u, Tri<const float> e);
+// r = f - N(u) in FP64, per-block max-norm partials, and FP32 copies of r and
+// of u.a (the base of the correction cycle).
+int launch_resid_cast(hipStream_t s, const OpParams &op, Tri<const double> u, Tri<const double> f,
+                      const double *phk, Tri<float> r32, float *base32,
+                      unsigned long long *partial);
+// Fills `count` floats with zero.
+void launch_zero(hipStream_t s, float *p, size_t count);
 
 }  // namespace pfc

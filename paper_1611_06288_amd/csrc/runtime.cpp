@@ -1,13 +1,15 @@
-// Host runtime of the PFC multigrid solver: handle, level hierarchy, cycle
-// driver, time step, instrumentation and the C ABI of include/pfc.h.
+// Host runtime of the PFC multigrid solver: handle, level hierarchy, FP64
+// cycle driver, time step, instrumentation and the C ABI of include/pfc.h.
 //
 // Algorithm (Section 5, Algorithm algorithm:FAS, with these readings): the
 // loop "while residual > tolerance" runs at the finest level only and tests
 // max|S - N(u)| over the three components before each cycle; a recursive call
 // performs one cycle; the coarse right-hand side is N_{l+1}(I u) + I r; the
 // coarse correction is I(v - I u); red-black colour (i+j+k) mod 2, colour 0
-// first in every sweep; the coarsest level (n = 3 or 4) is solved by Newton's
-// method.
+// first in every sweep; the coarsest level (n = 3 or 4) is solved exactly.
+//
+// The caller's fields are in natural C order; inside a call the finest level
+// works on colour-split copies (converted once per step or call).
 #include "pfc.h"
 
 #include <hip/hip_runtime.h>
@@ -31,7 +33,7 @@ namespace pfc {
 
 bool level_sizes(int n, std::vector<int> &out) {
     out.clear();
-    if (n < 4 || (n & 1)) return false;
+    if (n < 4 || (n & 1) || n > kMaxN) return false;
     int m = n;
     out.push_back(m);
     while ((m & 1) == 0 && m / 2 >= 3) {
@@ -45,7 +47,7 @@ std::string validate_config(const pfc_config *c) {
     if (!c) return "config is NULL";
     std::vector<int> sizes;
     if (!level_sizes(c->n, sizes))
-        return "n must be 2^k (k >= 2) or 3*2^k (k >= 1), got " + std::to_string(c->n);
+        return "n must be 2^k (k >= 2) or 3*2^k (k >= 1), at most 1024, got " + std::to_string(c->n);
     if (!(c->L > 0) || !std::isfinite(c->L)) return "L must be > 0";
     if (!(c->dt > 0) || !std::isfinite(c->dt)) return "dt must be > 0";
     if (!(c->tol >= 0) || !std::isfinite(c->tol)) return "tol must be >= 0";
@@ -103,11 +105,7 @@ void coarse_matrices(int n, double h, std::vector<double> &l1, std::vector<doubl
         }
 }
 
-}  // namespace pfc
-
-// ------------------------------------------------------------- handle
-
-static pfc_status fail(pfc_handle *H, pfc_status st, const std::string &msg) {
+pfc_status fail(pfc_handle *H, pfc_status st, const std::string &msg) {
     if (H)
         H->err = msg;
     else
@@ -115,28 +113,20 @@ static pfc_status fail(pfc_handle *H, pfc_status st, const std::string &msg) {
     return st;
 }
 
-static pfc_status hip_fail(pfc_handle *H, hipError_t e, const char *what) {
+pfc_status hip_fail(pfc_handle *H, hipError_t e, const char *what) {
     return fail(H, PFC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(H, expr)                                            \
-    do {                                                            \
-        hipError_t e_ = (expr);                                     \
-        if (e_ != hipSuccess) return hip_fail((H), e_, #expr);      \
-    } while (0)
-
-template <typename T>
-static bool dalloc(pfc_handle *H, T **p, size_t count) {
-    void *q = nullptr;
-    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return false;
-    H->allocs.push_back(q);
-    *p = (T *)q;
-    return true;
+OpParams op_of(const pfc_handle *H, int l) {
+    return OpParams{H->lev[l].lay, H->lev[l].h2inv, H->cfg.dt, H->cfg.eps};
 }
 
-static pfc::OpParams op_of(const pfc_handle *H, int l) {
-    return pfc::OpParams{H->lev[l].n, H->lev[l].h2inv, H->cfg.dt, H->cfg.eps};
+void invalidate_coarse(pfc_handle *H) {
+    (void)hipMemsetAsync(H->valid64, 0, sizeof(int), H->stream);
+    (void)hipMemsetAsync(H->valid32, 0, sizeof(int), H->stream);
 }
+
+}  // namespace pfc
 
 // ------------------------------------------------------------ timing
 
@@ -197,7 +187,7 @@ namespace pfc {
 
 static void sweep64(pfc_handle *H, int l) {
     Level &A = H->lev[l];
-    const pfc::OpParams op = op_of(H, l);
+    const OpParams op = op_of(H, l);
     for (int colour = 0; colour < 2; ++colour) {
         H->begin_timed(PFC_KERNEL_SMOOTH0, l);
         launch_smooth<double, false>(H->stream, op, colour, H->cfg.lin == PFC_LIN_PICARD, A.u,
@@ -211,38 +201,33 @@ void cycle64(pfc_handle *H, int l, bool fcycle) {
     if (l == H->nlev - 1) {
         H->begin_timed(PFC_KERNEL_COARSE, l);
         launch_coarse<double, false>(H->stream, op_of(H, l), A.u, cst(A.f), A.phk, nullptr,
-                                     H->lap1, H->lap3, H->d_iters);
+                                     H->lap1, H->lap3, H->minv64, nullptr, H->valid64, H->d_iters);
         H->end_timed();
         return;
     }
     Level &B = H->lev[l + 1];
     for (int s = 0; s < H->cfg.nu1; ++s) sweep64(H, l);
     H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
-    launch_resid_restrict<double, false>(H->stream, op_of(H, l), cst(A.u), cst(A.f), A.phk,
+    launch_resid_restrict<double, false>(H->stream, op_of(H, l), B.lay, cst(A.u), cst(A.f), A.phk,
                                          nullptr, B.ubar, B.f);
     H->end_timed();
     launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f, B.u, B.phk, nullptr);
     cycle64(H, l + 1, fcycle);
     if (fcycle) cycle64(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
-    launch_prolong<double>(H->stream, B.n, cst(B.u), cst(B.ubar), A.u);
+    launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u);
     H->end_timed();
     for (int s = 0; s < H->cfg.nu2; ++s) sweep64(H, l);
 }
 
 void restrict_phk(pfc_handle *H) {
     for (int l = 0; l + 1 < H->nlev; ++l)
-        launch_restrict<double>(H->stream, H->lev[l].n, H->lev[l].phk, H->lev[l + 1].phk);
+        launch_restrict<double>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev[l].phk,
+                                H->lev[l + 1].phk);
 }
 
-// Residual max-norm at the finest level (r.a may be null).  Synchronises.
-pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out) {
-    Level &A = H->lev[0];
-    H->begin_timed(PFC_KERNEL_NORM0, 0);
-    const int cnt = launch_resid_max<double, false>(H->stream, op_of(H, 0), cst(A.u), cst(A.f),
-                                                    A.phk, nullptr, r, H->partial);
-    H->end_timed();
-    launch_max_final(H->stream, H->partial, cnt, H->d_scal);
+pfc_status read_norm(pfc_handle *H, int partials, double *out) {
+    launch_max_final(H->stream, H->partial, partials, H->d_scal);
     HIP_TRY(H, hipGetLastError());
     HIP_TRY(H, hipMemcpyAsync(H->h_pin, H->d_scal, sizeof(double), hipMemcpyDeviceToHost,
                               H->stream));
@@ -252,6 +237,47 @@ pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out) {
     return PFC_OK;
 }
 
+// Residual max-norm at the finest level (r.a may be null).  Synchronises.
+pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out) {
+    Level &A = H->lev[0];
+    H->begin_timed(PFC_KERNEL_NORM0, 0);
+    const int cnt = launch_resid_max<double, false>(H->stream, op_of(H, 0), cst(A.u), cst(A.f),
+                                                    A.phk, nullptr, r, H->partial);
+    H->end_timed();
+    return read_norm(H, cnt, out);
+}
+
+}  // namespace pfc
+
+// ----------------------------------------------------- layout helpers
+
+static void to_level0(pfc_handle *H, const double *phi, const double *mu, const double *om) {
+    Level &A = H->lev[0];
+    launch_to_lay<double, double>(H->stream, A.lay, phi, A.u.a, 1);
+    launch_to_lay<double, double>(H->stream, A.lay, mu, A.u.b, 1);
+    launch_to_lay<double, double>(H->stream, A.lay, om, A.u.c, 1);
+}
+
+static void from_level0(pfc_handle *H, double *phi, double *mu, double *om) {
+    Level &A = H->lev[0];
+    launch_from_lay<double, double>(H->stream, A.lay, A.u.a, phi, 1);
+    launch_from_lay<double, double>(H->stream, A.lay, A.u.b, mu, 1);
+    launch_from_lay<double, double>(H->stream, A.lay, A.u.c, om, 1);
+}
+
+namespace pfc {
+void step_begin(pfc_handle *H, const double *phi_prev, const double *phi_cur, const double *mu,
+                const double *omega) {
+    Level &A = H->lev[0];
+    invalidate_coarse(H);
+    launch_source(H->stream, op_of(H, 0), phi_cur, phi_prev, A.f);
+    to_level0(H, phi_cur, mu, omega);
+    launch_to_lay<double, double>(H->stream, A.lay, phi_cur, A.phk, 1);
+    restrict_phk(H);
+}
+void step_end(pfc_handle *H, double *phi_next, double *mu, double *omega) {
+    from_level0(H, phi_next, mu, omega);
+}
 }  // namespace pfc
 
 // ------------------------------------------------------------- C ABI
@@ -290,33 +316,32 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
     level_sizes(cfg->n, sizes);
     H->nlev = (int)sizes.size();
     bool ok = true;
-    for (int l = 0; l < H->nlev; ++l) {
+    for (int l = 0; l < H->nlev && ok; ++l) {
         Level &A = H->lev[l];
         A.n = sizes[l];
         A.h = cfg->L / A.n;
         A.h2inv = 1.0 / (A.h * A.h);
         A.P = (size_t)A.n * A.n * A.n;
-        if (l == 0) continue;  // finest level buffers are bound per call
+        A.lay = make_lay(A.n, l < H->nlev - 1);
         double *u, *f, *ub;
-        ok = ok && dalloc(H, &u, 3 * A.P) && dalloc(H, &f, 3 * A.P) && dalloc(H, &ub, 3 * A.P) &&
+        ok = dalloc(H, &u, 3 * A.P) && dalloc(H, &f, 3 * A.P) && dalloc(H, &ub, 3 * A.P) &&
              dalloc(H, &A.phk, A.P);
         if (!ok) break;
         A.u = Tri<double>{u, u + A.P, u + 2 * A.P};
         A.f = Tri<double>{f, f + A.P, f + 2 * A.P};
         A.ubar = Tri<double>{ub, ub + A.P, ub + 2 * A.P};
     }
-    const size_t P0 = H->lev[0].P;
-    double *f0 = nullptr;
-    ok = ok && dalloc(H, &f0, 3 * P0);
-    if (ok) H->f0 = Tri<double>{f0, f0 + P0, f0 + 2 * P0};
-    ok = ok && dalloc(H, &H->partial, (P0 + kBlock - 1) / kBlock + 16);
+    ok = ok && dalloc(H, &H->partial, (size_t)kMaxReduceBlocks + 16);
     ok = ok && dalloc(H, &H->d_scal, 16) && dalloc(H, &H->d_iters, 4);
-    ok = ok && dalloc(H, &H->energy_part, (size_t)6 * pfc::energy_blocks(cfg->n) + 16);
-    // coarsest-level matrices
-    const Level &C = H->lev[H->nlev - 1];
+    ok = ok && dalloc(H, &H->energy_part, (size_t)6 * kMaxReduceBlocks + 16);
+    ok = ok && dalloc(H, &H->minv64, 64 * 64) && dalloc(H, &H->minv32, 64 * 64) &&
+         dalloc(H, &H->valid64, 4) && dalloc(H, &H->valid32, 4);
     std::vector<double> l1, l3;
-    pfc::coarse_matrices(C.n, C.h, l1, l3);
-    ok = ok && dalloc(H, &H->lap1, l1.size()) && dalloc(H, &H->lap3, l3.size());
+    if (ok) {
+        const Level &C = H->lev[H->nlev - 1];
+        coarse_matrices(C.n, C.h, l1, l3);
+        ok = dalloc(H, &H->lap1, l1.size()) && dalloc(H, &H->lap3, l3.size());
+    }
     if (ok && hipHostMalloc((void **)&H->h_pin, 64 * sizeof(double), 0) != hipSuccess) {
         H->h_pin = nullptr;
         ok = false;
@@ -328,12 +353,14 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
     if (hipMemcpy(H->lap1, l1.data(), l1.size() * sizeof(double), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(H->lap3, l3.data(), l3.size() * sizeof(double), hipMemcpyHostToDevice) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipMemset(H->valid64, 0, sizeof(int)) != hipSuccess ||
+        hipMemset(H->valid32, 0, sizeof(int)) != hipSuccess) {
         delete H;
-        return fail(nullptr, PFC_ERR_HIP, "upload of coarse matrices failed");
+        return fail(nullptr, PFC_ERR_HIP, "initialisation of coarse-level data failed");
     }
     if (cfg->precision == PFC_MIXED) {
-        const pfc_status st = pfc::mixed_init(H);
+        const pfc_status st = mixed_init(H);
         if (st != PFC_OK) {
             g_create_error = H->err;
             delete H;
@@ -367,7 +394,9 @@ int32_t pfc_level_size(const pfc_handle *h, int32_t level) {
 pfc_status pfc_init_guess(pfc_handle *h, const double *phi0, double *mu, double *omega) {
     if (!h) return PFC_ERR_INVALID_ARG;
     if (!phi0 || !mu || !omega) return fail(h, PFC_ERR_INVALID_ARG, "NULL field pointer");
-    launch_init_guess(h->stream, op_of(h, 0), phi0, mu, omega);
+    OpParams nat = op_of(h, 0);
+    nat.lay = make_lay(h->lev[0].n, false);
+    launch_init_guess(h->stream, nat, phi0, mu, omega);
     HIP_TRY(h, hipGetLastError());
     return PFC_OK;
 }
@@ -380,15 +409,8 @@ pfc_status pfc_step(pfc_handle *h, const double *phi_prev, const double *phi_cur
     if (phi_next == phi_cur || phi_next == phi_prev)
         return fail(h, PFC_ERR_INVALID_ARG, "phi_next aliases an input");
     if (h->cfg.precision == PFC_MIXED)
-        return pfc::mixed_step(h, phi_prev, phi_cur, phi_next, mu, omega, info);
-    Level &A = h->lev[0];
-    HIP_TRY(h, hipMemcpyAsync(phi_next, phi_cur, A.P * sizeof(double), hipMemcpyDeviceToDevice,
-                              h->stream));
-    launch_source(h->stream, op_of(h, 0), phi_cur, phi_prev, h->f0);
-    A.u = Tri<double>{phi_next, mu, omega};
-    A.f = h->f0;
-    A.phk = const_cast<double *>(phi_cur);
-    restrict_phk(h);
+        return mixed_step(h, phi_prev, phi_cur, phi_next, mu, omega, info);
+    step_begin(h, phi_prev, phi_cur, mu, omega);
     HIP_TRY(h, hipGetLastError());
     int c = 0;
     double rho = 0, rho0 = 0;
@@ -409,6 +431,9 @@ pfc_status pfc_step(pfc_handle *h, const double *phi_prev, const double *phi_cur
         cycle64(h, 0, h->cfg.cycle == PFC_CYCLE_F);
         ++c;
     }
+    step_end(h, phi_next, mu, omega);
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     if (info) {
         info->cycles = c;
         info->status = status;
@@ -424,13 +449,12 @@ pfc_status pfc_fas_vcycle(pfc_handle *h, double *u3, const double *f3, const dou
     if (!h) return PFC_ERR_INVALID_ARG;
     if (!u3 || !f3 || !phi_cur) return fail(h, PFC_ERR_INVALID_ARG, "NULL field pointer");
     Level &A = h->lev[0];
-    const size_t P = A.P;
-    A.u = Tri<double>{u3, u3 + P, u3 + 2 * P};
-    double *f = const_cast<double *>(f3);
-    A.f = Tri<double>{f, f + P, f + 2 * P};
-    A.phk = const_cast<double *>(phi_cur);
+    launch_to_lay<double, double>(h->stream, A.lay, u3, A.u.a, 3);
+    launch_to_lay<double, double>(h->stream, A.lay, f3, A.f.a, 3);
+    launch_to_lay<double, double>(h->stream, A.lay, phi_cur, A.phk, 1);
     restrict_phk(h);
     cycle64(h, 0, h->cfg.cycle == PFC_CYCLE_F);
+    launch_from_lay<double, double>(h->stream, A.lay, A.u.a, u3, 3);
     HIP_TRY(h, hipGetLastError());
     if (res_after) {
         const pfc_status st = resid_norm64(h, Tri<double>{nullptr, nullptr, nullptr}, res_after);
@@ -443,7 +467,8 @@ pfc_status pfc_energy(pfc_handle *h, const double *phi, const double *phi_prev, 
     if (!h) return PFC_ERR_INVALID_ARG;
     if (!phi || !out) return fail(h, PFC_ERR_INVALID_ARG, "NULL pointer");
     const Level &A = h->lev[0];
-    launch_energy(h->stream, A.n, A.h, h->cfg.eps, phi, phi_prev, h->energy_part, h->d_scal);
+    launch_energy(h->stream, make_lay(A.n, false), A.h, h->cfg.eps, phi, phi_prev, h->energy_part,
+                  h->d_scal);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipMemcpyAsync(h->h_pin, h->d_scal, 3 * sizeof(double), hipMemcpyDeviceToHost,
                               h->stream));
@@ -455,14 +480,19 @@ pfc_status pfc_energy(pfc_handle *h, const double *phi, const double *phi_prev, 
 }
 
 // ---------------------------------------------- kernel-level entry points
+// Inputs arrive in natural order; they are converted into the level's own
+// buffers (its storage layout), the kernel runs there, and outputs are
+// converted back.
 
 static bool level_ok(const pfc_handle *h, int level) { return level >= 0 && level < h->nlev; }
 
 pfc_status pfc_source(pfc_handle *h, const double *phi_prev, const double *phi_cur, double *f3) {
     if (!h) return PFC_ERR_INVALID_ARG;
     if (!phi_prev || !phi_cur || !f3) return fail(h, PFC_ERR_INVALID_ARG, "NULL pointer");
+    OpParams nat = op_of(h, 0);
+    nat.lay = make_lay(h->lev[0].n, false);
     const size_t P = h->lev[0].P;
-    launch_source(h->stream, op_of(h, 0), phi_cur, phi_prev, Tri<double>{f3, f3 + P, f3 + 2 * P});
+    launch_source(h->stream, nat, phi_cur, phi_prev, Tri<double>{f3, f3 + P, f3 + 2 * P});
     HIP_TRY(h, hipGetLastError());
     return PFC_OK;
 }
@@ -471,20 +501,20 @@ pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const do
                         const double *phk, double *r3, double *maxnorm) {
     if (!h) return PFC_ERR_INVALID_ARG;
     if (!level_ok(h, level) || !u3 || !f3 || !phk) return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
-    const size_t P = h->lev[level].P;
-    Tri<const double> u{u3, u3 + P, u3 + 2 * P}, f{f3, f3 + P, f3 + 2 * P};
+    Level &A = h->lev[level];
+    launch_to_lay<double, double>(h->stream, A.lay, u3, A.u.a, 3);
+    launch_to_lay<double, double>(h->stream, A.lay, f3, A.f.a, 3);
+    launch_to_lay<double, double>(h->stream, A.lay, phk, A.phk, 1);
     Tri<double> r{nullptr, nullptr, nullptr};
-    if (r3) r = Tri<double>{r3, r3 + P, r3 + 2 * P};
-    const int cnt = launch_resid_max<double, false>(h->stream, op_of(h, level), u, f, phk, nullptr,
-                                                    r, h->partial);
-    launch_max_final(h->stream, h->partial, cnt, h->d_scal);
+    if (r3) r = A.ubar;
+    const int cnt = launch_resid_max<double, false>(h->stream, op_of(h, level), cst(A.u), cst(A.f),
+                                                    A.phk, nullptr, r, h->partial);
+    if (r3) launch_from_lay<double, double>(h->stream, A.lay, A.ubar.a, r3, 3);
     HIP_TRY(h, hipGetLastError());
-    if (maxnorm) {
-        HIP_TRY(h, hipMemcpyAsync(h->h_pin, h->d_scal, sizeof(double), hipMemcpyDeviceToHost,
-                                  h->stream));
-        HIP_TRY(h, hipStreamSynchronize(h->stream));
-        *maxnorm = h->h_pin[0];
-    }
+    double m = 0;
+    const pfc_status st = read_norm(h, cnt, &m);
+    if (st != PFC_OK) return st;
+    if (maxnorm) *maxnorm = m;
     return PFC_OK;
 }
 
@@ -492,12 +522,15 @@ pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3, 
                       const double *phk) {
     if (!h) return PFC_ERR_INVALID_ARG;
     if (!level_ok(h, level) || (colour != 0 && colour != 1) || !u3 || !f3 || !phk ||
-        (h->lev[level].n & 1))
-        return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
-    const size_t P = h->lev[level].P;
+        !h->lev[level].lay.split)
+        return fail(h, PFC_ERR_INVALID_ARG, "bad argument (level must be a smoothed level)");
+    Level &A = h->lev[level];
+    launch_to_lay<double, double>(h->stream, A.lay, u3, A.u.a, 3);
+    launch_to_lay<double, double>(h->stream, A.lay, f3, A.f.a, 3);
+    launch_to_lay<double, double>(h->stream, A.lay, phk, A.phk, 1);
     launch_smooth<double, false>(h->stream, op_of(h, level), colour,
-                                 h->cfg.lin == PFC_LIN_PICARD, Tri<double>{u3, u3 + P, u3 + 2 * P},
-                                 Tri<const double>{f3, f3 + P, f3 + 2 * P}, phk, nullptr);
+                                 h->cfg.lin == PFC_LIN_PICARD, A.u, cst(A.f), A.phk, nullptr);
+    launch_from_lay<double, double>(h->stream, A.lay, A.u.a, u3, 3);
     HIP_TRY(h, hipGetLastError());
     return PFC_OK;
 }
@@ -505,11 +538,13 @@ pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3, 
 pfc_status pfc_restrict(pfc_handle *h, int32_t level, const double *fine, double *coarse,
                         int32_t ncomp) {
     if (!h) return PFC_ERR_INVALID_ARG;
-    if (!level_ok(h, level) || level + 1 >= h->nlev || !fine || !coarse || ncomp < 1)
+    if (!level_ok(h, level) || level + 1 >= h->nlev || !fine || !coarse || ncomp < 1 || ncomp > 3)
         return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
-    const size_t Pf = h->lev[level].P, Pc = h->lev[level + 1].P;
+    Level &A = h->lev[level], &B = h->lev[level + 1];
+    launch_to_lay<double, double>(h->stream, A.lay, fine, A.u.a, ncomp);
     for (int c = 0; c < ncomp; ++c)
-        launch_restrict<double>(h->stream, h->lev[level].n, fine + c * Pf, coarse + c * Pc);
+        launch_restrict<double>(h->stream, A.lay, B.lay, A.u.a + c * A.P, B.u.a + c * B.P);
+    launch_from_lay<double, double>(h->stream, B.lay, B.u.a, coarse, ncomp);
     HIP_TRY(h, hipGetLastError());
     return PFC_OK;
 }
@@ -520,18 +555,20 @@ pfc_status pfc_prolong_add(pfc_handle *h, int32_t level, const double *coarse_v,
     if (!level_ok(h, level) || level + 1 >= h->nlev || !coarse_v || !fine ||
         (ncomp != 1 && ncomp != 3))
         return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
-    const size_t Pf = h->lev[level].P, Pc = h->lev[level + 1].P;
-    const int nc = h->lev[level + 1].n;
+    Level &A = h->lev[level], &B = h->lev[level + 1];
+    launch_to_lay<double, double>(h->stream, B.lay, coarse_v, B.u.a, ncomp);
+    if (coarse_ubar) launch_to_lay<double, double>(h->stream, B.lay, coarse_ubar, B.ubar.a, ncomp);
+    launch_to_lay<double, double>(h->stream, A.lay, fine, A.u.a, ncomp);
+    const Tri<const double> none{nullptr, nullptr, nullptr};
     if (ncomp == 3) {
-        Tri<const double> ub{nullptr, nullptr, nullptr};
-        if (coarse_ubar) ub = Tri<const double>{coarse_ubar, coarse_ubar + Pc, coarse_ubar + 2 * Pc};
-        launch_prolong<double>(h->stream, nc, Tri<const double>{coarse_v, coarse_v + Pc, coarse_v + 2 * Pc},
-                               ub, Tri<double>{fine, fine + Pf, fine + 2 * Pf});
+        launch_prolong<double>(h->stream, B.lay, A.lay, cst(B.u), coarse_ubar ? cst(B.ubar) : none,
+                               A.u);
     } else {
-        launch_prolong<double>(h->stream, nc, Tri<const double>{coarse_v, nullptr, nullptr},
-                               Tri<const double>{coarse_ubar, nullptr, nullptr},
-                               Tri<double>{fine, nullptr, nullptr});
+        launch_prolong<double>(h->stream, B.lay, A.lay, Tri<const double>{B.u.a, nullptr, nullptr},
+                               Tri<const double>{coarse_ubar ? B.ubar.a : nullptr, nullptr, nullptr},
+                               Tri<double>{A.u.a, nullptr, nullptr});
     }
+    launch_from_lay<double, double>(h->stream, A.lay, A.u.a, fine, ncomp);
     HIP_TRY(h, hipGetLastError());
     return PFC_OK;
 }
@@ -542,9 +579,10 @@ pfc_status pfc_coarse_solve(pfc_handle *h, double *u3, const double *f3, const d
     if (!u3 || !f3 || !phk) return fail(h, PFC_ERR_INVALID_ARG, "NULL pointer");
     const int l = h->nlev - 1;
     const size_t P = h->lev[l].P;
+    invalidate_coarse(h);
     launch_coarse<double, false>(h->stream, op_of(h, l), Tri<double>{u3, u3 + P, u3 + 2 * P},
                                  Tri<const double>{f3, f3 + P, f3 + 2 * P}, phk, nullptr, h->lap1,
-                                 h->lap3, h->d_iters);
+                                 h->lap3, h->minv64, nullptr, h->valid64, h->d_iters);
     HIP_TRY(h, hipGetLastError());
     if (iters) {
         HIP_TRY(h, hipMemcpyAsync(h->h_pin, h->d_iters, sizeof(int), hipMemcpyDeviceToHost,
@@ -581,7 +619,7 @@ pfc_status pfc_timing_get(pfc_handle *h, int32_t kernel, int64_t *launches, doub
     h->collect_timings();
     if (launches) *launches = h->t_count[kernel];
     if (total_ms) *total_ms = h->t_ms[kernel];
-    if (bytes_per_launch) *bytes_per_launch = pfc::algorithmic_bytes(h, kernel);
+    if (bytes_per_launch) *bytes_per_launch = algorithmic_bytes(h, kernel);
     return PFC_OK;
 }
 

@@ -13,15 +13,16 @@ namespace pfc {
 
 constexpr int kMaxLevels = 24;
 
-// One level of the multigrid hierarchy (FP64 storage).  Level 0 binds the
-// caller's buffers per call; coarser levels own theirs.
+// One level of the FP64 multigrid hierarchy.  Smoothed levels are stored
+// colour-split, the coarsest level in natural order.
 struct Level {
     int n = 0;
     double h = 0, h2inv = 0;
     size_t P = 0;
+    Lay lay{};
     Tri<double> u{nullptr, nullptr, nullptr};     // iterate
     Tri<double> f{nullptr, nullptr, nullptr};     // right-hand side
-    Tri<double> ubar{nullptr, nullptr, nullptr};  // restricted fine iterate I u
+    Tri<double> ubar{nullptr, nullptr, nullptr};  // restricted fine iterate I u (scratch on level 0)
     double *phk = nullptr;                        // phi^kappa on this level
 };
 
@@ -31,7 +32,7 @@ struct Level32 {
     Tri<float> f{nullptr, nullptr, nullptr};     // right-hand side
     Tri<float> ebar{nullptr, nullptr, nullptr};  // restricted fine correction
     float *phk = nullptr;                        // phi^kappa
-    float *base = nullptr;                       // FP64 iterate's phi, rounded/restricted
+    float *base = nullptr;                       // FP64 iterate's phi, rounded and restricted
 };
 
 struct TimedLaunch {
@@ -53,13 +54,13 @@ struct pfc_handle {
     pfc::Level lev[pfc::kMaxLevels];
     pfc::Level32 lev32[pfc::kMaxLevels];
     std::vector<void *> allocs;
-    pfc::Tri<double> f0{nullptr, nullptr, nullptr};  // finest-level source
-    pfc::Tri<double> r0{nullptr, nullptr, nullptr};  // finest-level FP64 residual (mixed form)
     unsigned long long *partial = nullptr;
     double *d_scal = nullptr;
     int *d_iters = nullptr;
     double *h_pin = nullptr;
     double *lap1 = nullptr, *lap3 = nullptr;
+    double *minv64 = nullptr, *minv32 = nullptr;  // cached coarsest Newton inverses
+    int *valid64 = nullptr, *valid32 = nullptr;
     double *energy_part = nullptr;
     std::string err;
     // instrumentation
@@ -77,11 +78,35 @@ struct pfc_handle {
 };
 
 namespace pfc {
+OpParams op_of(const pfc_handle *H, int l);
 void cycle64(pfc_handle *H, int l, bool fcycle);
 void restrict_phk(pfc_handle *H);
 pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out);
+pfc_status read_norm(pfc_handle *H, int partials, double *out);
 pfc_status mixed_init(pfc_handle *H);
 pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_cur,
                       double *phi_next, double *mu, double *omega, pfc_step_info *info);
 double algorithmic_bytes(const pfc_handle *H, int kernel);
+// Finest-level set-up of one time step (source, layout conversion of the
+// guess and of phi^k, phi^k hierarchy) and the conversion back.
+void step_begin(pfc_handle *H, const double *phi_prev, const double *phi_cur, const double *mu,
+                const double *omega);
+void step_end(pfc_handle *H, double *phi_next, double *mu, double *omega);
+void invalidate_coarse(pfc_handle *H);
+template <typename T>
+bool dalloc(pfc_handle *H, T **p, size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return false;
+    H->allocs.push_back(q);
+    *p = (T *)q;
+    return true;
+}
+pfc_status fail(pfc_handle *H, pfc_status st, const std::string &msg);
+pfc_status hip_fail(pfc_handle *H, hipError_t e, const char *what);
 }  // namespace pfc
+
+#define HIP_TRY(H, expr)                                                  \
+    do {                                                                  \
+        hipError_t e_ = (expr);                                           \
+        if (e_ != hipSuccess) return pfc::hip_fail((H), e_, #expr);       \
+    } while (0)
