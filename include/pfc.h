@@ -209,9 +209,27 @@ pfc_status pfc_batch_set_state(pfc_batch *b, int32_t i, const double *phi_prev,
 /* Reads instance i's state back (phi_prev, phi_cur, mu, omega; device). */
 pfc_status pfc_batch_get_state(pfc_batch *b, int32_t i, double *phi_prev, double *phi_cur,
                                double *mu, double *omega);
-/* Advances every instance by `steps` time steps.  infos (host, nullable):
- * count*steps entries, instance-major. */
+/* Sets instance i to the first-step state of phi0 (device, n_i^3):
+ * phi_prev = phi_cur = phi0 (the bootstrap phi^{-1} = phi^0) and (mu, omega)
+ * as in pfc_init_guess. */
+pfc_status pfc_batch_init_state(pfc_batch *b, int32_t i, const double *phi0);
+/* Advances every instance by `steps` time steps of scheme (1.10).  Each
+ * phase of a cycle is one launch over all instances that take part in it
+ * (levels aligned from the finest); an instance stops cycling when its own
+ * residual meets the tolerance, so it follows exactly the cycle sequence of
+ * pfc_step.  One cycle plus the stop test is captured as a hipGraph on the
+ * batch's own stream and replayed.  infos (host, nullable): count*steps
+ * entries, instance-major.  Returns the first non-OK instance status (the
+ * others still advance).  Synchronises. */
 pfc_status pfc_batch_run(pfc_batch *b, int32_t steps, pfc_step_info *infos);
+/* Chooses the workgroup size (64, 128, 256 or 512) of the batched smoothing,
+ * residual+coarsening, tau and interpolation launches by timing each on
+ * this batch; with cache_path (nullable) choices are read from / written to
+ * a JSON file keyed by GPU architecture, instance sizes and kernel.
+ * chosen (host, nullable): 4 ints in that kernel order.  Leaves the state
+ * unchanged.  Synchronises. */
+pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *chosen);
+const char *pfc_batch_last_error(const pfc_batch *b);
 
 /* ---------------------------------------------------------------------------
  * Instrumentation

@@ -73,6 +73,9 @@ SIGNATURES = {
     "pfc_batch_set_state": (_i32, [_vp, _i32, _dp, _dp, _dp, _dp]),
     "pfc_batch_get_state": (_i32, [_vp, _i32, _dp, _dp, _dp, _dp]),
     "pfc_batch_run": (_i32, [_vp, _i32, C.POINTER(PfcStepInfo)]),
+    "pfc_batch_init_state": (_i32, [_vp, _i32, _dp]),
+    "pfc_batch_autotune": (_i32, [_vp, C.c_char_p, C.POINTER(_i32)]),
+    "pfc_batch_last_error": (C.c_char_p, [_vp]),
     "pfc_timing_enable": (_i32, [_vp, _i32]),
     "pfc_timing_get": (_i32, [_vp, _i32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                               C.POINTER(C.c_double)]),

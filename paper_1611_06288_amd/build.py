@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libpfc_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "runtime.cpp", "mixed.cpp", "extras.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "mixed.cpp", "adjoint.hip", "batch.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

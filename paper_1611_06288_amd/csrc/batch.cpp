@@ -1,0 +1,505 @@
+// Batched form: many independent PFC simulations (own n, L, eps, dt) advanced
+// together.  Every phase of a multigrid cycle is ONE launch over all instances
+// that take part in it (levels aligned from the finest); instances whose
+// residual met the tolerance are masked by a device flag, so each instance
+// runs exactly the cycle sequence of the single-instance driver.  One cycle
+// (stop test + V or F cycle) is captured once as a hipGraph and replayed
+// until no instance is active.  Workgroup sizes of the batched kernels are
+// chosen by a small autotuner whose choices can be cached in a JSON file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "runtime_internal.h"
+
+using namespace pfc;
+
+struct pfc_batch {
+    int count = 0;
+    pfc_config cfg{};  // shared cycle parameters (from cfgs[0])
+    hipStream_t user_stream = nullptr, stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<pfc_handle *> inst;
+    std::vector<double *> prev, cur, nxt, mu, om;  // natural-layout state per instance
+    int maxdepth = 0;
+    std::vector<std::vector<BSeg>> h_all, h_mid, h_bot;  // per depth (host copies)
+    std::vector<BSeg *> d_all, d_mid, d_bot;              // device copies
+    BSeg *d_norm = nullptr;
+    int n_norm = 0;
+    unsigned norm_blocks = 0;
+    unsigned long long *partial = nullptr;
+    BState st{};
+    int **d_valid = nullptr;
+    int *h_num = nullptr;   // pinned
+    int *h_stats = nullptr; // pinned: cycles, status per instance
+    double *h_res = nullptr;  // pinned: res0, res per instance
+    int tile[4] = {256, 256, 256, 256};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_ready = false;
+    std::vector<void *> allocs;
+    std::string err;
+    ~pfc_batch();
+};
+
+pfc_batch::~pfc_batch() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto *h : inst) pfc_destroy(h);
+    for (void *p : allocs) (void)hipFree(p);
+    if (h_num) (void)hipHostFree(h_num);
+    if (h_stats) (void)hipHostFree(h_stats);
+    if (h_res) (void)hipHostFree(h_res);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+namespace {
+thread_local std::string g_batch_error;
+
+template <typename T>
+bool balloc(pfc_batch *B, T **p, size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return false;
+    B->allocs.push_back(q);
+    *p = (T *)q;
+    return true;
+}
+
+unsigned seg_count(const BSeg &g, int kind) {
+    const unsigned n = (unsigned)g.op.lay.n, P = n * n * n;
+    switch (kind) {
+        case BK_SMOOTH: return P / 2;
+        case BK_RR: return (unsigned)(g.lay_c.n * g.lay_c.n * g.lay_c.n);
+        case BK_PROLONG: return (unsigned)g.lay_c.n * n * n;
+        default: return P;
+    }
+}
+
+unsigned blocks_of(const std::vector<BSeg> &v, int kind, int tile) {
+    unsigned b = 0;
+    for (const auto &g : v) b += (seg_count(g, kind) + tile - 1) / tile;
+    return b;
+}
+
+BSeg make_seg(pfc_handle *h, int l, int i, const int *active) {
+    BSeg g{};
+    const Level &A = h->lev[l];
+    g.op = op_of(h, l);
+    g.u = A.u;
+    g.f = A.f;
+    g.ubar = A.ubar;
+    g.phk = A.phk;
+    if (l + 1 < h->nlev) {
+        const Level &C = h->lev[l + 1];
+        g.lay_c = C.lay;
+        g.uc = C.u;
+        g.fc = C.f;
+        g.ubarc = C.ubar;
+    } else {
+        g.lay_c = A.lay;
+    }
+    g.lap1 = h->lap1;
+    g.lap3 = h->lap3;
+    g.minv = h->minv64;
+    g.valid = h->valid64;
+    g.iters = h->d_iters;
+    g.active = active;
+    g.inst = i;
+    return g;
+}
+
+pfc_status bfail(pfc_batch *B, pfc_status s, const std::string &m) {
+    if (B)
+        B->err = m;
+    else
+        g_batch_error = m;
+    return s;
+}
+
+// One cycle of every active instance, aligned by depth from the finest level.
+void bcycle(pfc_batch *B, int d, bool fcycle) {
+    const hipStream_t s = B->stream;
+    if (!B->h_bot[d].empty()) launch_batch_coarse(s, B->d_bot[d], (int)B->h_bot[d].size());
+    if (B->h_mid[d].empty()) return;
+    const auto &mid = B->h_mid[d];
+    const int nm = (int)mid.size();
+    const int picard = B->cfg.lin == PFC_LIN_PICARD;
+    auto sweep = [&]() {
+        const unsigned nb = blocks_of(mid, BK_SMOOTH, B->tile[BK_SMOOTH]);
+        for (int c = 0; c < 2; ++c)
+            launch_batch(s, BK_SMOOTH, B->d_mid[d], nm, nb, B->tile[BK_SMOOTH], c, picard);
+    };
+    for (int q = 0; q < B->cfg.nu1; ++q) sweep();
+    launch_batch(s, BK_RR, B->d_mid[d], nm, blocks_of(mid, BK_RR, B->tile[BK_RR]), B->tile[BK_RR], 0, 0);
+    const auto &nxt = B->h_all[d + 1];
+    launch_batch(s, BK_TAU, B->d_all[d + 1], (int)nxt.size(), blocks_of(nxt, BK_TAU, B->tile[BK_TAU]),
+                 B->tile[BK_TAU], 0, 0);
+    bcycle(B, d + 1, fcycle);
+    if (fcycle) bcycle(B, d + 1, false);
+    launch_batch(s, BK_PROLONG, B->d_mid[d], nm, blocks_of(mid, BK_PROLONG, B->tile[BK_PROLONG]),
+                 B->tile[BK_PROLONG], 0, 0);
+    for (int q = 0; q < B->cfg.nu2; ++q) sweep();
+}
+
+void record_cycle(pfc_batch *B) {
+    launch_batch_norm(B->stream, B->d_norm, B->n_norm, B->norm_blocks, B->partial, B->st, B->cfg.tol,
+                      B->cfg.max_cycles);
+    bcycle(B, 0, B->cfg.cycle == PFC_CYCLE_F);
+}
+
+pfc_status capture(pfc_batch *B) {
+    if (B->exec) {
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+    }
+    if (B->graph) {
+        (void)hipGraphDestroy(B->graph);
+        B->graph = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(B, PFC_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    record_cycle(B);
+    e = hipStreamEndCapture(B->stream, &B->graph);
+    if (e != hipSuccess) return bfail(B, PFC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return bfail(B, PFC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    B->graph_ready = true;
+    return PFC_OK;
+}
+
+pfc_status run_step(pfc_batch *B, pfc_step_info *infos_step) {
+    const hipStream_t s = B->stream;
+    for (int i = 0; i < B->count; ++i) step_begin(B->inst[i], B->prev[i], B->cur[i], B->mu[i], B->om[i]);
+    launch_batch_reset(s, B->st, B->count, B->d_valid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(B, PFC_ERR_HIP, hipGetErrorString(e));
+    if (!B->graph_ready) {
+        const pfc_status stc = capture(B);
+        if (stc != PFC_OK) return stc;
+    }
+    for (int guard = 0; guard <= B->cfg.max_cycles + 2; ++guard) {
+        e = hipGraphLaunch(B->exec, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(B->h_num, B->st.num_active, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bfail(B, PFC_ERR_HIP, std::string("batched cycle: ") + hipGetErrorString(e));
+        if (*B->h_num == 0) break;
+    }
+    for (int i = 0; i < B->count; ++i) step_end(B->inst[i], B->nxt[i], B->mu[i], B->om[i]);
+    const size_t n = (size_t)B->count;
+    e = hipMemcpyAsync(B->h_stats, B->st.cycles, n * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->h_stats + n, B->st.status, n * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->h_res, B->st.res0, n * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->h_res + n, B->st.res, n * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bfail(B, PFC_ERR_HIP, std::string("batched step: ") + hipGetErrorString(e));
+    pfc_status worst = PFC_OK;
+    for (int i = 0; i < B->count; ++i) {
+        if (infos_step) {
+            infos_step[i].cycles = B->h_stats[i];
+            infos_step[i].status = B->h_stats[n + i];
+            infos_step[i].res0 = B->h_res[i];
+            infos_step[i].res_final = B->h_res[n + i];
+        }
+        if (B->h_stats[n + i] != PFC_OK && worst == PFC_OK) worst = B->h_stats[n + i];
+        std::swap(B->prev[i], B->nxt[i]);   // nxt <- old prev (spare)
+        std::swap(B->prev[i], B->cur[i]);   // prev <- old cur, cur <- new phi
+    }
+    return worst;
+}
+
+std::string device_name() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    return std::string(p.gcnArchName);
+}
+
+std::map<std::string, int> read_cache(const char *path) {
+    std::map<std::string, int> m;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        const size_t a = line.find('"'), b = line.find('"', a + 1), c = line.find(':', b);
+        if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
+        m[line.substr(a + 1, b - a - 1)] = std::atoi(line.c_str() + c + 1);
+    }
+    return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, int> &m) {
+    std::ofstream out(path);
+    out << "{\n";
+    size_t k = 0;
+    for (const auto &kv : m) out << "  \"" << kv.first << "\": " << kv.second << (++k < m.size() ? ",\n" : "\n");
+    out << "}\n";
+}
+
+}  // namespace
+
+extern "C" {
+
+pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream, pfc_batch **out) {
+    if (!out) return bfail(nullptr, PFC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count > 4096 || !cfgs) return bfail(nullptr, PFC_ERR_INVALID_ARG, "count must be in 1..4096");
+    for (int i = 0; i < count; ++i) {
+        const std::string why = validate_config(&cfgs[i]);
+        if (!why.empty()) return bfail(nullptr, PFC_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": " + why);
+        if (cfgs[i].precision != PFC_FP64) return bfail(nullptr, PFC_ERR_INVALID_ARG, "the batched form is FP64");
+        if (cfgs[i].nu1 != cfgs[0].nu1 || cfgs[i].nu2 != cfgs[0].nu2 || cfgs[i].cycle != cfgs[0].cycle ||
+            cfgs[i].lin != cfgs[0].lin || cfgs[i].tol != cfgs[0].tol || cfgs[i].max_cycles != cfgs[0].max_cycles)
+            return bfail(nullptr, PFC_ERR_INVALID_ARG, "nu1, nu2, cycle, lin, tol, max_cycles must agree");
+    }
+    pfc_batch *B = new pfc_batch();
+    B->count = count;
+    B->cfg = cfgs[0];
+    B->user_stream = (hipStream_t)stream;
+    if (hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess) {
+        delete B;
+        return bfail(nullptr, PFC_ERR_HIP, "stream/event creation failed");
+    }
+    bool ok = true;
+    std::vector<int> nlev(count);
+    for (int i = 0; i < count && ok; ++i) {
+        pfc_handle *h = nullptr;
+        const pfc_status st = pfc_create(&cfgs[i], B->stream, &h);
+        if (st != PFC_OK) {
+            const std::string msg = pfc_last_error(nullptr);
+            delete B;
+            return bfail(nullptr, st, "instance " + std::to_string(i) + ": " + msg);
+        }
+        B->inst.push_back(h);
+        nlev[i] = h->nlev;
+        B->maxdepth = std::max(B->maxdepth, h->nlev);
+        const size_t P = h->lev[0].P;
+        double *p0, *p1, *p2, *p3, *p4;
+        ok = balloc(B, &p0, P) && balloc(B, &p1, P) && balloc(B, &p2, P) && balloc(B, &p3, P) && balloc(B, &p4, P);
+        if (!ok) break;
+        ok = hipMemset(p0, 0, P * 8) == hipSuccess && hipMemset(p1, 0, P * 8) == hipSuccess &&
+             hipMemset(p2, 0, P * 8) == hipSuccess && hipMemset(p3, 0, P * 8) == hipSuccess &&
+             hipMemset(p4, 0, P * 8) == hipSuccess;
+        B->prev.push_back(p0);
+        B->cur.push_back(p1);
+        B->nxt.push_back(p2);
+        B->mu.push_back(p3);
+        B->om.push_back(p4);
+    }
+    const size_t n = (size_t)count;
+    ok = ok && balloc(B, &B->st.active, n) && balloc(B, &B->st.cycles, n) && balloc(B, &B->st.status, n) &&
+         balloc(B, &B->st.res0, n) && balloc(B, &B->st.res, n) && balloc(B, &B->st.num_active, 1) &&
+         balloc(B, &B->d_valid, n);
+    unsigned *nf = nullptr, *nbk = nullptr;
+    ok = ok && balloc(B, &nf, n) && balloc(B, &nbk, n);
+    if (!ok) {
+        delete B;
+        return bfail(nullptr, PFC_ERR_OOM, "device allocation failed");
+    }
+    B->st.norm_first = nf;
+    B->st.norm_blocks = nbk;
+    // segment lists by depth
+    B->h_all.resize(B->maxdepth);
+    B->h_mid.resize(B->maxdepth);
+    B->h_bot.resize(B->maxdepth);
+    for (int i = 0; i < count; ++i)
+        for (int l = 0; l < nlev[i]; ++l) {
+            const BSeg g = make_seg(B->inst[i], l, i, B->st.active + i);
+            B->h_all[l].push_back(g);
+            (l + 1 < nlev[i] ? B->h_mid[l] : B->h_bot[l]).push_back(g);
+        }
+    auto upload = [&](const std::vector<BSeg> &v, BSeg **d) -> bool {
+        if (v.empty()) {
+            *d = nullptr;
+            return true;
+        }
+        return balloc(B, d, v.size()) &&
+               hipMemcpy(*d, v.data(), v.size() * sizeof(BSeg), hipMemcpyHostToDevice) == hipSuccess;
+    };
+    B->d_all.resize(B->maxdepth);
+    B->d_mid.resize(B->maxdepth);
+    B->d_bot.resize(B->maxdepth);
+    for (int d = 0; d < B->maxdepth && ok; ++d)
+        ok = upload(B->h_all[d], &B->d_all[d]) && upload(B->h_mid[d], &B->d_mid[d]) &&
+             upload(B->h_bot[d], &B->d_bot[d]);
+    // stop test over the finest levels
+    B->d_norm = B->d_all.empty() ? nullptr : B->d_all[0];
+    B->n_norm = count;
+    std::vector<unsigned> first(n), nblk(n);
+    unsigned acc = 0;
+    for (int s = 0; s < count; ++s) {
+        first[s] = acc;
+        nblk[s] = (seg_count(B->h_all[0][s], BK_NORM) + kBlock - 1) / kBlock;
+        acc += nblk[s];
+    }
+    B->norm_blocks = acc;
+    std::vector<int *> valids(n);
+    for (int i = 0; i < count; ++i) valids[i] = B->inst[i]->valid64;
+    ok = ok && balloc(B, &B->partial, acc + 16) &&
+         hipMemcpy(nf, first.data(), n * sizeof(unsigned), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(nbk, nblk.data(), n * sizeof(unsigned), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(B->d_valid, valids.data(), n * sizeof(int *), hipMemcpyHostToDevice) == hipSuccess &&
+         hipHostMalloc((void **)&B->h_num, sizeof(int), 0) == hipSuccess &&
+         hipHostMalloc((void **)&B->h_stats, 2 * n * sizeof(int), 0) == hipSuccess &&
+         hipHostMalloc((void **)&B->h_res, 2 * n * sizeof(double), 0) == hipSuccess;
+    if (!ok) {
+        delete B;
+        return bfail(nullptr, PFC_ERR_OOM, "allocation of batch tables failed");
+    }
+    *out = B;
+    return PFC_OK;
+}
+
+pfc_status pfc_batch_destroy(pfc_batch *b) {
+    if (!b) return PFC_ERR_INVALID_ARG;
+    delete b;
+    return PFC_OK;
+}
+
+static pfc_status check_inst(pfc_batch *b, int32_t i) {
+    if (!b) return PFC_ERR_INVALID_ARG;
+    if (i < 0 || i >= b->count) return bfail(b, PFC_ERR_INVALID_ARG, "instance index out of range");
+    return PFC_OK;
+}
+
+pfc_status pfc_batch_set_state(pfc_batch *b, int32_t i, const double *phi_prev, const double *phi_cur,
+                               const double *mu, const double *omega) {
+    const pfc_status s = check_inst(b, i);
+    if (s != PFC_OK) return s;
+    if (!phi_prev || !phi_cur || !mu || !omega) return bfail(b, PFC_ERR_INVALID_ARG, "NULL pointer");
+    const size_t bytes = b->inst[i]->lev[0].P * sizeof(double);
+    (void)hipEventRecord(b->ev_in, b->user_stream);
+    (void)hipStreamWaitEvent(b->stream, b->ev_in, 0);
+    hipError_t e = hipMemcpyAsync(b->prev[i], phi_prev, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->cur[i], phi_cur, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->mu[i], mu, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->om[i], omega, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, PFC_ERR_HIP, hipGetErrorString(e));
+    return PFC_OK;
+}
+
+pfc_status pfc_batch_get_state(pfc_batch *b, int32_t i, double *phi_prev, double *phi_cur, double *mu,
+                               double *omega) {
+    const pfc_status s = check_inst(b, i);
+    if (s != PFC_OK) return s;
+    const size_t bytes = b->inst[i]->lev[0].P * sizeof(double);
+    hipError_t e = hipSuccess;
+    if (phi_prev) e = hipMemcpyAsync(phi_prev, b->prev[i], bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess && phi_cur) e = hipMemcpyAsync(phi_cur, b->cur[i], bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess && mu) e = hipMemcpyAsync(mu, b->mu[i], bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess && omega) e = hipMemcpyAsync(omega, b->om[i], bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, PFC_ERR_HIP, hipGetErrorString(e));
+    return PFC_OK;
+}
+
+pfc_status pfc_batch_run(pfc_batch *b, int32_t steps, pfc_step_info *infos) {
+    if (!b || steps < 0) return PFC_ERR_INVALID_ARG;
+    (void)hipEventRecord(b->ev_in, b->user_stream);
+    (void)hipStreamWaitEvent(b->stream, b->ev_in, 0);
+    pfc_status worst = PFC_OK;
+    std::vector<pfc_step_info> one((size_t)b->count);
+    for (int s = 0; s < steps; ++s) {
+        const pfc_status st = run_step(b, one.data());
+        if (st == PFC_ERR_HIP) return st;
+        if (infos)
+            for (int i = 0; i < b->count; ++i) infos[(size_t)i * steps + s] = one[i];
+        if (st != PFC_OK && worst == PFC_OK) worst = st;
+    }
+    (void)hipEventRecord(b->ev_out, b->stream);
+    (void)hipStreamWaitEvent(b->user_stream, b->ev_out, 0);
+    if (worst != PFC_OK) bfail(b, worst, pfc_status_string(worst));
+    return worst;
+}
+
+pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *chosen) {
+    if (!b) return PFC_ERR_INVALID_ARG;
+    std::vector<int> sizes;
+    for (auto *h : b->inst) sizes.push_back(h->lev[0].n);
+    std::sort(sizes.begin(), sizes.end());
+    std::ostringstream sig;
+    sig << device_name() << "|" << sizes.size() << ":";
+    for (size_t i = 0; i < sizes.size(); ++i) sig << (i ? "," : "") << sizes[i];
+    static const char *kind_name[4] = {"smooth", "resid_restrict", "tau", "prolong"};
+    std::map<std::string, int> cache;
+    if (cache_path) cache = read_cache(cache_path);
+    bool changed = false;
+    // make the working buffers hold a sane state to time on
+    for (int i = 0; i < b->count; ++i) step_begin(b->inst[i], b->prev[i], b->cur[i], b->mu[i], b->om[i]);
+    launch_batch_reset(b->stream, b->st, b->count, b->d_valid);
+    hipEvent_t t0, t1;
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    for (int kind = 0; kind < 4; ++kind) {
+        const std::string key = sig.str() + "|" + kind_name[kind];
+        auto it = cache.find(key);
+        if (it != cache.end() && (it->second == 64 || it->second == 128 || it->second == 256 || it->second == 512)) {
+            b->tile[kind] = it->second;
+            continue;
+        }
+        const int d = kind == BK_TAU ? 1 : 0;
+        if (d >= b->maxdepth || b->h_mid[0].empty()) continue;
+        const auto &segs = kind == BK_TAU ? b->h_all[1] : b->h_mid[0];
+        BSeg *dsegs = kind == BK_TAU ? b->d_all[1] : b->d_mid[0];
+        float best = 1e30f;
+        int best_tile = 256;
+        for (int tile : {64, 128, 256, 512}) {
+            const unsigned nb = blocks_of(segs, kind, tile);
+            for (int rep = 0; rep < 2; ++rep) launch_batch(b->stream, kind, dsegs, (int)segs.size(), nb, tile, rep & 1, 0);
+            (void)hipEventRecord(t0, b->stream);
+            for (int rep = 0; rep < 6; ++rep) launch_batch(b->stream, kind, dsegs, (int)segs.size(), nb, tile, rep & 1, 0);
+            (void)hipEventRecord(t1, b->stream);
+            if (hipEventSynchronize(t1) != hipSuccess) break;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, t0, t1);
+            if (ms < best) {
+                best = ms;
+                best_tile = tile;
+            }
+        }
+        b->tile[kind] = best_tile;
+        cache[key] = best_tile;
+        changed = true;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, PFC_ERR_HIP, hipGetErrorString(e));
+    if (cache_path && changed) write_cache(cache_path, cache);
+    b->graph_ready = false;  // recapture with the chosen tiles
+    if (chosen)
+        for (int k = 0; k < 4; ++k) chosen[k] = b->tile[k];
+    return PFC_OK;
+}
+
+const char *pfc_batch_last_error(const pfc_batch *b) { return b ? b->err.c_str() : g_batch_error.c_str(); }
+
+}  // extern "C"
+
+extern "C" pfc_status pfc_batch_init_state(pfc_batch *b, int32_t i, const double *phi0) {
+    const pfc_status s = check_inst(b, i);
+    if (s != PFC_OK) return s;
+    if (!phi0) return bfail(b, PFC_ERR_INVALID_ARG, "NULL pointer");
+    const size_t bytes = b->inst[i]->lev[0].P * sizeof(double);
+    (void)hipEventRecord(b->ev_in, b->user_stream);
+    (void)hipStreamWaitEvent(b->stream, b->ev_in, 0);
+    hipError_t e = hipMemcpyAsync(b->prev[i], phi0, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->cur[i], phi0, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return bfail(b, PFC_ERR_HIP, hipGetErrorString(e));
+    const pfc_status st = pfc_init_guess(b->inst[i], b->cur[i], b->mu[i], b->om[i]);
+    if (st != PFC_OK) return bfail(b, st, pfc_last_error(b->inst[i]));
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, PFC_ERR_HIP, hipGetErrorString(e));
+    return PFC_OK;
+}

@@ -13,7 +13,8 @@
 // Storage type T is double (FP64 path) or float (the correction cycle of the
 // mixed-precision form); operator arithmetic and the pointwise 3x3 solve run
 // in FP64 in both.
-#include "pfc_internal.h"
+#include "device_common.h"
+#include "pfc.h"
 
 #include <math.h>
 
@@ -43,142 +44,6 @@ Lay make_lay(int n, bool split) {
     return l;
 }
 
-static unsigned blocks_for(size_t count) { return (unsigned)((count + kBlock - 1) / kBlock); }
-
-static unsigned reduce_blocks(size_t count) {
-    const size_t b = (count + kBlock - 1) / kBlock;
-    return (unsigned)(b < (size_t)kMaxReduceBlocks ? b : (size_t)kMaxReduceBlocks);
-}
-
-__device__ __forceinline__ unsigned xcd_block() {
-    const unsigned nb = gridDim.x, b = blockIdx.x;
-    const unsigned per = nb >> 3;
-    if (b < (per << 3)) return (b & 7u) * per + (b >> 3);
-    return b;
-}
-
-__device__ __forceinline__ int wrap_p(int i, int n) { return i == n - 1 ? 0 : i + 1; }
-__device__ __forceinline__ int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
-
-__device__ __forceinline__ size_t npts(const Lay &L) { return (size_t)L.n * L.n * L.n; }
-
-// Storage offset of point (i, j, k).
-__device__ __forceinline__ size_t sidx(const Lay &L, int i, int j, int k) {
-    const size_t n = (size_t)L.n;
-    if (!L.split) return ((size_t)k * n + (size_t)j) * n + (size_t)i;
-    const size_t H = n * n * n / 2;
-    return (size_t)((i + j + k) & 1) * H + ((size_t)k * n + (size_t)j) * (n >> 1) + (size_t)(i >> 1);
-}
-
-// Grid point stored at offset t.
-__device__ __forceinline__ void decode(const Lay &L, unsigned t, int &i, int &j, int &k) {
-    const int n = L.n;
-    if (!L.split) {
-        const unsigned row = L.dn.q(t);
-        i = (int)(t - row * (unsigned)n);
-        k = (int)L.dn.q(row);
-        j = (int)(row - (unsigned)k * (unsigned)n);
-        return;
-    }
-    const unsigned H = (unsigned)((size_t)n * n * n / 2);
-    const int c = t >= H ? 1 : 0;
-    const unsigned r = t - (c ? H : 0u);
-    const unsigned hn = (unsigned)(n >> 1);
-    const unsigned row = L.dh.q(r);
-    const int m = (int)(r - row * hn);
-    k = (int)L.dn.q(row);
-    j = (int)(row - (unsigned)k * (unsigned)n);
-    i = 2 * m + ((c + j + k) & 1);
-}
-
-// Grid point number t in natural (x fastest) order, whatever the storage.
-__device__ __forceinline__ void decode_nat(const Lay &L, unsigned t, int &i, int &j, int &k) {
-    const unsigned row = L.dn.q(t);
-    i = (int)(t - row * (unsigned)L.n);
-    k = (int)L.dn.q(row);
-    j = (int)(row - (unsigned)k * (unsigned)L.n);
-}
-
-// 32-bit storage offset (every level has at most 2^30 points).
-__device__ __forceinline__ unsigned sidx32(const Lay &L, int i, int j, int k) {
-    const unsigned n = (unsigned)L.n;
-    if (!L.split) return ((unsigned)k * n + (unsigned)j) * n + (unsigned)i;
-    const unsigned H = n * n * n / 2;
-    return ((unsigned)((i + j + k) & 1)) * H + ((unsigned)k * n + (unsigned)j) * (n >> 1) +
-           (unsigned)(i >> 1);
-}
-
-// A point and its six face neighbours, periodic, as 32-bit offsets.
-struct Off {
-    unsigned c, xp, xm, yp, ym, zp, zm;
-};
-
-__device__ __forceinline__ Off offs(const Lay &L, int i, int j, int k) {
-    const int n = L.n;
-    const int im = wrap_m(i, n), ip = wrap_p(i, n), jm = wrap_m(j, n), jp = wrap_p(j, n),
-              km = wrap_m(k, n), kp = wrap_p(k, n);
-    Off q;
-    const unsigned un = (unsigned)n;
-    if (!L.split) {
-        const unsigned row = (unsigned)k * un + (unsigned)j;
-        q.c = row * un + (unsigned)i;
-        q.xm = row * un + (unsigned)im;
-        q.xp = row * un + (unsigned)ip;
-        q.ym = ((unsigned)k * un + (unsigned)jm) * un + (unsigned)i;
-        q.yp = ((unsigned)k * un + (unsigned)jp) * un + (unsigned)i;
-        q.zm = ((unsigned)km * un + (unsigned)j) * un + (unsigned)i;
-        q.zp = ((unsigned)kp * un + (unsigned)j) * un + (unsigned)i;
-        return q;
-    }
-    const unsigned hn = un >> 1, H = un * un * hn;
-    const unsigned colour = (unsigned)((i + j + k) & 1);
-    const unsigned oc = (colour ^ 1u) * H;
-    const unsigned row = (unsigned)k * un + (unsigned)j;
-    const unsigned m = (unsigned)(i >> 1);
-    q.c = colour * H + row * hn + m;
-    q.xm = oc + row * hn + (unsigned)(im >> 1);
-    q.xp = oc + row * hn + (unsigned)(ip >> 1);
-    q.ym = oc + ((unsigned)k * un + (unsigned)jm) * hn + m;
-    q.yp = oc + ((unsigned)k * un + (unsigned)jp) * hn + m;
-    q.zm = oc + ((unsigned)km * un + (unsigned)j) * hn + m;
-    q.zp = oc + ((unsigned)kp * un + (unsigned)j) * hn + m;
-    return q;
-}
-
-template <typename T>
-__device__ __forceinline__ double nsum(const T *__restrict__ v, const Off &q) {
-    return ((double)v[q.xp] + (double)v[q.xm]) + ((double)v[q.yp] + (double)v[q.ym]) +
-           ((double)v[q.zp] + (double)v[q.zm]);
-}
-
-// Cubic term of the chemical potential in its second-order form,
-// g(x; a) = 1/4 (x + a)(x^2 + a^2), a = phi^kappa (Section 5, N2).
-// DELTA: the correction form G(e) = g(b + e; a) - g(b; a), expanded without
-// cancellation, b the base iterate.
-template <bool DELTA>
-struct Cubic;
-
-template <>
-struct Cubic<false> {
-    __device__ static __forceinline__ double g(double x, double a, double) {
-        return 0.25 * (x + a) * (x * x + a * a);
-    }
-    __device__ static __forceinline__ double dg(double x, double a, double) {
-        return 0.25 * (3.0 * x * x + 2.0 * x * a + a * a);
-    }
-};
-
-template <>
-struct Cubic<true> {
-    __device__ static __forceinline__ double g(double e, double a, double b) {
-        return 0.25 * (e * (b * b + a * a) + (b + e + a) * (2.0 * b * e + e * e));
-    }
-    __device__ static __forceinline__ double dg(double e, double a, double b) {
-        const double x = b + e;
-        return 0.25 * (3.0 * x * x + 2.0 * x * a + a * a);
-    }
-};
-
 // ------------------------------------------------------------- smoothing
 //
 // Pointwise solve of the three equations of N(u) = f at one point with the
@@ -190,13 +55,12 @@ struct Cubic<true> {
 // phi = (r1 - A r2 + A B r3) / (1 + A (c + B Dd)).
 // One thread per point of colour `colour` (colour-split storage only).
 template <typename T, bool DELTA>
-__global__ __launch_bounds__(kBlock) void k_smooth(OpParams op, int colour, int picard, Tri<T> u,
-                                                   Tri<const T> f, const T *__restrict__ phk,
-                                                   const T *__restrict__ base) {
+__device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int picard, Tri<T> u,
+                                            Tri<const T> f, const T *__restrict__ phk,
+                                            const T *__restrict__ base, unsigned t) {
     const Lay &L = op.lay;
     const int n = L.n, hn = n >> 1;
     const unsigned H = (unsigned)((size_t)n * n * n / 2);
-    const unsigned t = xcd_block() * kBlock + threadIdx.x;
     if (t >= H) return;
     const unsigned row = L.dh.q(t);
     const int m = (int)(t - row * (unsigned)hn);
@@ -245,6 +109,13 @@ __global__ __launch_bounds__(kBlock) void k_smooth(OpParams op, int colour, int 
 }
 
 template <typename T, bool DELTA>
+__global__ __launch_bounds__(kBlock) void k_smooth(OpParams op, int colour, int picard, Tri<T> u,
+                                                   Tri<const T> f, const T *__restrict__ phk,
+                                                   const T *__restrict__ base) {
+    smooth_body<T, DELTA>(op, colour, picard, u, f, phk, base, xcd_block() * kBlock + threadIdx.x);
+}
+
+template <typename T, bool DELTA>
 void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
                    Tri<const T> f, const T *phk, const T *base) {
     const size_t H = npts_host(op.lay) / 2;
@@ -271,25 +142,24 @@ __device__ __forceinline__ void resid_at(const OpParams &op, const Tri<const T> 
     r3 = (double)f.c[q.c] - (om - 0.5 * lphi);
 }
 
-__device__ __forceinline__ unsigned long long abs_bits(double v) {
-    return (unsigned long long)__double_as_longlong(v) & 0x7fffffffffffffffull;
-}
-
-__device__ __forceinline__ unsigned long long umax(unsigned long long a, unsigned long long b) {
-    return a > b ? a : b;
-}
-
-// Block max of non-negative IEEE bit patterns (NaN sorts above +Inf, so a
-// NaN residual is never lost).
-__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v) {
-    __shared__ unsigned long long red[kBlock];
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = umax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
+// Residual at the point stored at t (written to r if r.a is set); returns the
+// largest |component| as an IEEE bit pattern.
+template <typename T, bool DELTA>
+__device__ __forceinline__ unsigned long long resid_bits(const OpParams &op, const Tri<const T> &u,
+                                                         const Tri<const T> &f, const T *phk,
+                                                         const T *base, const Tri<T> &r,
+                                                         unsigned t) {
+    int i, j, k;
+    decode(op.lay, t, i, j, k);
+    const Off q = offs(op.lay, i, j, k);
+    double r1, r2, r3;
+    resid_at<T, DELTA>(op, u, f, phk, base, q, r1, r2, r3);
+    if (r.a) {
+        r.a[q.c] = (T)r1;
+        r.b[q.c] = (T)r2;
+        r.c[q.c] = (T)r3;
     }
-    return red[0];
+    return umax(abs_bits(r1), umax(abs_bits(r2), abs_bits(r3)));
 }
 
 template <typename T, bool DELTA>
@@ -300,19 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_max(OpParams op, Tri<const T> 
     const Lay &L = op.lay;
     const unsigned total = (unsigned)npts(L);
     unsigned long long m = 0;
-    for (unsigned t = xcd_block() * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock) {
-        int i, j, k;
-        decode(L, t, i, j, k);
-        const Off q = offs(L, i, j, k);
-        double r1, r2, r3;
-        resid_at<T, DELTA>(op, u, f, phk, base, q, r1, r2, r3);
-        if (r.a) {
-            r.a[q.c] = (T)r1;
-            r.b[q.c] = (T)r2;
-            r.c[q.c] = (T)r3;
-        }
-        m = umax(m, umax(abs_bits(r1), umax(abs_bits(r2), abs_bits(r3))));
-    }
+    for (unsigned t = xcd_block() * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock)
+        m = umax(m, resid_bits<T, DELTA>(op, u, f, phk, base, r, t));
     m = block_max_u64(m);
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
@@ -343,14 +202,13 @@ void launch_max_final(hipStream_t s, const unsigned long long *partial, int coun
 // One thread per coarse cell: residual at its 8 children, then the coarse
 // cell's restricted residual I r and restricted iterate I u (8-child means).
 template <typename T, bool DELTA>
-__global__ __launch_bounds__(kBlock) void k_resid_restrict(OpParams op, Lay LC, Tri<const T> u,
-                                                           Tri<const T> f,
-                                                           const T *__restrict__ phk,
-                                                           const T *__restrict__ base,
-                                                           Tri<T> ubar_c, Tri<T> rr_c) {
+__device__ __forceinline__ void resid_restrict_body(const OpParams &op, const Lay &LC,
+                                                    Tri<const T> u, Tri<const T> f,
+                                                    const T *__restrict__ phk,
+                                                    const T *__restrict__ base, Tri<T> ubar_c,
+                                                    Tri<T> rr_c, unsigned tn) {
     // coarse cells in natural order, so that consecutive threads read
     // consecutive fine offsets of each colour
-    const unsigned tn = xcd_block() * kBlock + threadIdx.x;
     if (tn >= (unsigned)npts(LC)) return;
     int I, J, K;
     decode_nat(LC, tn, I, J, K);
@@ -374,6 +232,16 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(OpParams op, Lay LC, 
     ubar_c.a[t] = (T)(0.125 * ua);
     ubar_c.b[t] = (T)(0.125 * ub);
     ubar_c.c[t] = (T)(0.125 * uc);
+}
+
+template <typename T, bool DELTA>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(OpParams op, Lay LC, Tri<const T> u,
+                                                           Tri<const T> f,
+                                                           const T *__restrict__ phk,
+                                                           const T *__restrict__ base,
+                                                           Tri<T> ubar_c, Tri<T> rr_c) {
+    resid_restrict_body<T, DELTA>(op, LC, u, f, phk, base, ubar_c, rr_c,
+                                  xcd_block() * kBlock + threadIdx.x);
 }
 
 template <typename T, bool DELTA>
@@ -412,11 +280,10 @@ void launch_restrict(hipStream_t s, const Lay &fine, const Lay &coarse, const T 
 // Coarse right-hand side of the FAS: f_c = N_c(I u) + I r (f holds I r on
 // entry); also starts the coarse iterate at I u.
 template <typename T, bool DELTA>
-__global__ __launch_bounds__(kBlock) void k_tau(OpParams op, Tri<const T> ubar, Tri<T> f, Tri<T> u,
-                                                const T *__restrict__ phk,
-                                                const T *__restrict__ base) {
+__device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, Tri<T> f, Tri<T> u,
+                                         const T *__restrict__ phk, const T *__restrict__ base,
+                                         unsigned t) {
     const Lay &L = op.lay;
-    const unsigned t = xcd_block() * kBlock + threadIdx.x;
     if (t >= (unsigned)npts(L)) return;
     int i, j, k;
     decode(L, t, i, j, k);
@@ -439,6 +306,13 @@ __global__ __launch_bounds__(kBlock) void k_tau(OpParams op, Tri<const T> ubar, 
 }
 
 template <typename T, bool DELTA>
+__global__ __launch_bounds__(kBlock) void k_tau(OpParams op, Tri<const T> ubar, Tri<T> f, Tri<T> u,
+                                                const T *__restrict__ phk,
+                                                const T *__restrict__ base) {
+    tau_body<T, DELTA>(op, ubar, f, u, phk, base, xcd_block() * kBlock + threadIdx.x);
+}
+
+template <typename T, bool DELTA>
 void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                 const T *phk, const T *base) {
     hipLaunchKernelGGL((k_tau<T, DELTA>), dim3(blocks_for(npts_host(opc.lay))), dim3(kBlock), 0, s,
@@ -454,10 +328,9 @@ void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f,
 // {I-1, I, I+1} x {J0, J1} x {K0, K1}.  Consecutive threads take consecutive
 // I, so the fine accesses are unit-stride in each colour block.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T> v, Tri<const T> ubar,
-                                                    Tri<T> fine) {
+__device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<const T> v,
+                                             Tri<const T> ubar, Tri<T> fine, unsigned t) {
     const int nc = LC.n, nf = LF.n;
-    const unsigned t = xcd_block() * kBlock + threadIdx.x;
     if (t >= (unsigned)nc * (unsigned)nf * (unsigned)nf) return;
     const unsigned row = LC.dn.q(t);           // (k, j) fine row
     const int I = (int)(t - row * (unsigned)nc);
@@ -498,6 +371,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T>
 }
 
 template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T> v, Tri<const T> ubar,
+                                                    Tri<T> fine) {
+    prolong_body<T>(LC, LF, v, ubar, fine, xcd_block() * kBlock + threadIdx.x);
+}
+
+template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
                     Tri<const T> ubar, Tri<T> fine_u) {
     const size_t pairs = (size_t)coarse.n * fine.n * fine.n;
@@ -519,18 +398,12 @@ void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const
 // rebuilt at the current iterate (which makes that step a Newton step).  The
 // inverse comes from Gauss-Jordan elimination with partial pivoting in LDS.
 // Stops when max|update| <= 1e-14 max(1, max|phi|) (or after 60 iterations).
-__device__ __forceinline__ double wave_max(double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
 template <typename T, bool DELTA>
-__global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const T> f,
-                                               const T *__restrict__ phk,
-                                               const T *__restrict__ base,
-                                               const double *__restrict__ lap1,
-                                               const double *__restrict__ lap3, double *minv,
-                                               int *valid, int *iters) {
+__device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<const T> f,
+                                            const T *__restrict__ phk, const T *__restrict__ base,
+                                            const double *__restrict__ lap1,
+                                            const double *__restrict__ lap3, double *minv,
+                                            int *valid, int *iters) {
     __shared__ double A[64 * 64];  // column-major: A[col * P + row]
     __shared__ double vec[64];
     __shared__ double dvec[64];
@@ -581,47 +454,7 @@ __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const 
                 A[o] = (q == p ? 1.0 : 0.0) - tau * lap1[o] * dvec[q] - 0.5 * tau * lap3[o];
             }
         __syncthreads();
-        for (int c = 0; c < P; ++c) {
-            double val = (act && p >= c) ? fabs(A[c * P + p]) : -1.0;
-            int id = p;
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(val, off, 64);
-                const int oid = __shfl_xor(id, off, 64);
-                if (ov > val || (ov == val && oid < id)) {
-                    val = ov;
-                    id = oid;
-                }
-            }
-            const int pr = id;
-            if (p == 0) perm[c] = pr;
-            if (pr != c && act) {  // swap rows c and pr; lane p handles column p
-                const double tmp = A[p * P + c];
-                A[p * P + c] = A[p * P + pr];
-                A[p * P + pr] = tmp;
-            }
-            __syncthreads();
-            const double pinv = 1.0 / A[c * P + c];
-            __syncthreads();
-            if (act) A[p * P + c] = (p == c ? 1.0 : A[p * P + c]) * pinv;  // scale pivot row
-            __syncthreads();
-            if (act && p != c) {
-                const double fr = A[c * P + p];
-                for (int q = 0; q < P; ++q) {
-                    const double old = (q == c) ? 0.0 : A[q * P + p];
-                    A[q * P + p] = old - fr * A[q * P + c];
-                }
-            }
-            __syncthreads();
-        }
-        for (int c = P - 1; c >= 0; --c) {  // undo the row swaps as column swaps
-            const int pr = perm[c];
-            if (pr != c && act) {
-                const double tmp = A[c * P + p];
-                A[c * P + p] = A[pr * P + p];
-                A[pr * P + p] = tmp;
-            }
-            __syncthreads();
-        }
+        gj_invert(A, P, perm);
         if (act)
             for (int q = 0; q < P; ++q) minv[q * P + p] = A[q * P + p];
         __syncthreads();
@@ -690,6 +523,16 @@ __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const 
         *valid = 1;
         if (iters) *iters = it;
     }
+}
+
+template <typename T, bool DELTA>
+__global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const T> f,
+                                               const T *__restrict__ phk,
+                                               const T *__restrict__ base,
+                                               const double *__restrict__ lap1,
+                                               const double *__restrict__ lap3, double *minv,
+                                               int *valid, int *iters) {
+    coarse_body<T, DELTA>(op, u, f, phk, base, lap1, lap3, minv, valid, iters);
 }
 
 template <typename T, bool DELTA>
@@ -926,6 +769,191 @@ __global__ __launch_bounds__(kBlock) void k_zero(float *p, size_t count) {
 
 void launch_zero(hipStream_t s, float *p, size_t count) {
     hipLaunchKernelGGL(k_zero, dim3(blocks_for(count)), dim3(kBlock), 0, s, p, count);
+}
+
+// ----------------------------------------------------------- batched form
+//
+// One launch serves every instance that takes part in a multigrid phase: the
+// grid is the concatenation of each instance's blocks (its "segment"), a
+// workgroup finds its segment by a scan over the per-instance block counts,
+// and instances whose convergence flag is cleared return at once.
+
+__device__ __forceinline__ unsigned bseg_count(const BSeg &g, int kind) {
+    const unsigned n = (unsigned)g.op.lay.n, P = n * n * n;
+    switch (kind) {
+        case BK_SMOOTH: return P / 2;
+        case BK_RR: return (unsigned)(g.lay_c.n * g.lay_c.n * g.lay_c.n);
+        case BK_PROLONG: return (unsigned)g.lay_c.n * n * n;
+        default: return P;  // BK_TAU, BK_NORM
+    }
+}
+
+// Segment of workgroup blockIdx.x for a launch of `kind`; -1 past the end.
+__device__ __forceinline__ int bseg_find(const BSeg *segs, int nseg, int kind, unsigned &local) {
+    unsigned acc = 0;
+    const unsigned b = blockIdx.x, bd = blockDim.x;
+    for (int s = 0; s < nseg; ++s) {
+        const unsigned nb = (bseg_count(segs[s], kind) + bd - 1) / bd;
+        if (b < acc + nb) {
+            local = b - acc;
+            return s;
+        }
+        acc += nb;
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(512) void kb_smooth(const BSeg *segs, int nseg, int colour, int picard) {
+    unsigned lb;
+    const int s = bseg_find(segs, nseg, BK_SMOOTH, lb);
+    if (s < 0 || !*segs[s].active) return;
+    const BSeg &g = segs[s];
+    smooth_body<double, false>(g.op, colour, picard, g.u, cst(g.f), g.phk, nullptr,
+                               lb * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(512) void kb_resid_restrict(const BSeg *segs, int nseg) {
+    unsigned lb;
+    const int s = bseg_find(segs, nseg, BK_RR, lb);
+    if (s < 0 || !*segs[s].active) return;
+    const BSeg &g = segs[s];
+    resid_restrict_body<double, false>(g.op, g.lay_c, cst(g.u), cst(g.f), g.phk, nullptr, g.ubarc,
+                                       g.fc, lb * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(512) void kb_tau(const BSeg *segs, int nseg) {
+    unsigned lb;
+    const int s = bseg_find(segs, nseg, BK_TAU, lb);
+    if (s < 0 || !*segs[s].active) return;
+    const BSeg &g = segs[s];
+    tau_body<double, false>(g.op, cst(g.ubar), g.f, g.u, g.phk, nullptr, lb * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(512) void kb_prolong(const BSeg *segs, int nseg) {
+    unsigned lb;
+    const int s = bseg_find(segs, nseg, BK_PROLONG, lb);
+    if (s < 0 || !*segs[s].active) return;
+    const BSeg &g = segs[s];
+    prolong_body<double>(g.lay_c, g.op.lay, cst(g.uc), cst(g.ubarc), g.u, lb * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(64) void kb_coarse(const BSeg *segs, int nseg) {
+    const int s = blockIdx.x;
+    if (s >= nseg || !*segs[s].active) return;
+    const BSeg &g = segs[s];
+    coarse_body<double, false>(g.op, g.u, cst(g.f), g.phk, nullptr, g.lap1, g.lap3, g.minv, g.valid,
+                               g.iters);
+}
+
+// Per-block residual maxima of every instance's finest level (kBlock threads
+// per block, one point per thread); partial[] follows the segment order.
+__global__ __launch_bounds__(kBlock) void kb_norm(const BSeg *segs, int nseg,
+                                                  unsigned long long *partial) {
+    unsigned lb;
+    const int s = bseg_find(segs, nseg, BK_NORM, lb);
+    if (s < 0) return;
+    const BSeg &g = segs[s];
+    const unsigned t = lb * kBlock + threadIdx.x;
+    unsigned long long m = 0;
+    if (*g.active && t < bseg_count(g, BK_NORM))
+        m = resid_bits<double, false>(g.op, cst(g.u), cst(g.f), g.phk, nullptr,
+                                      Tri<double>{nullptr, nullptr, nullptr}, t);
+    m = block_max_u64(m);
+    if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+// Stop test of every instance (one wavefront per instance in turn): residual
+// max-norm from its partials, then the rule of the single-instance driver:
+// finished if the norm is at most tol (or not finite, or max_cycles cycles
+// were done), otherwise one more cycle is counted.  Also counts the
+// instances still active.
+__global__ __launch_bounds__(1024) void kb_update(const BSeg *segs, int nseg, const unsigned long long *partial,
+                                                  BState st, double tol, int max_cycles) {
+    __shared__ int live[1024 / 64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    int mine = 0;
+    for (int s = w; s < nseg; s += nw) {
+        const int i = segs[s].inst;
+        unsigned long long m = 0;
+        for (unsigned b = st.norm_first[s] + lane; b < st.norm_first[s] + st.norm_blocks[s]; b += 64)
+            m = umax(m, partial[b]);
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(m, off, 64);
+            m = umax(m, o);
+        }
+        if (lane == 0 && st.active[i]) {
+            const double r = __longlong_as_double((long long)m);
+            if (st.cycles[i] == 0) st.res0[i] = r;
+            st.res[i] = r;
+            if (!(r <= 1.7976931348623157e308)) {  // NaN or Inf
+                st.status[i] = PFC_ERR_NONFINITE;
+                st.active[i] = 0;
+            } else if (r <= tol) {
+                st.active[i] = 0;
+            } else if (st.cycles[i] == max_cycles) {
+                st.status[i] = PFC_ERR_NOT_CONVERGED;
+                st.active[i] = 0;
+            } else {
+                st.cycles[i] += 1;
+            }
+        }
+        if (lane == 0 && st.active[i]) ++mine;
+    }
+    if (lane == 0) live[w] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int q = 0; q < nw; ++q) tot += live[q];
+        *st.num_active = tot;
+    }
+}
+
+// Start of a time step: every instance active, counters cleared, cached
+// coarsest inverses invalidated.
+__global__ __launch_bounds__(kBlock) void kb_reset(BState st, int count, int **valid) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count) return;
+    st.active[i] = 1;
+    st.cycles[i] = 0;
+    st.status[i] = 0;
+    st.res0[i] = 0.0;
+    st.res[i] = 0.0;
+    *valid[i] = 0;
+}
+
+void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned blocks, int block,
+                  int colour, int picard) {
+    switch (kind) {
+        case BK_SMOOTH:
+            hipLaunchKernelGGL(kb_smooth, dim3(blocks), dim3(block), 0, s, segs, nseg, colour, picard);
+            break;
+        case BK_RR:
+            hipLaunchKernelGGL(kb_resid_restrict, dim3(blocks), dim3(block), 0, s, segs, nseg);
+            break;
+        case BK_TAU:
+            hipLaunchKernelGGL(kb_tau, dim3(blocks), dim3(block), 0, s, segs, nseg);
+            break;
+        case BK_PROLONG:
+            hipLaunchKernelGGL(kb_prolong, dim3(blocks), dim3(block), 0, s, segs, nseg);
+            break;
+        default: break;
+    }
+}
+
+void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg) {
+    hipLaunchKernelGGL(kb_coarse, dim3(nseg), dim3(64), 0, s, segs, nseg);
+}
+
+void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned blocks,
+                       unsigned long long *partial, BState st, double tol, int max_cycles) {
+    hipLaunchKernelGGL(kb_norm, dim3(blocks), dim3(kBlock), 0, s, segs, nseg, partial);
+    hipLaunchKernelGGL(kb_update, dim3(1), dim3(1024), 0, s, segs, nseg,
+                       (const unsigned long long *)partial, st, tol, max_cycles);
+}
+
+void launch_batch_reset(hipStream_t s, BState st, int count, int **valid) {
+    hipLaunchKernelGGL(kb_reset, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, st, count,
+                       valid);
 }
 
 // ------------------------------------------------------ instantiations

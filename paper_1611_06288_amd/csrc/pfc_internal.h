@@ -17,7 +17,7 @@ struct Tri {
 };
 
 template <typename T>
-inline Tri<const T> cst(Tri<T> t) { return Tri<const T>{t.a, t.b, t.c}; }
+__host__ __device__ inline Tri<const T> cst(Tri<T> t) { return Tri<const T>{t.a, t.b, t.c}; }
 
 // Division by n = 2^s or 3*2^s without integer divide instructions.
 struct Div {
@@ -123,5 +123,38 @@ int launch_resid_cast(hipStream_t s, const OpParams &op, Tri<const double> u, Tr
                       unsigned long long *partial);
 // Fills `count` floats with zero.
 void launch_zero(hipStream_t s, float *p, size_t count);
+
+
+// ---- batched form ----
+enum { BK_SMOOTH = 0, BK_RR = 1, BK_TAU = 2, BK_PROLONG = 3, BK_NORM = 4 };
+
+// One instance on one level, as seen by a batched launch.
+struct BSeg {
+    OpParams op;                 // this level
+    Lay lay_c;                   // next coarser level (restriction, interpolation)
+    Tri<double> u, f, ubar;      // this level
+    Tri<double> uc, fc, ubarc;   // next coarser level
+    double *phk;                 // phi^k on this level
+    const double *lap1, *lap3;   // coarsest-level matrices of this instance
+    double *minv;                // cached coarsest inverse
+    int *valid, *iters;
+    const int *active;           // the instance's convergence flag
+    int inst;
+};
+
+// Per-instance state of the batched stop test (device arrays).
+struct BState {
+    int *active, *cycles, *status;
+    double *res0, *res;
+    const unsigned *norm_first, *norm_blocks;  // per finest-level segment
+    int *num_active;
+};
+
+void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned blocks, int block,
+                  int colour, int picard);
+void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg);
+void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned blocks,
+                       unsigned long long *partial, BState st, double tol, int max_cycles);
+void launch_batch_reset(hipStream_t s, BState st, int count, int **valid);
 
 }  // namespace pfc

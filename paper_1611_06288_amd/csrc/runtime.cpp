@@ -335,7 +335,8 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
     ok = ok && dalloc(H, &H->d_scal, 16) && dalloc(H, &H->d_iters, 4);
     ok = ok && dalloc(H, &H->energy_part, (size_t)6 * kMaxReduceBlocks + 16);
     ok = ok && dalloc(H, &H->minv64, 64 * 64) && dalloc(H, &H->minv32, 64 * 64) &&
-         dalloc(H, &H->valid64, 4) && dalloc(H, &H->valid32, 4);
+         dalloc(H, &H->valid64, 4) && dalloc(H, &H->valid32, 4) &&
+         dalloc(H, &H->minv_adj, 64 * 64) && dalloc(H, &H->valid_adj, 4);
     std::vector<double> l1, l3;
     if (ok) {
         const Level &C = H->lev[H->nlev - 1];

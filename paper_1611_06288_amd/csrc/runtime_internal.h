@@ -61,6 +61,8 @@ struct pfc_handle {
     double *lap1 = nullptr, *lap3 = nullptr;
     double *minv64 = nullptr, *minv32 = nullptr;  // cached coarsest Newton inverses
     int *valid64 = nullptr, *valid32 = nullptr;
+    double *minv_adj = nullptr;  // cached coarsest inverse of the adjoint solve
+    int *valid_adj = nullptr;
     double *energy_part = nullptr;
     std::string err;
     // instrumentation

@@ -233,3 +233,78 @@ class Solver:
         cnt, ms, b = C.c_int64(), C.c_double(), C.c_double()
         self._check(self.lib.pfc_timing_get(self._h, kernel, C.byref(cnt), C.byref(ms), C.byref(b)))
         return cnt.value, ms.value, b.value
+
+
+class Batch:
+    """Many independent simulations advanced together (``pfc_batch_*``).
+
+    ``instances``: list of dicts with keys n, L, eps, dt.  The cycle
+    parameters (tol, nu1, nu2, cycle, lin, max_cycles) are shared."""
+
+    def __init__(self, instances, tol=1e-10, nu1=2, nu2=2, max_cycles=400, cycle="V",
+                 lin="newton", device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the PFC solver needs a GPU (torch.cuda.is_available() is False)")
+        self.lib = abi.lib()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.count = len(instances)
+        self.sizes = [int(p["n"]) for p in instances]
+        cfgs = (abi.PfcConfig * self.count)()
+        for c, p in zip(cfgs, instances):
+            c.n, c.nu1, c.nu2, c.max_cycles = int(p["n"]), nu1, nu2, max_cycles
+            c.cycle = {"V": abi.PFC_CYCLE_V, "F": abi.PFC_CYCLE_F}[cycle]
+            c.lin = {"newton": abi.PFC_LIN_NEWTON, "picard": abi.PFC_LIN_PICARD}[lin]
+            c.precision, c.reserved = abi.PFC_FP64, 0
+            c.L, c.eps, c.dt, c.tol = float(p["L"]), float(p["eps"]), float(p["dt"]), float(tol)
+        self._b = C.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        st = self.lib.pfc_batch_create(self.count, cfgs, C.c_void_p(stream), C.byref(self._b))
+        if st != abi.PFC_OK:
+            raise PFCError(st, self.lib.pfc_batch_last_error(None).decode())
+
+    def _check(self, st):
+        if st != abi.PFC_OK:
+            raise PFCError(st, self.lib.pfc_batch_last_error(self._b).decode())
+
+    def close(self):
+        if self._b:
+            self.lib.pfc_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_state(self, i, phi0):
+        self._check(self.lib.pfc_batch_init_state(self._b, i, _ptr(phi0, self.sizes[i] ** 3, "phi0")))
+
+    def set_state(self, i, phi_prev, phi_cur, mu, omega):
+        P = self.sizes[i] ** 3
+        self._check(self.lib.pfc_batch_set_state(self._b, i, _ptr(phi_prev, P, "phi_prev"),
+                                                 _ptr(phi_cur, P, "phi_cur"), _ptr(mu, P, "mu"),
+                                                 _ptr(omega, P, "omega")))
+
+    def get_state(self, i):
+        n = self.sizes[i]
+        out = [torch.empty((n, n, n), dtype=torch.float64, device=self.device) for _ in range(4)]
+        self._check(self.lib.pfc_batch_get_state(self._b, i, *[_ptr(t, n ** 3, "state") for t in out]))
+        return tuple(out)
+
+    def run(self, steps, raise_on_error=True):
+        """Returns infos[i][k] (instance i, step k)."""
+        infos = (abi.PfcStepInfo * (self.count * steps))()
+        st = self.lib.pfc_batch_run(self._b, steps, infos)
+        if raise_on_error:
+            self._check(st)
+        return [[StepInfo(infos[i * steps + k].cycles, infos[i * steps + k].status,
+                          infos[i * steps + k].res0, infos[i * steps + k].res_final)
+                 for k in range(steps)] for i in range(self.count)]
+
+    def autotune(self, cache_path=None):
+        """Workgroup sizes of (smooth, residual+coarsening, tau, interpolation)."""
+        chosen = (C.c_int32 * 4)()
+        path = None if cache_path is None else str(cache_path).encode()
+        self._check(self.lib.pfc_batch_autotune(self._b, path, chosen))
+        return list(chosen)

@@ -1,0 +1,101 @@
+"""Batched form: instances advanced together must follow exactly the
+single-instance solver (same kernels, same cycle sequence), and one of them
+the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cfas
+from paper_1611_06288_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def small_ensemble():
+    out = []
+    for i, n in enumerate([8, 12, 16, 24, 32, 48, 6, 32]):
+        g = inputs.rng(4000 + i)
+        eps = float(g.uniform(0.02, 0.3))
+        mean = float(g.uniform(0.05, 0.3))
+        L = n * math.pi / 4
+        phi0 = mean + 0.05 * g.uniform(-1, 1, (n, n, n))
+        out.append(dict(n=n, L=L, eps=eps, dt=0.1, phi0=phi0))
+    return out
+
+
+@pytest.mark.parametrize("cycle", ["V", "F"])
+def test_batch_matches_single_instances(cycle):
+    from paper_1611_06288_amd.solver import Batch, Solver
+    ens = small_ensemble()
+    steps = 3
+    b = Batch(ens, tol=1e-10, cycle=cycle)
+    for i, p in enumerate(ens):
+        b.init_state(i, dev(p["phi0"]))
+    infos = b.run(steps)
+    for i, p in enumerate(ens):
+        s = Solver(p["n"], p["L"], p["eps"], p["dt"], tol=1e-10, cycle=cycle)
+        prev, cur, mu, om, sinfos = s.simulate(dev(p["phi0"]), steps)
+        bprev, bcur, bmu, bom = b.get_state(i)
+        assert [x.cycles for x in infos[i]] == [x.cycles for x in sinfos], i
+        err = float((bcur - cur).abs().max() / cur.abs().max())
+        assert err <= 1e-13, (i, err)
+        assert float((bprev - prev).abs().max()) <= 1e-13 * float(prev.abs().max())
+        assert float((bmu - mu).abs().max()) <= 1e-12 * float(mu.abs().max())
+
+
+def test_batch_instance_matches_oracle_and_autotune_keeps_results(tmp_path):
+    from paper_1611_06288_amd.solver import Batch
+    ens = small_ensemble()[:5]
+    steps = 2
+    b = Batch(ens, tol=1e-10)                          # default workgroup sizes
+    b2 = Batch(ens, tol=1e-10)
+    tiles = b2.autotune(cache_path=tmp_path / "tiles.json")
+    assert all(t in (64, 128, 256, 512) for t in tiles)
+    assert (tmp_path / "tiles.json").exists()
+    b3 = Batch(ens, tol=1e-10)
+    assert b3.autotune(cache_path=tmp_path / "tiles.json") == tiles   # read back from the cache
+    b3.close()
+    for bb in (b, b2):
+        for i, p in enumerate(ens):
+            bb.init_state(i, dev(p["phi0"]))
+    i1 = b.run(steps)
+    i2 = b2.run(steps)          # per-point arithmetic does not depend on the tiles
+    for i, p in enumerate(ens):
+        assert [x.cycles for x in i1[i]] == [x.cycles for x in i2[i]]
+        assert torch.equal(b.get_state(i)[1], b2.get_state(i)[1])
+    # instance 3 (24^3) against the oracle
+    p = ens[3]
+    phis, oinfos, _ = cfas.simulate(p["phi0"], p["L"], p["eps"], p["dt"], steps, tol=1e-10)
+    got = b.get_state(3)[1].cpu().numpy()
+    assert [x.cycles for x in i1[3]] == [x.cycles for x in oinfos]
+    assert np.max(np.abs(got - phis[-1])) / np.max(np.abs(phis[-1])) < 1e-11
+
+
+def test_batch_64_instances_uneven():
+    """The 64-instance ensemble (n in {32,48,64,96}, eps in [0.02,0.3]) for two
+    steps; four instances, one of each size, against single-instance runs."""
+    from paper_1611_06288_amd.solver import Batch, Solver
+    ens = inputs.batched_ensemble(64, steps=2)
+    params = [dict(n=e.params.n, L=e.params.L, eps=e.params.eps, dt=e.params.dt) for e in ens]
+    b = Batch(params, tol=1e-10)
+    for i, e in enumerate(ens):
+        b.init_state(i, dev(e.phi0()))
+    infos = b.run(2)
+    assert all(x.status == 0 and x.res_final <= 1e-10 for row in infos for x in row)
+    seen = set()
+    for i, e in enumerate(ens):
+        if e.params.n in seen:
+            continue
+        seen.add(e.params.n)
+        p = e.params
+        s = Solver(p.n, p.L, p.eps, p.dt, tol=1e-10)
+        _, cur, _, _, sinfos = s.simulate(dev(e.phi0()), 2)
+        assert [x.cycles for x in infos[i]] == [x.cycles for x in sinfos]
+        assert float((b.get_state(i)[1] - cur).abs().max()) <= 1e-13 * float(cur.abs().max())
+    assert seen == {32, 48, 64, 96}
