@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=3,
                     help="oracle cycles timed for the CPU baseline (0 disables it)")
+    ap.add_argument("--batch-steps", type=int, default=6,
+                    help="time steps of the 64-instance batched ensemble (0 skips it)")
+    ap.add_argument("--adjoint-steps", type=int, default=20,
+                    help="time steps of the 64^3 differentiated rollout (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device-to-device copy (bandwidth ceiling and "
                          "counter calibration) and exit")
@@ -135,6 +139,66 @@ def run_path(Solver, abi, torch, precision, state0, p, steps, warmup, cycle):
     return res, phis
 
 
+def run_batched(torch, inputs, steps, warmup=1):
+    """64 instances, n in {32,48,64,96}, eps in [0.02,0.3], s = 0.1, V(2,2) to
+    1e-10, workgroup sizes from the autotuner.  Returns rates aggregated over
+    the instances."""
+    from paper_1611_06288_amd.solver import Batch
+    ens = inputs.batched_ensemble(64, steps=steps)
+    params = [dict(n=e.params.n, L=e.params.L, eps=e.params.eps, dt=e.params.dt) for e in ens]
+    b = Batch(params, tol=1e-10)
+    tiles = b.autotune()
+    for i, e in enumerate(ens):
+        b.init_state(i, torch.from_numpy(e.phi0()).cuda())
+    if warmup:
+        b.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = b.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pts = sum(e.params.n ** 3 for e in ens)
+    cyc = [sum(x.cycles for x in row) for row in infos]
+    b.close()
+    return {
+        "instances": len(ens), "steps": steps, "grid_points": pts,
+        "sizes": {str(n): sum(1 for e in ens if e.params.n == n) for n in (32, 48, 64, 96)},
+        "instance_steps_per_s": round(len(ens) * steps / dt, 3),
+        "batch_steps_per_s": round(steps / dt, 4),
+        "v_cycles_per_s_summed": round(sum(cyc) / dt, 2),
+        "mean_cycles_per_instance_step": round(sum(cyc) / (len(ens) * steps), 2),
+        "max_cycles_per_step": max(max(x.cycles for x in row) for row in infos),
+        "autotuned_workgroup_sizes": dict(zip(["smooth", "resid_restrict", "tau", "prolong"], tiles)),
+    }
+
+
+def run_adjoint(torch, inputs, steps):
+    """d loss / d (phi0, eps) through `steps` steps at 64^3 (eps = 0.1,
+    s = 0.1, checkpoints every 5 steps), forward and adjoint to 1e-10."""
+    from paper_1611_06288_amd.autograd import rollout
+    p = inputs.adjoint_params(64)
+    params = dict(n=p.n, L=p.L, dt=p.dt, tol=1e-10, max_cycles=1000, adj_tol=1e-10)
+    phi0 = torch.from_numpy(inputs.adjoint_phi0(64, seed=5)).cuda()
+    with torch.no_grad():
+        tgt = rollout(torch.from_numpy(inputs.adjoint_phi0(64, seed=6)).cuda(),
+                      torch.tensor(0.12, dtype=torch.float64), params, steps)
+    p0 = phi0.clone().requires_grad_(True)
+    e = torch.tensor(p.eps, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = rollout(p0, e, params, steps, ckpt_every=5)
+    loss = ((out - tgt) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"n": 64, "steps": steps, "forward_s": round(t1 - t0, 4),
+            "backward_s": round(t2 - t1, 4),
+            "gradient_steps_per_s": round(steps / (t2 - t0), 3),
+            "loss": float(loss.detach()), "dloss_deps": float(e.grad)}
+
+
 def cpu_baseline(cfas, phi0, p, cycles, cycles_per_step):
     """Times the CPU oracle for `cycles` V(2,2) cycles of the first step."""
     n = phi0.shape[0]
@@ -218,6 +282,13 @@ def main():
         except PFCError as e:
             mixed = {"unavailable": str(e)}
 
+    batched = run_batched(torch, inputs, args.batch_steps) if args.batch_steps > 0 else None
+    if batched:
+        print(f"batched: {batched['instance_steps_per_s']} instance-steps/s", file=sys.stderr, flush=True)
+    adjoint = run_adjoint(torch, inputs, args.adjoint_steps) if args.adjoint_steps > 0 else None
+    if adjoint:
+        print(f"adjoint: {adjoint['gradient_steps_per_s']} steps/s", file=sys.stderr, flush=True)
+
     sm = fp64["kernels"].get("smooth0", {})
     achieved = sm.get("achieved_GBps")
     roofline = {
@@ -263,6 +334,8 @@ def main():
         "cycles_per_step": fp64["cycles_per_step"],
         "kernels": fp64["kernels"],
         "mixed": mixed,
+        "batched": batched,
+        "adjoint": adjoint,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
