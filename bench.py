@@ -292,7 +292,7 @@ def main():
     sm = fp64["kernels"].get("smooth0", {})
     achieved = sm.get("achieved_GBps")
     roofline = {
-        "kernel": "finest-level red-black smoother (one half-sweep per launch)",
+        "kernel": "finest-level fused red-black sweep (one full sweep per launch, 72 B/pt)",
         "bound": "hbm",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,

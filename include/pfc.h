@@ -170,7 +170,11 @@ pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const do
                         const double *phk, double *r3, double *maxnorm);
 
 /* One red-black half-sweep (Section 5 smoothing scheme, red-black order) of
- * colour `colour` ((i+j+k) mod 2) at level l, in place on u3. */
+ * colour `colour` ((i+j+k) mod 2) at level l, in place on u3; with colour =
+ * PFC_SWEEP_FULL, one full sweep (colour 0, then colour 1), the form the
+ * cycles use: on levels of at least 128^3 with n a multiple of 64 it runs as
+ * a single fused pass whose result equals the two half-sweeps bit for bit. */
+#define PFC_SWEEP_FULL 2
 pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3,
                       const double *f3, const double *phk);
 

@@ -20,6 +20,7 @@ PFC_ERR_OOM = 5
 PFC_FP64, PFC_MIXED = 0, 1
 PFC_CYCLE_V, PFC_CYCLE_F = 0, 1
 PFC_LIN_NEWTON, PFC_LIN_PICARD = 0, 1
+PFC_SWEEP_FULL = 2
 
 PFC_KERNEL_SMOOTH0 = 0
 PFC_KERNEL_RESIDUAL0 = 1

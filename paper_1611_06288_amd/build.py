@@ -20,7 +20,10 @@ ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "runtime.cpp", "mixed.cpp", "adjoint.hip", "batch.cpp"]
 
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# Contraction off: every kernel evaluates a formula exactly as written, so
+# kernels that share a formula (the half-sweep and the fused sweep) agree
+# bitwise.
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -146,6 +146,7 @@ void bcycle(pfc_batch *B, int d, bool fcycle) {
                  B->tile[BK_TAU], 0, 0);
     bcycle(B, d + 1, fcycle);
     if (fcycle) bcycle(B, d + 1, false);
+    launch_batch(s, BK_ERR, B->d_mid[d], nm, blocks_of(mid, BK_RR, B->tile[BK_RR]), B->tile[BK_RR], 0, 0);
     launch_batch(s, BK_PROLONG, B->d_mid[d], nm, blocks_of(mid, BK_PROLONG, B->tile[BK_PROLONG]),
                  B->tile[BK_PROLONG], 0, 0);
     for (int q = 0; q < B->cfg.nu2; ++q) sweep();

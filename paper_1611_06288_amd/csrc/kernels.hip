@@ -18,6 +18,9 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <numeric>
+
 namespace pfc {
 
 // ------------------------------------------------------------------ layout
@@ -54,6 +57,30 @@ Lay make_lay(int n, bool split) {
 // c is the linearised slope of the cubic term; eliminating omega and mu gives
 // phi = (r1 - A r2 + A B r3) / (1 + A (c + B Dd)).
 // One thread per point of colour `colour` (colour-split storage only).
+template <bool DELTA>
+__device__ __forceinline__ void point_solve(const OpParams &op, int picard, double phin, double a,
+                                            double b, double f1, double f2, double f3, double smu,
+                                            double som, double sphi, double &phi, double &mu,
+                                            double &om) {
+    const double h2inv = op.h2inv, tau = op.tau, lin_c = 0.5 * (1.0 - op.eps);
+    double c, r2;
+    if (!DELTA && picard) {
+        const double qq = 0.25 * (phin * phin + a * a);
+        c = qq + lin_c;
+        r2 = f2 + som * h2inv + qq * a;
+    } else {
+        const double gp = Cubic<DELTA>::dg(phin, a, b);
+        c = gp + lin_c;
+        r2 = f2 + som * h2inv + (Cubic<DELTA>::g(phin, a, b) - gp * phin);
+    }
+    const double r1 = f1 + tau * smu * h2inv;
+    const double r3 = f3 + 0.5 * sphi * h2inv;
+    const double A = 6.0 * tau * h2inv, B = 6.0 * h2inv, Dd = 3.0 * h2inv;
+    phi = (r1 - A * r2 + A * B * r3) / (1.0 + A * (c + B * Dd));
+    om = r3 - Dd * phi;
+    mu = r2 + c * phi - B * om;
+}
+
 template <typename T, bool DELTA>
 __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int picard, Tri<T> u,
                                             Tri<const T> f, const T *__restrict__ phk,
@@ -84,25 +111,10 @@ __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int 
                        ((double)u.c[zp] + (double)u.c[zm]);
     const double sphi = ((double)u.a[xp] + (double)u.a[xm]) + ((double)u.a[yp] + (double)u.a[ym]) +
                         ((double)u.a[zp] + (double)u.a[zm]);
-    const double phin = u.a[own], a = phk[own];
-    const double b = DELTA ? (double)base[own] : 0.0;
-    const double h2inv = op.h2inv, tau = op.tau, lin_c = 0.5 * (1.0 - op.eps);
-    double c, r2;
-    if (!DELTA && picard) {
-        const double qq = 0.25 * (phin * phin + a * a);
-        c = qq + lin_c;
-        r2 = (double)f.b[own] + som * h2inv + qq * a;
-    } else {
-        const double gp = Cubic<DELTA>::dg(phin, a, b);
-        c = gp + lin_c;
-        r2 = (double)f.b[own] + som * h2inv + (Cubic<DELTA>::g(phin, a, b) - gp * phin);
-    }
-    const double r1 = (double)f.a[own] + tau * smu * h2inv;
-    const double r3 = (double)f.c[own] + 0.5 * sphi * h2inv;
-    const double A = 6.0 * tau * h2inv, B = 6.0 * h2inv, Dd = 3.0 * h2inv;
-    const double phi = (r1 - A * r2 + A * B * r3) / (1.0 + A * (c + B * Dd));
-    const double om = r3 - Dd * phi;
-    const double mu = r2 + c * phi - B * om;
+    double phi, mu, om;
+    point_solve<DELTA>(op, picard, (double)u.a[own], (double)phk[own],
+                       DELTA ? (double)base[own] : 0.0, (double)f.a[own], (double)f.b[own],
+                       (double)f.c[own], smu, som, sphi, phi, mu, om);
     u.a[own] = (T)phi;
     u.b[own] = (T)mu;
     u.c[own] = (T)om;
@@ -121,6 +133,254 @@ void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tr
     const size_t H = npts_host(op.lay) / 2;
     hipLaunchKernelGGL((k_smooth<T, DELTA>), dim3(blocks_for(H)), dim3(kBlock), 0, s, op, colour,
                        picard, u, f, phk, base);
+}
+
+// ------------------------------------------------- fused red-black sweep
+//
+// One full red-black sweep in one pass, from u_in to u_out (two buffers;
+// colour-split storage).  A workgroup owns an x-y column of kFX x kFY points
+// and a range [z0, z1) of planes, and walks it in z.  At step k it
+//   * computes the new colour-0 values of plane k on its box plus a one-cell
+//     ring in x and y (the ring cells, and the planes z0-1 and z1, belong to
+//     other workgroups, which compute the same values; they are not written)
+//     into a 3-plane LDS ring, reading the old colour-1 neighbours from a
+//     second 3-plane LDS ring (box plus a two-cell ring) that holds every
+//     old colour-1 value of the column exactly once;
+//   * computes the new colour-1 values of plane k-1 on its box, whose six
+//     colour-0 neighbours are all in the first ring.
+// The old colour-1 plane k+2 and the own-point inputs of the next step are
+// loaded into registers while step k computes, so each thread keeps its
+// next loads in flight across both barriers.
+// Each point sees the neighbour values of the two half-sweeps (old colour 1
+// for colour 0, new colour 0 for colour 1) and the same arithmetic, so, with
+// floating-point contraction off, the result is bitwise that of two
+// launch_smooth calls, while each field is read and written once.
+constexpr int kFX = 64, kFY = 8, kFT = 256;  // column extents, threads per workgroup
+constexpr int kFSl = kFX / 2 + 1;            // colour-0 ring: points per row
+constexpr int kFRw = kFY + 2;                //                rows
+constexpr int kFCs = kFX / 2 + 2;            // colour-1 ring: points per row
+constexpr int kFCr = kFY + 4;                //                rows
+constexpr int kFNr = kFSl * kFRw, kFNb = (kFX / 2) * kFY, kFNc = kFCs * kFCr;
+constexpr int kFIr = (kFNr + kFT - 1) / kFT, kFIb = (kFNb + kFT - 1) / kFT,
+              kFIc = (kFNc + kFT - 1) / kFT;  // items per thread in each phase
+
+template <typename T, bool DELTA>
+__global__ __launch_bounds__(kFT) void k_sweep_fused(
+    OpParams op, int picard, int nz, const T *__restrict__ ua, const T *__restrict__ ub,
+    const T *__restrict__ uc, T *__restrict__ oa, T *__restrict__ ob, T *__restrict__ oc,
+    const T *__restrict__ fa, const T *__restrict__ fb, const T *__restrict__ fc,
+    const T *__restrict__ phk, const T *__restrict__ base) {
+    __shared__ T c1[3][3][kFCr][kFCs];   // [field][plane slot][row][point] old colour 1
+    __shared__ T red[3][3][kFRw][kFSl];  // [field][plane slot][row][point] new colour 0
+    const int n = op.lay.n, hn = n >> 1;
+    const unsigned un = (unsigned)n, uhn = (unsigned)hn, H = un * un * uhn;
+    const int nbx = n / kFX, nby = n / kFY;
+    const int b = (int)xcd_block();
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int x0 = bx * kFX, y0 = by * kFY;
+    const int z0 = bz * n / nz, z1 = (bz + 1) * n / nz;
+    const int tid = threadIdx.x;
+    // one-step periodic wraps (every coordinate below is within one period)
+    auto wn = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+    auto wh = [hn](int v) { return v < 0 ? v + hn : (v >= hn ? v - hn : v); };
+    auto cslot = [z0](int p) { return (p - z0 + 3) % 3; };  // colour-1 ring slot of plane p
+    auto rslot = [z0](int p) { return (p - z0 + 1) % 3; };  // colour-0 ring slot of plane p
+
+    // old colour-1 values of one plane (box plus two-cell ring), in registers
+    T cn[kFIc][3];
+    auto load_c1 = [&](int p) {
+        const unsigned pw = (unsigned)wn(p);
+#pragma unroll
+        for (int i = 0; i < kFIc; ++i) {
+            const int c = tid + i * kFT;
+            if (c < kFNc) {
+                const int cr = c / kFCs, cs = c - cr * kFCs;
+                const unsigned g = H + (pw * un + (unsigned)wn(y0 - 2 + cr)) * uhn +
+                                   (unsigned)wh(x0 / 2 - 1 + cs);
+                cn[i][0] = ua[g];
+                cn[i][1] = ub[g];
+                cn[i][2] = uc[g];
+            }
+        }
+    };
+    auto store_c1 = [&](int p) {
+        const int s = cslot(p);
+#pragma unroll
+        for (int i = 0; i < kFIc; ++i) {
+            const int c = tid + i * kFT;
+            if (c < kFNc) {
+                const int cr = c / kFCs, cs = c - cr * kFCs;
+                c1[0][s][cr][cs] = cn[i][0];
+                c1[1][s][cr][cs] = cn[i][1];
+                c1[2][s][cr][cs] = cn[i][2];
+            }
+        }
+    };
+    // own inputs of the colour-0 points of plane k (box plus ring)
+    T ro[kFIr][6];
+    unsigned rg[kFIr];
+    auto load_red = [&](int k) {
+        const unsigned kw = (unsigned)wn(k);
+#pragma unroll
+        for (int i = 0; i < kFIr; ++i) {
+            const int q = tid + i * kFT;
+            if (q < kFNr) {
+                const int r = q / kFSl, sl = q - r * kFSl;
+                const int y = y0 - 1 + r;
+                const int x = x0 - 1 + ((x0 - 1 + y + k) & 1) + 2 * sl;
+                const unsigned g = (kw * un + (unsigned)wn(y)) * uhn + (unsigned)(wn(x) >> 1);
+                rg[i] = g;
+                ro[i][0] = ua[g];
+                ro[i][1] = phk[g];
+                ro[i][2] = DELTA ? base[g] : (T)0;
+                ro[i][3] = fa[g];
+                ro[i][4] = fb[g];
+                ro[i][5] = fc[g];
+            }
+        }
+    };
+    // own inputs of the colour-1 points of plane kb (box); old phi comes from LDS
+    T bo[kFIb][5];
+    T bphi[kFIb];
+    auto load_black = [&](int kb) {
+#pragma unroll
+        for (int i = 0; i < kFIb; ++i) {
+            const int q = tid + i * kFT;
+            if (q < kFNb) {
+                const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
+                const int y = y0 + rb;
+                const int x = x0 + ((x0 + y + kb + 1) & 1) + 2 * s;
+                const unsigned g = H + ((unsigned)kb * un + (unsigned)y) * uhn + (unsigned)(x >> 1);
+                bo[i][0] = phk[g];
+                bo[i][1] = DELTA ? base[g] : (T)0;
+                bo[i][2] = fa[g];
+                bo[i][3] = fb[g];
+                bo[i][4] = fc[g];
+            }
+        }
+    };
+
+    load_c1(z0 - 2);
+    store_c1(z0 - 2);
+    load_c1(z0 - 1);
+    store_c1(z0 - 1);
+    load_c1(z0);
+    load_red(z0 - 1);
+    for (int k = z0 - 1; k <= z1; ++k) {
+        const int kb = k - 1;  // plane of this step's colour-1 points
+        store_c1(k + 1);       // its slot last held plane k-2, finished in the previous step
+        if (kb >= z0) load_black(kb);
+        __syncthreads();
+        // colour 0, plane k
+        const int sk = cslot(k), skm = cslot(k - 1), skp = cslot(k + 1), rq = rslot(k);
+#pragma unroll
+        for (int i = 0; i < kFIr; ++i) {
+            const int q = tid + i * kFT;
+            if (q < kFNr) {
+                const int r = q / kFSl, sl = q - r * kFSl;
+                const int y = y0 - 1 + r;
+                const int x = x0 - 1 + ((x0 - 1 + y + k) & 1) + 2 * sl;
+                // ring column of x and of its x-neighbours (colour-1 point m = x' >> 1)
+                const int cx = (x - x0 + 2) >> 1, cxm = (x - x0 + 1) >> 1, cxp = (x - x0 + 3) >> 1;
+                double s3[3];
+#pragma unroll
+                for (int fl = 0; fl < 3; ++fl)
+                    s3[fl] = ((double)c1[fl][sk][r + 1][cxp] + (double)c1[fl][sk][r + 1][cxm]) +
+                             ((double)c1[fl][sk][r + 2][cx] + (double)c1[fl][sk][r][cx]) +
+                             ((double)c1[fl][skp][r + 1][cx] + (double)c1[fl][skm][r + 1][cx]);
+                double phi, mu, om;
+                point_solve<DELTA>(op, picard, (double)ro[i][0], (double)ro[i][1],
+                                   (double)ro[i][2], (double)ro[i][3], (double)ro[i][4],
+                                   (double)ro[i][5], s3[1], s3[2], s3[0], phi, mu, om);
+                const T tphi = (T)phi, tmu = (T)mu, tom = (T)om;
+                red[0][rq][r][sl] = tphi;
+                red[1][rq][r][sl] = tmu;
+                red[2][rq][r][sl] = tom;
+                if (x >= x0 && x < x0 + kFX && y >= y0 && y < y0 + kFY && k >= z0 && k < z1) {
+                    oa[rg[i]] = tphi;
+                    ob[rg[i]] = tmu;
+                    oc[rg[i]] = tom;
+                }
+            }
+        }
+        // old phi of this step's colour-1 points, read before their slot is reused
+        if (kb >= z0) {
+            const int sb = cslot(kb);
+#pragma unroll
+            for (int i = 0; i < kFIb; ++i) {
+                const int q = tid + i * kFT;
+                if (q < kFNb) {
+                    const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
+                    const int x = x0 + ((x0 + y0 + rb + kb + 1) & 1) + 2 * s;
+                    bphi[i] = c1[0][sb][rb + 2][(x - x0 + 2) >> 1];
+                }
+            }
+        }
+        if (k + 2 <= z1 + 1) load_c1(k + 2);
+        if (k + 1 <= z1) load_red(k + 1);
+        __syncthreads();
+        // colour 1, plane kb
+        if (kb >= z0) {
+            const int qm = rslot(kb - 1), q0 = rslot(kb), qp = rq;
+#pragma unroll
+            for (int i = 0; i < kFIb; ++i) {
+                const int q = tid + i * kFT;
+                if (q < kFNb) {
+                    const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
+                    const int y = y0 + rb;
+                    const int x = x0 + ((x0 + y + kb + 1) & 1) + 2 * s;
+                    const unsigned g =
+                        H + ((unsigned)kb * un + (unsigned)y) * uhn + (unsigned)(x >> 1);
+                    const int s0 = (x - x0 + 1) >> 1, sm = (x - x0) >> 1, sp = (x - x0 + 2) >> 1;
+                    const int rr = rb + 1;
+                    double s3[3];
+#pragma unroll
+                    for (int fl = 0; fl < 3; ++fl)
+                        s3[fl] = ((double)red[fl][q0][rr][sp] + (double)red[fl][q0][rr][sm]) +
+                                 ((double)red[fl][q0][rr + 1][s0] + (double)red[fl][q0][rr - 1][s0]) +
+                                 ((double)red[fl][qp][rr][s0] + (double)red[fl][qm][rr][s0]);
+                    double phi, mu, om;
+                    point_solve<DELTA>(op, picard, (double)bphi[i], (double)bo[i][0],
+                                       (double)bo[i][1], (double)bo[i][2], (double)bo[i][3],
+                                       (double)bo[i][4], s3[1], s3[2], s3[0], phi, mu, om);
+                    oa[g] = (T)phi;
+                    ob[g] = (T)mu;
+                    oc[g] = (T)om;
+                }
+            }
+        }
+    }
+}
+
+bool fused_fits(int n) { return n % kFX == 0 && n % kFY == 0 && n >= kFusedMinN; }
+
+int fused_slots(int device) {
+    int occ = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (k_sweep_fused<double, false>), kFT, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    return occ * cus;
+}
+
+// z-split of a level: the smallest number of plane ranges for which the launch
+// is a whole number of resident waves (slots workgroups each), with at least 4
+// planes per range; a partly filled last wave costs as much as a full one.
+int fused_nz(int n, int slots) {
+    const int cols = (n / kFX) * (n / kFY);
+    if (slots <= 0) return std::max(1, n / 16);
+    int nz = slots / std::gcd(cols, slots);
+    if (n / nz < 4) nz = std::max(1, n / 4);
+    return nz;
+}
+
+template <typename T, bool DELTA>
+void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
+                        Tri<T> uout, Tri<const T> f, const T *phk, const T *base) {
+    const int n = op.lay.n;
+    const unsigned blocks = (unsigned)((n / kFX) * (n / kFY) * nz);
+    hipLaunchKernelGGL((k_sweep_fused<T, DELTA>), dim3(blocks), dim3(kFT), 0, s, op, picard, nz,
+                       uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b, f.c, phk, base);
 }
 
 // ------------------------------------------------------------ residual
@@ -370,6 +630,20 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
     }
 }
 
+// ubar <- v - ubar on the coarse level (the correction to interpolate).
+template <typename T>
+__device__ __forceinline__ void coarse_err_body(size_t P, Tri<const T> v, Tri<T> ubar, unsigned t) {
+    if (t >= P) return;
+    ubar.a[t] = (T)((double)v.a[t] - (double)ubar.a[t]);
+    ubar.b[t] = (T)((double)v.b[t] - (double)ubar.b[t]);
+    ubar.c[t] = (T)((double)v.c[t] - (double)ubar.c[t]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_err(size_t P, Tri<const T> v, Tri<T> ubar) {
+    coarse_err_body<T>(P, v, ubar, xcd_block() * kBlock + threadIdx.x);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T> v, Tri<const T> ubar,
                                                     Tri<T> fine) {
@@ -380,6 +654,16 @@ template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
                     Tri<const T> ubar, Tri<T> fine_u) {
     const size_t pairs = (size_t)coarse.n * fine.n * fine.n;
+    if (ubar.a && fine_u.b) {
+        // e = v - ubar once on the coarse level (in place of ubar), so the
+        // fine-level pass loads one coarse array instead of two
+        Tri<T> e{const_cast<T *>(ubar.a), const_cast<T *>(ubar.b), const_cast<T *>(ubar.c)};
+        hipLaunchKernelGGL((k_coarse_err<T>), dim3(blocks_for(npts_host(coarse))), dim3(kBlock), 0, s,
+                           npts_host(coarse), v, e);
+        hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine,
+                           cst(e), Tri<const T>{nullptr, nullptr, nullptr}, fine_u);
+        return;
+    }
     hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine, v,
                        ubar, fine_u);
 }
@@ -829,12 +1113,21 @@ __global__ __launch_bounds__(512) void kb_tau(const BSeg *segs, int nseg) {
     tau_body<double, false>(g.op, cst(g.ubar), g.f, g.u, g.phk, nullptr, lb * blockDim.x + threadIdx.x);
 }
 
+__global__ __launch_bounds__(512) void kb_coarse_err(const BSeg *segs, int nseg) {
+    unsigned lb;
+    const int s = bseg_find(segs, nseg, BK_RR, lb);   // one thread per coarse point
+    if (s < 0 || !*segs[s].active) return;
+    const BSeg &g = segs[s];
+    coarse_err_body<double>(npts(g.lay_c), cst(g.uc), g.ubarc, lb * blockDim.x + threadIdx.x);
+}
+
 __global__ __launch_bounds__(512) void kb_prolong(const BSeg *segs, int nseg) {
     unsigned lb;
     const int s = bseg_find(segs, nseg, BK_PROLONG, lb);
     if (s < 0 || !*segs[s].active) return;
     const BSeg &g = segs[s];
-    prolong_body<double>(g.lay_c, g.op.lay, cst(g.uc), cst(g.ubarc), g.u, lb * blockDim.x + threadIdx.x);
+    prolong_body<double>(g.lay_c, g.op.lay, cst(g.ubarc), Tri<const double>{nullptr, nullptr, nullptr},
+                         g.u, lb * blockDim.x + threadIdx.x);
 }
 
 __global__ __launch_bounds__(64) void kb_coarse(const BSeg *segs, int nseg) {
@@ -936,6 +1229,9 @@ void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned 
         case BK_PROLONG:
             hipLaunchKernelGGL(kb_prolong, dim3(blocks), dim3(block), 0, s, segs, nseg);
             break;
+        case BK_ERR:
+            hipLaunchKernelGGL(kb_coarse_err, dim3(blocks), dim3(block), 0, s, segs, nseg);
+            break;
         default: break;
     }
 }
@@ -975,6 +1271,9 @@ void launch_batch_reset(hipStream_t s, BState st, int count, int **valid) {
 
 PFC_INST(double, false)
 PFC_INST(float, true)
+template void launch_sweep_fused<double, false>(hipStream_t, const OpParams &, int, int,
+                                                Tri<const double>, Tri<double>, Tri<const double>,
+                                                const double *, const double *);
 template void launch_restrict<double>(hipStream_t, const Lay &, const Lay &, const double *, double *);
 template void launch_restrict<float>(hipStream_t, const Lay &, const Lay &, const float *, float *);
 template void launch_prolong<double>(hipStream_t, const Lay &, const Lay &, Tri<const double>,

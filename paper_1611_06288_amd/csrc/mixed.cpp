@@ -12,6 +12,7 @@
 // smoother's pointwise 3x3 solve, the residual and all reductions run in
 // FP64 arithmetic; only stored fields of the correction cycle are FP32.
 #include <cmath>
+#include <utility>
 
 #include "runtime_internal.h"
 
@@ -118,15 +119,20 @@ pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_c
     return status;
 }
 
-// Algorithmic HBM bytes per finest-level launch.  A full red-black sweep must
-// read u (3 fields), f (3) and phi^k (1) and write u (3): 80 B per point in
-// FP64; the FP32 correction sweep also reads the base b: 11 values of 4 B =
-// 44 B.  Each half-sweep launch is credited half a sweep.
+// Algorithmic HBM bytes per finest-level launch: each value the launch must
+// read or write, once.  A fused FP64 sweep reads the old phi everywhere, the
+// old mu and omega at colour-1 points only (colour 0's are overwritten
+// unread), f (3 fields) and phi^k, and writes u: 8 + 8 + 24 + 8 + 24 = 72 B
+// per point.  A half-sweep launch updates one colour: the other colour's
+// three fields and its own old phi, f, phi^k and new u, i.e. 44 B per point
+// of the level in FP64, and 24 B in the FP32 correction form (4 B values,
+// plus the base).
 double algorithmic_bytes(const pfc_handle *H, int kernel) {
     const double P = (double)H->lev[0].P;
     const bool mixed = H->cfg.precision == PFC_MIXED;
+    const double smooth = mixed ? 24.0 : (H->lev[0].fused ? 72.0 : 44.0);
     switch (kernel) {
-        case PFC_KERNEL_SMOOTH0: return (mixed ? 22.0 : 40.0) * P;
+        case PFC_KERNEL_SMOOTH0: return smooth * P;
         case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0) * P;
         case PFC_KERNEL_PROLONG0: return (mixed ? 27.0 : 54.0) * P;
         case PFC_KERNEL_NORM0: return (mixed ? 72.0 : 56.0) * P;

@@ -54,7 +54,7 @@ struct OpParams {
 };
 
 constexpr int kBlock = 256;
-constexpr int kMaxReduceBlocks = 2048;
+constexpr int kMaxReduceBlocks = 16384;
 constexpr int kMaxN = 1024;
 
 // ---- building blocks; T = double or float, DELTA selects the correction
@@ -62,6 +62,18 @@ constexpr int kMaxN = 1024;
 template <typename T, bool DELTA>
 void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
                    Tri<const T> f, const T *phk, const T *base);
+
+// One full red-black sweep (colour 0 then colour 1) from uin into uout
+// (distinct buffers, colour-split storage), bitwise equal to two launch_smooth
+// calls; the level is cut into nz plane ranges (see fused_nz).  Instantiated
+// for double only.
+template <typename T, bool DELTA>
+void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
+                        Tri<T> uout, Tri<const T> f, const T *phk, const T *base);
+bool fused_fits(int n);           // n admits the fused sweep's column tiling
+int fused_slots(int device);      // resident fused-sweep workgroups on the device (0 on error)
+int fused_nz(int n, int slots);   // plane ranges per column for a level of size n
+constexpr int kFusedMinN = 128;  // smaller levels use the half-sweeps
 
 template <typename T, bool DELTA>
 void launch_resid_restrict(hipStream_t s, const OpParams &op, const Lay &coarse, Tri<const T> u,
@@ -126,7 +138,7 @@ void launch_zero(hipStream_t s, float *p, size_t count);
 
 
 // ---- batched form ----
-enum { BK_SMOOTH = 0, BK_RR = 1, BK_TAU = 2, BK_PROLONG = 3, BK_NORM = 4 };
+enum { BK_SMOOTH = 0, BK_RR = 1, BK_TAU = 2, BK_PROLONG = 3, BK_NORM = 4, BK_ERR = 5 };
 
 // One instance on one level, as seen by a batched launch.
 struct BSeg {

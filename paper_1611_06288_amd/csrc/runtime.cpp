@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -188,6 +189,14 @@ namespace pfc {
 static void sweep64(pfc_handle *H, int l) {
     Level &A = H->lev[l];
     const OpParams op = op_of(H, l);
+    if (A.fused) {  // one pass, then the two iterate buffers trade places
+        H->begin_timed(PFC_KERNEL_SMOOTH0, l);
+        launch_sweep_fused<double, false>(H->stream, op, H->cfg.lin == PFC_LIN_PICARD, A.nz,
+                                          cst(A.u), A.u2, cst(A.f), A.phk, nullptr);
+        H->end_timed();
+        std::swap(A.u, A.u2);
+        return;
+    }
     for (int colour = 0; colour < 2; ++colour) {
         H->begin_timed(PFC_KERNEL_SMOOTH0, l);
         launch_smooth<double, false>(H->stream, op, colour, H->cfg.lin == PFC_LIN_PICARD, A.u,
@@ -315,6 +324,9 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
     std::vector<int> sizes;
     level_sizes(cfg->n, sizes);
     H->nlev = (int)sizes.size();
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) device = 0;
+    const int slots = fused_slots(device);
     bool ok = true;
     for (int l = 0; l < H->nlev && ok; ++l) {
         Level &A = H->lev[l];
@@ -330,6 +342,14 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
         A.u = Tri<double>{u, u + A.P, u + 2 * A.P};
         A.f = Tri<double>{f, f + A.P, f + 2 * A.P};
         A.ubar = Tri<double>{ub, ub + A.P, ub + 2 * A.P};
+        A.fused = l < H->nlev - 1 && fused_fits(A.n);
+        if (A.fused) {
+            A.nz = fused_nz(A.n, slots);
+            double *u2;
+            ok = dalloc(H, &u2, 3 * A.P);
+            if (!ok) break;
+            A.u2 = Tri<double>{u2, u2 + A.P, u2 + 2 * A.P};
+        }
     }
     ok = ok && dalloc(H, &H->partial, (size_t)kMaxReduceBlocks + 16);
     ok = ok && dalloc(H, &H->d_scal, 16) && dalloc(H, &H->d_iters, 4);
@@ -522,15 +542,18 @@ pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const do
 pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3, const double *f3,
                       const double *phk) {
     if (!h) return PFC_ERR_INVALID_ARG;
-    if (!level_ok(h, level) || (colour != 0 && colour != 1) || !u3 || !f3 || !phk ||
+    if (!level_ok(h, level) || colour < 0 || colour > PFC_SWEEP_FULL || !u3 || !f3 || !phk ||
         !h->lev[level].lay.split)
         return fail(h, PFC_ERR_INVALID_ARG, "bad argument (level must be a smoothed level)");
     Level &A = h->lev[level];
     launch_to_lay<double, double>(h->stream, A.lay, u3, A.u.a, 3);
     launch_to_lay<double, double>(h->stream, A.lay, f3, A.f.a, 3);
     launch_to_lay<double, double>(h->stream, A.lay, phk, A.phk, 1);
-    launch_smooth<double, false>(h->stream, op_of(h, level), colour,
-                                 h->cfg.lin == PFC_LIN_PICARD, A.u, cst(A.f), A.phk, nullptr);
+    if (colour == PFC_SWEEP_FULL)
+        sweep64(h, level);
+    else
+        launch_smooth<double, false>(h->stream, op_of(h, level), colour,
+                                     h->cfg.lin == PFC_LIN_PICARD, A.u, cst(A.f), A.phk, nullptr);
     launch_from_lay<double, double>(h->stream, A.lay, A.u.a, u3, 3);
     HIP_TRY(h, hipGetLastError());
     return PFC_OK;

@@ -23,7 +23,10 @@ struct Level {
     Tri<double> u{nullptr, nullptr, nullptr};     // iterate
     Tri<double> f{nullptr, nullptr, nullptr};     // right-hand side
     Tri<double> ubar{nullptr, nullptr, nullptr};  // restricted fine iterate I u (scratch on level 0)
+    Tri<double> u2{nullptr, nullptr, nullptr};    // second iterate buffer (fused sweeps ping-pong)
     double *phk = nullptr;                        // phi^kappa on this level
+    bool fused = false;                           // smoothed by the fused red-black sweep
+    int nz = 1;                                   // its plane ranges per column
 };
 
 // One level of the FP32 correction cycle of the mixed-precision form.

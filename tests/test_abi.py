@@ -35,6 +35,14 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert sorted(_lib.SIGNATURES) == declared_functions()
 
 
+def test_header_constants_match_the_binding():
+    text = open(HEADER).read()
+    consts = dict((k, int(v)) for k, v in re.findall(r"^#define\s+(PFC_\w+)\s+(-?\d+)", text, flags=re.M))
+    assert "PFC_SWEEP_FULL" in consts and "PFC_KERNEL_COUNT" in consts
+    for name, value in consts.items():
+        assert getattr(_lib, name) == value, name
+
+
 def test_status_strings_and_create_errors_without_gpu_work():
     if not os.path.exists(_lib.LIB_PATH):
         pytest.skip("HIP library not built")

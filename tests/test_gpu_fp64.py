@@ -91,6 +91,29 @@ def test_smoother_half_sweeps(n, level, lin):
         assert rel(host(ud), ref) < KERNEL_RTOL
 
 
+# Full sweeps: levels of >= 128^3 with n % 64 == 0 run the fused one-pass
+# sweep (n = 128 and 256 cut each column into uneven plane ranges, n = 192
+# into even ones); n = 96 runs two half-sweeps.  The fused pass must equal
+# the GPU's own two half-sweeps bitwise and the oracle's within rounding.
+@pytest.mark.parametrize("n,lin", [(96, "newton"), (128, "newton"), (128, "picard"),
+                                   (192, "newton"), (256, "newton")])
+def test_full_sweep_fused(n, lin):
+    from paper_1611_06288_amd._lib import PFC_SWEEP_FULL
+    s = make(n, lin=lin)
+    phk, u, f = rand_state(n, 300 + n)
+    fd, pd = dev(f), dev(phk)
+    full, halves = dev(u), dev(u)
+    ref = u
+    for _ in range(2):
+        s.smooth(0, PFC_SWEEP_FULL, full, fd, pd)
+        for colour in (0, 1):
+            s.smooth(0, colour, halves, fd, pd)
+            ref = cfas.smooth_half(ref, f, phk, s.h, s.eps, s.dt, colour, picard=(lin == "picard"))
+        torch.cuda.synchronize()
+        assert torch.equal(full, halves)
+        assert rel(host(full), ref) < KERNEL_RTOL
+
+
 @pytest.mark.parametrize("n,level", [(12, 0), (48, 0), (48, 1), (96, 0)])
 def test_transfers(n, level):
     s = make(n)
@@ -146,8 +169,10 @@ def test_energy(n):
 
 # ----------------------------------------------------------- cycle level
 
-@pytest.mark.parametrize("n,cycle", [(12, "V"), (32, "V"), (48, "V"), (48, "F"), (64, "V")])
+@pytest.mark.parametrize("n,cycle", [(12, "V"), (32, "V"), (48, "V"), (48, "F"), (64, "V"),
+                                     (128, "V"), (192, "F")])
 def test_one_cycle_matches_oracle(n, cycle):
+    """Levels of 128 and more use the fused red-black sweep (one pass per sweep)."""
     s = make(n, cycle=cycle)
     phk = inputs.polycrystal_phi0(n, s.L, 2, seed=600 + n, radius_cells=4)
     phkm1 = phk + 0.005 * inputs.random_field(n, 601 + n)

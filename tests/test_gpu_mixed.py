@@ -31,14 +31,14 @@ def run(precision, n, L, eps, dt, phi0, steps, tol=1e-10, cycle="V"):
     return phis, infos
 
 
-@pytest.mark.parametrize("n,cycle", [(32, "V"), (48, "F")])
-def test_mixed_matches_fp64_oracle_polycrystal(n, cycle):
+@pytest.mark.parametrize("n,cycle,steps", [(32, "V", 3), (48, "F", 3), (128, "F", 1)])
+def test_mixed_matches_fp64_oracle_polycrystal(n, cycle, steps):
     L, eps, dt, tol = n * math.pi / 4, 0.25, 0.5, 1e-10
     phi0 = inputs.polycrystal_phi0(n, L, 2, seed=900 + n, radius_cells=4)
-    mp, mi = run("mixed", n, L, eps, dt, phi0, 3, tol, cycle)
-    fp, fi = run("fp64", n, L, eps, dt, phi0, 3, tol, cycle)
-    op, oi, _ = cfas.simulate(phi0, L, eps, dt, 3, tol=tol, cycle=cycle)
-    for k in range(3):
+    mp, mi = run("mixed", n, L, eps, dt, phi0, steps, tol, cycle)
+    fp, fi = run("fp64", n, L, eps, dt, phi0, steps, tol, cycle)
+    op, oi, _ = cfas.simulate(phi0, L, eps, dt, steps, tol=tol, cycle=cycle)
+    for k in range(steps):
         assert mi[k].status == 0 and mi[k].res_final <= tol
         err = float(np.max(np.abs(mp[k] - op[k + 1])))
         print(f"step {k}: cycles mixed {mi[k].cycles} fp64 {fi[k].cycles} oracle {oi[k].cycles}; "
