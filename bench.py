@@ -30,12 +30,14 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of one finest-level FP64 smoother launch at 256^3, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, averaged over
-# the step's launches) scaled by what the same counters read for a 1 GiB
-# device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the kernel source it
-# was measured on (first 16 hex digits of its sha256); otherwise reported null.
-SMOOTHER_TRAFFIC = {"kernels_sha256_16": "2d93c991cd057296", "n": 256,
-                    "fetch_KiB": 341098, "write_KiB": 196608,
+# the step's 256^3 launches) scaled by what the same counters read for a 1 GiB
+# device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the smoother sources
+# it was measured on (first 16 hex digits of the sha256 of smooth.hip, smooth.h
+# and device_common.h, concatenated); otherwise reported null.
+SMOOTHER_TRAFFIC = {"sources_sha256_16": "b6fa55da3c5a3a86", "n": 256,
+                    "fetch_KiB": 467966, "write_KiB": 395553,
                     "fetch_scale": 2.0, "write_scale": 1.0}
+SMOOTHER_SOURCES = ("smooth.hip", "smooth.h", "device_common.h")
 METRIC = "time-steps/s & V-cycles/s at 256^3 (FP64 vs mixed); smoother HBM GB/s %peak"
 
 
@@ -78,12 +80,17 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=20):
     return 2 * nbytes / sec / 1e9
 
 
-def smoother_traffic_bytes(n):
+def smoother_sources_sha():
     import hashlib
-    src = os.path.join(ROOT, "paper_1611_06288_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in SMOOTHER_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1611_06288_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def smoother_traffic_bytes(n):
     t = SMOOTHER_TRAFFIC
-    if sha != t["kernels_sha256_16"] or n != t["n"]:
+    if t["fetch_KiB"] is None or smoother_sources_sha() != t["sources_sha256_16"] or n != t["n"]:
         return None
     return 1024.0 * (t["fetch_KiB"] * t["fetch_scale"] + t["write_KiB"] * t["write_scale"])
 

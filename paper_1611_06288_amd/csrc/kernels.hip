@@ -15,6 +15,7 @@
 // in FP64 in both.
 #include "device_common.h"
 #include "pfc.h"
+#include "smooth.h"
 
 #include <math.h>
 
@@ -45,342 +46,6 @@ Lay make_lay(int n, bool split) {
     l.dn = make_div(n);
     l.dh = make_div(split ? n / 2 : 1);
     return l;
-}
-
-// ------------------------------------------------------------- smoothing
-//
-// Pointwise solve of the three equations of N(u) = f at one point with the
-// six neighbours held (Section 5 smoothing scheme, M = 1):
-//     phi + A mu             = r1     A = 6 tau/h^2, r1 = f1 + tau S_mu/h^2
-//    -c phi + mu + B omega   = r2     B = 6/h^2,     r2 = f2 + S_om/h^2 + (lin.)
-//     Dd phi + omega         = r3     Dd = 3/h^2,    r3 = f3 + S_phi/(2h^2)
-// c is the linearised slope of the cubic term; eliminating omega and mu gives
-// phi = (r1 - A r2 + A B r3) / (1 + A (c + B Dd)).
-// One thread per point of colour `colour` (colour-split storage only).
-template <bool DELTA>
-__device__ __forceinline__ void point_solve(const OpParams &op, int picard, double phin, double a,
-                                            double b, double f1, double f2, double f3, double smu,
-                                            double som, double sphi, double &phi, double &mu,
-                                            double &om) {
-    const double h2inv = op.h2inv, tau = op.tau, lin_c = 0.5 * (1.0 - op.eps);
-    double c, r2;
-    if (!DELTA && picard) {
-        const double qq = 0.25 * (phin * phin + a * a);
-        c = qq + lin_c;
-        r2 = f2 + som * h2inv + qq * a;
-    } else {
-        const double gp = Cubic<DELTA>::dg(phin, a, b);
-        c = gp + lin_c;
-        r2 = f2 + som * h2inv + (Cubic<DELTA>::g(phin, a, b) - gp * phin);
-    }
-    const double r1 = f1 + tau * smu * h2inv;
-    const double r3 = f3 + 0.5 * sphi * h2inv;
-    const double A = 6.0 * tau * h2inv, B = 6.0 * h2inv, Dd = 3.0 * h2inv;
-    phi = (r1 - A * r2 + A * B * r3) / (1.0 + A * (c + B * Dd));
-    om = r3 - Dd * phi;
-    mu = r2 + c * phi - B * om;
-}
-
-template <typename T, bool DELTA>
-__device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int picard, Tri<T> u,
-                                            Tri<const T> f, const T *__restrict__ phk,
-                                            const T *__restrict__ base, unsigned t) {
-    const Lay &L = op.lay;
-    const int n = L.n, hn = n >> 1;
-    const unsigned H = (unsigned)((size_t)n * n * n / 2);
-    if (t >= H) return;
-    const unsigned row = L.dh.q(t);
-    const int m = (int)(t - row * (unsigned)hn);
-    const int k = (int)L.dn.q(row);
-    const int j = (int)(row - (unsigned)k * (unsigned)n);
-    const int p = (colour + j + k) & 1;  // x parity of this point
-    // other colour: same row for x-neighbours, same m for y/z neighbours
-    const size_t oc = (size_t)(colour ^ 1) * H;
-    const size_t own = (size_t)colour * H + t;
-    const size_t rbase = oc + (size_t)row * hn;
-    const size_t xm = rbase + (p ? m : (m == 0 ? hn - 1 : m - 1));
-    const size_t xp = rbase + (p ? (m == hn - 1 ? 0 : m + 1) : m);
-    const size_t ym = oc + ((size_t)k * n + wrap_m(j, n)) * hn + m;
-    const size_t yp = oc + ((size_t)k * n + wrap_p(j, n)) * hn + m;
-    const size_t zm = oc + ((size_t)wrap_m(k, n) * n + j) * hn + m;
-    const size_t zp = oc + ((size_t)wrap_p(k, n) * n + j) * hn + m;
-
-    const double smu = ((double)u.b[xp] + (double)u.b[xm]) + ((double)u.b[yp] + (double)u.b[ym]) +
-                       ((double)u.b[zp] + (double)u.b[zm]);
-    const double som = ((double)u.c[xp] + (double)u.c[xm]) + ((double)u.c[yp] + (double)u.c[ym]) +
-                       ((double)u.c[zp] + (double)u.c[zm]);
-    const double sphi = ((double)u.a[xp] + (double)u.a[xm]) + ((double)u.a[yp] + (double)u.a[ym]) +
-                        ((double)u.a[zp] + (double)u.a[zm]);
-    double phi, mu, om;
-    point_solve<DELTA>(op, picard, (double)u.a[own], (double)phk[own],
-                       DELTA ? (double)base[own] : 0.0, (double)f.a[own], (double)f.b[own],
-                       (double)f.c[own], smu, som, sphi, phi, mu, om);
-    u.a[own] = (T)phi;
-    u.b[own] = (T)mu;
-    u.c[own] = (T)om;
-}
-
-template <typename T, bool DELTA>
-__global__ __launch_bounds__(kBlock) void k_smooth(OpParams op, int colour, int picard, Tri<T> u,
-                                                   Tri<const T> f, const T *__restrict__ phk,
-                                                   const T *__restrict__ base) {
-    smooth_body<T, DELTA>(op, colour, picard, u, f, phk, base, xcd_block() * kBlock + threadIdx.x);
-}
-
-template <typename T, bool DELTA>
-void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
-                   Tri<const T> f, const T *phk, const T *base) {
-    const size_t H = npts_host(op.lay) / 2;
-    hipLaunchKernelGGL((k_smooth<T, DELTA>), dim3(blocks_for(H)), dim3(kBlock), 0, s, op, colour,
-                       picard, u, f, phk, base);
-}
-
-// ------------------------------------------------- fused red-black sweep
-//
-// One full red-black sweep in one pass, from u_in to u_out (two buffers;
-// colour-split storage).  A workgroup owns an x-y column of kFX x kFY points
-// and a range [z0, z1) of planes, and walks it in z.  At step k it
-//   * computes the new colour-0 values of plane k on its box plus a one-cell
-//     ring in x and y (the ring cells, and the planes z0-1 and z1, belong to
-//     other workgroups, which compute the same values; they are not written)
-//     into a 3-plane LDS ring, reading the old colour-1 neighbours from a
-//     second 3-plane LDS ring (box plus a two-cell ring) that holds every
-//     old colour-1 value of the column exactly once;
-//   * computes the new colour-1 values of plane k-1 on its box, whose six
-//     colour-0 neighbours are all in the first ring.
-// The old colour-1 plane k+2 and the own-point inputs of the next step are
-// loaded into registers while step k computes, so each thread keeps its
-// next loads in flight across both barriers.
-// Each point sees the neighbour values of the two half-sweeps (old colour 1
-// for colour 0, new colour 0 for colour 1) and the same arithmetic, so, with
-// floating-point contraction off, the result is bitwise that of two
-// launch_smooth calls, while each field is read and written once.
-constexpr int kFX = 64, kFY = 8, kFT = 256;  // column extents, threads per workgroup
-constexpr int kFSl = kFX / 2 + 1;            // colour-0 ring: points per row
-constexpr int kFRw = kFY + 2;                //                rows
-constexpr int kFCs = kFX / 2 + 2;            // colour-1 ring: points per row
-constexpr int kFCr = kFY + 4;                //                rows
-constexpr int kFNr = kFSl * kFRw, kFNb = (kFX / 2) * kFY, kFNc = kFCs * kFCr;
-constexpr int kFIr = (kFNr + kFT - 1) / kFT, kFIb = (kFNb + kFT - 1) / kFT,
-              kFIc = (kFNc + kFT - 1) / kFT;  // items per thread in each phase
-
-template <typename T, bool DELTA>
-__global__ __launch_bounds__(kFT) void k_sweep_fused(
-    OpParams op, int picard, int nz, const T *__restrict__ ua, const T *__restrict__ ub,
-    const T *__restrict__ uc, T *__restrict__ oa, T *__restrict__ ob, T *__restrict__ oc,
-    const T *__restrict__ fa, const T *__restrict__ fb, const T *__restrict__ fc,
-    const T *__restrict__ phk, const T *__restrict__ base) {
-    __shared__ T c1[3][3][kFCr][kFCs];   // [field][plane slot][row][point] old colour 1
-    __shared__ T red[3][3][kFRw][kFSl];  // [field][plane slot][row][point] new colour 0
-    const int n = op.lay.n, hn = n >> 1;
-    const unsigned un = (unsigned)n, uhn = (unsigned)hn, H = un * un * uhn;
-    const int nbx = n / kFX, nby = n / kFY;
-    const int b = (int)xcd_block();
-    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-    const int x0 = bx * kFX, y0 = by * kFY;
-    const int z0 = bz * n / nz, z1 = (bz + 1) * n / nz;
-    const int tid = threadIdx.x;
-    // one-step periodic wraps (every coordinate below is within one period)
-    auto wn = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
-    auto wh = [hn](int v) { return v < 0 ? v + hn : (v >= hn ? v - hn : v); };
-    auto cslot = [z0](int p) { return (p - z0 + 3) % 3; };  // colour-1 ring slot of plane p
-    auto rslot = [z0](int p) { return (p - z0 + 1) % 3; };  // colour-0 ring slot of plane p
-
-    // old colour-1 values of one plane (box plus two-cell ring), in registers
-    T cn[kFIc][3];
-    auto load_c1 = [&](int p) {
-        const unsigned pw = (unsigned)wn(p);
-#pragma unroll
-        for (int i = 0; i < kFIc; ++i) {
-            const int c = tid + i * kFT;
-            if (c < kFNc) {
-                const int cr = c / kFCs, cs = c - cr * kFCs;
-                const unsigned g = H + (pw * un + (unsigned)wn(y0 - 2 + cr)) * uhn +
-                                   (unsigned)wh(x0 / 2 - 1 + cs);
-                cn[i][0] = ua[g];
-                cn[i][1] = ub[g];
-                cn[i][2] = uc[g];
-            }
-        }
-    };
-    auto store_c1 = [&](int p) {
-        const int s = cslot(p);
-#pragma unroll
-        for (int i = 0; i < kFIc; ++i) {
-            const int c = tid + i * kFT;
-            if (c < kFNc) {
-                const int cr = c / kFCs, cs = c - cr * kFCs;
-                c1[0][s][cr][cs] = cn[i][0];
-                c1[1][s][cr][cs] = cn[i][1];
-                c1[2][s][cr][cs] = cn[i][2];
-            }
-        }
-    };
-    // own inputs of the colour-0 points of plane k (box plus ring)
-    T ro[kFIr][6];
-    unsigned rg[kFIr];
-    auto load_red = [&](int k) {
-        const unsigned kw = (unsigned)wn(k);
-#pragma unroll
-        for (int i = 0; i < kFIr; ++i) {
-            const int q = tid + i * kFT;
-            if (q < kFNr) {
-                const int r = q / kFSl, sl = q - r * kFSl;
-                const int y = y0 - 1 + r;
-                const int x = x0 - 1 + ((x0 - 1 + y + k) & 1) + 2 * sl;
-                const unsigned g = (kw * un + (unsigned)wn(y)) * uhn + (unsigned)(wn(x) >> 1);
-                rg[i] = g;
-                ro[i][0] = ua[g];
-                ro[i][1] = phk[g];
-                ro[i][2] = DELTA ? base[g] : (T)0;
-                ro[i][3] = fa[g];
-                ro[i][4] = fb[g];
-                ro[i][5] = fc[g];
-            }
-        }
-    };
-    // own inputs of the colour-1 points of plane kb (box); old phi comes from LDS
-    T bo[kFIb][5];
-    T bphi[kFIb];
-    auto load_black = [&](int kb) {
-#pragma unroll
-        for (int i = 0; i < kFIb; ++i) {
-            const int q = tid + i * kFT;
-            if (q < kFNb) {
-                const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
-                const int y = y0 + rb;
-                const int x = x0 + ((x0 + y + kb + 1) & 1) + 2 * s;
-                const unsigned g = H + ((unsigned)kb * un + (unsigned)y) * uhn + (unsigned)(x >> 1);
-                bo[i][0] = phk[g];
-                bo[i][1] = DELTA ? base[g] : (T)0;
-                bo[i][2] = fa[g];
-                bo[i][3] = fb[g];
-                bo[i][4] = fc[g];
-            }
-        }
-    };
-
-    load_c1(z0 - 2);
-    store_c1(z0 - 2);
-    load_c1(z0 - 1);
-    store_c1(z0 - 1);
-    load_c1(z0);
-    load_red(z0 - 1);
-    for (int k = z0 - 1; k <= z1; ++k) {
-        const int kb = k - 1;  // plane of this step's colour-1 points
-        store_c1(k + 1);       // its slot last held plane k-2, finished in the previous step
-        if (kb >= z0) load_black(kb);
-        __syncthreads();
-        // colour 0, plane k
-        const int sk = cslot(k), skm = cslot(k - 1), skp = cslot(k + 1), rq = rslot(k);
-#pragma unroll
-        for (int i = 0; i < kFIr; ++i) {
-            const int q = tid + i * kFT;
-            if (q < kFNr) {
-                const int r = q / kFSl, sl = q - r * kFSl;
-                const int y = y0 - 1 + r;
-                const int x = x0 - 1 + ((x0 - 1 + y + k) & 1) + 2 * sl;
-                // ring column of x and of its x-neighbours (colour-1 point m = x' >> 1)
-                const int cx = (x - x0 + 2) >> 1, cxm = (x - x0 + 1) >> 1, cxp = (x - x0 + 3) >> 1;
-                double s3[3];
-#pragma unroll
-                for (int fl = 0; fl < 3; ++fl)
-                    s3[fl] = ((double)c1[fl][sk][r + 1][cxp] + (double)c1[fl][sk][r + 1][cxm]) +
-                             ((double)c1[fl][sk][r + 2][cx] + (double)c1[fl][sk][r][cx]) +
-                             ((double)c1[fl][skp][r + 1][cx] + (double)c1[fl][skm][r + 1][cx]);
-                double phi, mu, om;
-                point_solve<DELTA>(op, picard, (double)ro[i][0], (double)ro[i][1],
-                                   (double)ro[i][2], (double)ro[i][3], (double)ro[i][4],
-                                   (double)ro[i][5], s3[1], s3[2], s3[0], phi, mu, om);
-                const T tphi = (T)phi, tmu = (T)mu, tom = (T)om;
-                red[0][rq][r][sl] = tphi;
-                red[1][rq][r][sl] = tmu;
-                red[2][rq][r][sl] = tom;
-                if (x >= x0 && x < x0 + kFX && y >= y0 && y < y0 + kFY && k >= z0 && k < z1) {
-                    oa[rg[i]] = tphi;
-                    ob[rg[i]] = tmu;
-                    oc[rg[i]] = tom;
-                }
-            }
-        }
-        // old phi of this step's colour-1 points, read before their slot is reused
-        if (kb >= z0) {
-            const int sb = cslot(kb);
-#pragma unroll
-            for (int i = 0; i < kFIb; ++i) {
-                const int q = tid + i * kFT;
-                if (q < kFNb) {
-                    const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
-                    const int x = x0 + ((x0 + y0 + rb + kb + 1) & 1) + 2 * s;
-                    bphi[i] = c1[0][sb][rb + 2][(x - x0 + 2) >> 1];
-                }
-            }
-        }
-        if (k + 2 <= z1 + 1) load_c1(k + 2);
-        if (k + 1 <= z1) load_red(k + 1);
-        __syncthreads();
-        // colour 1, plane kb
-        if (kb >= z0) {
-            const int qm = rslot(kb - 1), q0 = rslot(kb), qp = rq;
-#pragma unroll
-            for (int i = 0; i < kFIb; ++i) {
-                const int q = tid + i * kFT;
-                if (q < kFNb) {
-                    const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
-                    const int y = y0 + rb;
-                    const int x = x0 + ((x0 + y + kb + 1) & 1) + 2 * s;
-                    const unsigned g =
-                        H + ((unsigned)kb * un + (unsigned)y) * uhn + (unsigned)(x >> 1);
-                    const int s0 = (x - x0 + 1) >> 1, sm = (x - x0) >> 1, sp = (x - x0 + 2) >> 1;
-                    const int rr = rb + 1;
-                    double s3[3];
-#pragma unroll
-                    for (int fl = 0; fl < 3; ++fl)
-                        s3[fl] = ((double)red[fl][q0][rr][sp] + (double)red[fl][q0][rr][sm]) +
-                                 ((double)red[fl][q0][rr + 1][s0] + (double)red[fl][q0][rr - 1][s0]) +
-                                 ((double)red[fl][qp][rr][s0] + (double)red[fl][qm][rr][s0]);
-                    double phi, mu, om;
-                    point_solve<DELTA>(op, picard, (double)bphi[i], (double)bo[i][0],
-                                       (double)bo[i][1], (double)bo[i][2], (double)bo[i][3],
-                                       (double)bo[i][4], s3[1], s3[2], s3[0], phi, mu, om);
-                    oa[g] = (T)phi;
-                    ob[g] = (T)mu;
-                    oc[g] = (T)om;
-                }
-            }
-        }
-    }
-}
-
-bool fused_fits(int n) { return n % kFX == 0 && n % kFY == 0 && n >= kFusedMinN; }
-
-int fused_slots(int device) {
-    int occ = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (k_sweep_fused<double, false>), kFT, 0) !=
-            hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
-        return 0;
-    return occ * cus;
-}
-
-// z-split of a level: the smallest number of plane ranges for which the launch
-// is a whole number of resident waves (slots workgroups each), with at least 4
-// planes per range; a partly filled last wave costs as much as a full one.
-int fused_nz(int n, int slots) {
-    const int cols = (n / kFX) * (n / kFY);
-    if (slots <= 0) return std::max(1, n / 16);
-    int nz = slots / std::gcd(cols, slots);
-    if (n / nz < 4) nz = std::max(1, n / 4);
-    return nz;
-}
-
-template <typename T, bool DELTA>
-void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
-                        Tri<T> uout, Tri<const T> f, const T *phk, const T *base) {
-    const int n = op.lay.n;
-    const unsigned blocks = (unsigned)((n / kFX) * (n / kFY) * nz);
-    hipLaunchKernelGGL((k_sweep_fused<T, DELTA>), dim3(blocks), dim3(kFT), 0, s, op, picard, nz,
-                       uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b, f.c, phk, base);
 }
 
 // ------------------------------------------------------------ residual
@@ -650,6 +315,67 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T>
     prolong_body<T>(LC, LF, v, ubar, fine, xcd_block() * kBlock + threadIdx.x);
 }
 
+// Tiled form for colour-split fine levels with n a multiple of 64, on the
+// precomputed coarse error e: a workgroup owns a 64 x 8 x 2 block of fine
+// cells (coarse plane K) and stages the (32+2) x (4+2) x 3 coarse cells it
+// interpolates from in LDS, so each coarse value is fetched a few times per
+// workgroup rather than once per use through the caches.  A thread updates an
+// x-pair in both fine planes.  Same weights and operation order as
+// prolong_body.
+constexpr int kPX = 64, kPY = 8;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_tile(Lay LC, Lay LF, Tri<const T> e,
+                                                         Tri<T> fine) {
+    __shared__ double ce[3][3][kPY / 2 + 2][kPX / 2 + 2];  // [field][K-1..K+1][Y][X]
+    const int nc = LC.n, nf = LF.n;
+    const int nbx = nf / kPX, nby = nf / kPY;
+    const int b = (int)xcd_block();
+    const int bx = b % nbx, by = (b / nbx) % nby, K = b / (nbx * nby);
+    const int x0 = bx * kPX, y0 = by * kPY, X0 = x0 / 2, Y0 = y0 / 2;
+    const int tid = threadIdx.x, qx = tid & 31, qy = tid >> 5;
+    const int y = y0 + qy;
+    // the thread's fine values first (independent of the coarse block)
+    double fv[2][2][3];  // [dz][dx][field]
+    unsigned fo[2][2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            const unsigned g = sidx32(LF, x0 + 2 * qx + dx, y, 2 * K + dz);
+            fo[dz][dx] = g;
+            fv[dz][dx][0] = (double)fine.a[g];
+            fv[dz][dx][1] = (double)fine.b[g];
+            fv[dz][dx][2] = (double)fine.c[g];
+        }
+    constexpr int CW = kPX / 2 + 2, CH = kPY / 2 + 2;
+    auto wc = [nc](int v) { return v < 0 ? v + nc : (v >= nc ? v - nc : v); };
+    for (int c = tid; c < 3 * CH * CW; c += kBlock) {
+        const int pz = c / (CH * CW), rem = c - pz * (CH * CW), py = rem / CW, px = rem - py * CW;
+        const unsigned g = sidx32(LC, wc(X0 - 1 + px), wc(Y0 - 1 + py), wc(K - 1 + pz));
+        ce[0][pz][py][px] = (double)e.a[g];
+        ce[1][pz][py][px] = (double)e.b[g];
+        ce[2][pz][py][px] = (double)e.c[g];
+    }
+    __syncthreads();
+    const int cy = (y >> 1) - Y0 + 1, cy1 = (y & 1) ? cy + 1 : cy - 1, cx = qx + 1;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        const int z1 = dz ? 2 : 0;  // plane K-1 for fine plane 2K, K+1 for 2K+1
+#pragma unroll
+        for (int fl = 0; fl < 3; ++fl) {
+            double w[3];  // y/z-interpolated values at X-1, X, X+1
+#pragma unroll
+            for (int xx = 0; xx < 3; ++xx)
+                w[xx] = 0.75 * (0.75 * ce[fl][1][cy][cx - 1 + xx] + 0.25 * ce[fl][1][cy1][cx - 1 + xx]) +
+                        0.25 * (0.75 * ce[fl][z1][cy][cx - 1 + xx] + 0.25 * ce[fl][z1][cy1][cx - 1 + xx]);
+            T *ff = fl == 0 ? fine.a : (fl == 1 ? fine.b : fine.c);
+            ff[fo[dz][0]] = (T)(fv[dz][0][fl] + (0.75 * w[1] + 0.25 * w[0]));
+            ff[fo[dz][1]] = (T)(fv[dz][1][fl] + (0.75 * w[1] + 0.25 * w[2]));
+        }
+    }
+}
+
 template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
                     Tri<const T> ubar, Tri<T> fine_u) {
@@ -660,8 +386,14 @@ void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const
         Tri<T> e{const_cast<T *>(ubar.a), const_cast<T *>(ubar.b), const_cast<T *>(ubar.c)};
         hipLaunchKernelGGL((k_coarse_err<T>), dim3(blocks_for(npts_host(coarse))), dim3(kBlock), 0, s,
                            npts_host(coarse), v, e);
-        hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine,
-                           cst(e), Tri<const T>{nullptr, nullptr, nullptr}, fine_u);
+        if (fine.split && fine.n % kPX == 0 && fine.n % kPY == 0) {
+            const unsigned blocks = (unsigned)((fine.n / kPX) * (fine.n / kPY) * coarse.n);
+            hipLaunchKernelGGL((k_prolong_tile<T>), dim3(blocks), dim3(kBlock), 0, s, coarse, fine,
+                               cst(e), fine_u);
+        } else {
+            hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse,
+                               fine, cst(e), Tri<const T>{nullptr, nullptr, nullptr}, fine_u);
+        }
         return;
     }
     hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine, v,
@@ -1255,8 +987,6 @@ void launch_batch_reset(hipStream_t s, BState st, int count, int **valid) {
 // ------------------------------------------------------ instantiations
 
 #define PFC_INST(T, DELTA)                                                                        \
-    template void launch_smooth<T, DELTA>(hipStream_t, const OpParams &, int, int, Tri<T>,        \
-                                          Tri<const T>, const T *, const T *);                    \
     template void launch_resid_restrict<T, DELTA>(hipStream_t, const OpParams &, const Lay &,     \
                                                   Tri<const T>, Tri<const T>, const T *,          \
                                                   const T *, Tri<T>, Tri<T>);                     \
@@ -1271,9 +1001,6 @@ void launch_batch_reset(hipStream_t s, BState st, int count, int **valid) {
 
 PFC_INST(double, false)
 PFC_INST(float, true)
-template void launch_sweep_fused<double, false>(hipStream_t, const OpParams &, int, int,
-                                                Tri<const double>, Tri<double>, Tri<const double>,
-                                                const double *, const double *);
 template void launch_restrict<double>(hipStream_t, const Lay &, const Lay &, const double *, double *);
 template void launch_restrict<float>(hipStream_t, const Lay &, const Lay &, const float *, float *);
 template void launch_prolong<double>(hipStream_t, const Lay &, const Lay &, Tri<const double>,

@@ -83,8 +83,20 @@ pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_c
     pfc_status status = PFC_OK;
     for (;;) {
         H->begin_timed(PFC_KERNEL_NORM0, 0);
-        const int cnt = launch_resid_cast(H->stream, op_of(H, 0), cst(A.u), cst(A.f), A.phk, A32.f,
-                                          A32.base, H->partial);
+        int cnt;
+        if (A.rt) {
+            ResidTileArgs ra;
+            ra.u = cst(A.u);
+            ra.f = cst(A.f);
+            ra.phk = A.phk;
+            ra.r32 = A32.f;
+            ra.base32 = A32.base;
+            ra.partial = H->partial;
+            cnt = launch_resid_tile(H->stream, RT_CAST, op_of(H, 0), A.rt_nz[RT_CAST], ra);
+        } else {
+            cnt = launch_resid_cast(H->stream, op_of(H, 0), cst(A.u), cst(A.f), A.phk, A32.f,
+                                    A32.base, H->partial);
+        }
         H->end_timed();
         const pfc_status st = read_norm(H, cnt, &rho);
         if (st != PFC_OK) return st;

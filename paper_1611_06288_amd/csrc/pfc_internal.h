@@ -75,6 +75,25 @@ int fused_slots(int device);      // resident fused-sweep workgroups on the devi
 int fused_nz(int n, int slots);   // plane ranges per column for a level of size n
 constexpr int kFusedMinN = 128;  // smaller levels use the half-sweeps
 
+// Residual of a large FP64 level by z-marching column tiles (residual.hip),
+// with one of three epilogues.
+enum { RT_NORM = 0, RT_RESTRICT = 1, RT_CAST = 2 };
+struct ResidTileArgs {
+    Tri<const double> u{nullptr, nullptr, nullptr}, f{nullptr, nullptr, nullptr};
+    const double *phk = nullptr;
+    Lay LC{};                                  // RT_RESTRICT: the coarse level
+    Tri<double> ubar{nullptr, nullptr, nullptr};  // RT_RESTRICT: I u
+    Tri<double> rr{nullptr, nullptr, nullptr};    // RT_RESTRICT: I r
+    Tri<float> r32{nullptr, nullptr, nullptr};    // RT_CAST: r in FP32
+    float *base32 = nullptr;                      // RT_CAST: phi in FP32
+    unsigned long long *partial = nullptr;        // RT_NORM, RT_CAST: per-workgroup max |r|
+};
+bool resid_tile_fits(const Lay &L);
+int resid_tile_slots(int device, int mode);   // resident workgroups (0 on error)
+int resid_tile_nz(int n, int slots, int mode);
+int launch_resid_tile(hipStream_t s, int mode, const OpParams &op, int nz,
+                      const ResidTileArgs &a);  // returns the workgroup count
+
 template <typename T, bool DELTA>
 void launch_resid_restrict(hipStream_t s, const OpParams &op, const Lay &coarse, Tri<const T> u,
                            Tri<const T> f, const T *phk, const T *base, Tri<T> ubar_c, Tri<T> rr_c);

@@ -1,0 +1,239 @@
+// Residual kernels for large FP64 levels (colour-split storage, n a multiple
+// of 64): r = f - N(u) with N of the scheme's operator (scheme-PFC-o1..o3,
+// M = 1), followed by one of three epilogues:
+//   RT_NORM      max |r| over the level (stop test of the cycle loop),
+//   RT_RESTRICT  8-child means of r and u onto the coarse level (the FAS
+//                restriction, Section 3),
+//   RT_CAST      max |r|, plus r and phi rounded to FP32 (the defect and the
+//                base of the mixed-precision correction cycle).
+// A workgroup owns an x-y column of kRX x kRY points and a range of planes and
+// walks it in z.  Three planes of u (box plus a one-cell ring, all three
+// fields) sit in an LDS ring; the next plane and the next step's f and phi^k
+// are loaded into registers while the current plane computes, so every value
+// is fetched from HBM once per column instead of up to seven times through an
+// L2 that cannot hold the reuse distance.  Each thread owns an x-pair of
+// points per plane.  The arithmetic and, for RT_RESTRICT, the order of the
+// 8-child sums equal those of the thread-per-point kernels, so results agree
+// bitwise with them.
+#include "device_common.h"
+
+#include <algorithm>
+#include <numeric>
+
+namespace pfc {
+
+constexpr int kRX = 64, kRY = 8, kRT = 256;            // column extents, threads
+constexpr int kRC = kRX + 2, kRR = kRY + 2;            // tile with its ring
+constexpr int kRN = kRC * kRR, kRI = (kRN + kRT - 1) / kRT;  // ring points, per thread
+
+template <int MODE>
+__global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTileArgs a) {
+    __shared__ double t[3][3][kRR][kRC];  // [field][plane slot][row][x]
+    const double *__restrict__ ua = a.u.a;
+    const double *__restrict__ ub = a.u.b;
+    const double *__restrict__ uc = a.u.c;
+    const int n = op.lay.n, hn = n >> 1;
+    const unsigned un = (unsigned)n, uhn = (unsigned)hn, H = un * un * uhn;
+    const int nbx = n / kRX, nby = n / kRY;
+    const int b = (int)xcd_block();
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int x0 = bx * kRX, y0 = by * kRY;
+    int z0, z1;
+    if (MODE == RT_RESTRICT) {  // plane pairs stay in one workgroup
+        z0 = 2 * (bz * (n / 2) / nz);
+        z1 = 2 * ((bz + 1) * (n / 2) / nz);
+    } else {
+        z0 = bz * n / nz;
+        z1 = (bz + 1) * n / nz;
+    }
+    const int tid = threadIdx.x, qx = tid & 31, qy = tid >> 5;
+    const int xe = x0 + 2 * qx, y = y0 + qy;  // this thread's points: (xe, y), (xe + 1, y)
+    auto wn = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+    auto slot = [z0](int p) { return (p - z0 + 3) % 3; };  // p >= z0 - 1
+
+    double pre[kRI][3];
+    auto load_plane = [&](int p) {
+        const int pw = wn(p);
+#pragma unroll
+        for (int i = 0; i < kRI; ++i) {
+            const int c = tid + i * kRT;
+            if (c < kRN) {
+                const int r = c / kRC, col = c - r * kRC;
+                const int yy = wn(y0 - 1 + r), xx = wn(x0 - 1 + col);
+                const unsigned g = (unsigned)((xx + yy + pw) & 1) * H +
+                                   ((unsigned)pw * un + (unsigned)yy) * uhn + (unsigned)(xx >> 1);
+                pre[i][0] = ua[g];
+                pre[i][1] = ub[g];
+                pre[i][2] = uc[g];
+            }
+        }
+    };
+    auto store_plane = [&](int p) {
+        const int s = slot(p);
+#pragma unroll
+        for (int i = 0; i < kRI; ++i) {
+            const int c = tid + i * kRT;
+            if (c < kRN) {
+                const int r = c / kRC, col = c - r * kRC;
+                t[0][s][r][col] = pre[i][0];
+                t[1][s][r][col] = pre[i][1];
+                t[2][s][r][col] = pre[i][2];
+            }
+        }
+    };
+    // f (3 fields) and phi^k at the thread's two points of plane p
+    auto own_index = [&](int p, int e) {
+        const int x = xe + e;
+        return (unsigned)((x + y + p) & 1) * H + ((unsigned)p * un + (unsigned)y) * uhn +
+               (unsigned)(x >> 1);
+    };
+    auto load_own = [&](int p, double (&o)[2][4]) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const unsigned g = own_index(p, e);
+            o[e][0] = a.f.a[g];
+            o[e][1] = a.f.b[g];
+            o[e][2] = a.f.c[g];
+            o[e][3] = a.phk[g];
+        }
+    };
+
+    load_plane(z0 - 1);
+    store_plane(z0 - 1);
+    load_plane(z0);
+    store_plane(z0);
+    load_plane(z0 + 1);
+    double cur[2][4];
+    load_own(z0, cur);
+    store_plane(z0 + 1);
+    __syncthreads();
+
+    unsigned long long m = 0;
+    double sr[3] = {0.0, 0.0, 0.0}, su[3] = {0.0, 0.0, 0.0};
+    const double h2inv = op.h2inv, tau = op.tau, lin_c = 0.5 * (1.0 - op.eps);
+    for (int p = z0; p < z1; ++p) {
+        double nxt[2][4];
+        if (p + 1 < z1) {
+            load_plane(p + 2);
+            load_own(p + 1, nxt);
+        }
+        const int s0 = slot(p), sm = slot(p - 1), sp = slot(p + 1), row = qy + 1;
+        double r[2][3], uu[2][3];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int col = 2 * qx + e + 1;
+            double ls[3];
+#pragma unroll
+            for (int fl = 0; fl < 3; ++fl) {
+                uu[e][fl] = t[fl][s0][row][col];
+                const double nsum = (t[fl][s0][row][col + 1] + t[fl][s0][row][col - 1]) +
+                                    (t[fl][s0][row + 1][col] + t[fl][s0][row - 1][col]) +
+                                    (t[fl][sp][row][col] + t[fl][sm][row][col]);
+                ls[fl] = (nsum - 6.0 * uu[e][fl]) * h2inv;
+            }
+            const double phi = uu[e][0], mu = uu[e][1], om = uu[e][2], ak = cur[e][3];
+            r[e][0] = cur[e][0] - (phi - tau * ls[1]);
+            r[e][1] = cur[e][1] - (mu - Cubic<false>::g(phi, ak, 0.0) - lin_c * phi - ls[2]);
+            r[e][2] = cur[e][2] - (om - 0.5 * ls[0]);
+        }
+        if (MODE == RT_RESTRICT) {
+            // children in the order (x, y, z) = 000, 100, 010, 110, 001, ...: this
+            // row's pair, then the odd row's pair (lane + 32 of the same wave)
+#pragma unroll
+            for (int fl = 0; fl < 3; ++fl) {
+                const double pr0 = __shfl_xor(r[0][fl], 32), pr1 = __shfl_xor(r[1][fl], 32);
+                const double pu0 = __shfl_xor(uu[0][fl], 32), pu1 = __shfl_xor(uu[1][fl], 32);
+                sr[fl] += r[0][fl];
+                sr[fl] += r[1][fl];
+                sr[fl] += pr0;
+                sr[fl] += pr1;
+                su[fl] += uu[0][fl];
+                su[fl] += uu[1][fl];
+                su[fl] += pu0;
+                su[fl] += pu1;
+            }
+            if ((p & 1) && !(qy & 1)) {
+                const unsigned c = sidx32(a.LC, xe >> 1, y >> 1, p >> 1);
+                a.rr.a[c] = 0.125 * sr[0];
+                a.rr.b[c] = 0.125 * sr[1];
+                a.rr.c[c] = 0.125 * sr[2];
+                a.ubar.a[c] = 0.125 * su[0];
+                a.ubar.b[c] = 0.125 * su[1];
+                a.ubar.c[c] = 0.125 * su[2];
+            }
+            if (p & 1) {
+#pragma unroll
+                for (int fl = 0; fl < 3; ++fl) sr[fl] = su[fl] = 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                m = umax(m, umax(abs_bits(r[e][0]), umax(abs_bits(r[e][1]), abs_bits(r[e][2]))));
+                if (MODE == RT_CAST) {
+                    const unsigned g = own_index(p, e);
+                    a.r32.a[g] = (float)r[e][0];
+                    a.r32.b[g] = (float)r[e][1];
+                    a.r32.c[g] = (float)r[e][2];
+                    a.base32[g] = (float)uu[e][0];
+                }
+            }
+        }
+        __syncthreads();  // every thread is done with plane p - 1's slot
+        if (p + 1 < z1) {
+            store_plane(p + 2);
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) cur[e][v] = nxt[e][v];
+        }
+        __syncthreads();  // plane p + 2 visible
+    }
+    if (MODE != RT_RESTRICT) {
+        m = block_max_u64(m);
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = m;
+    }
+}
+
+bool resid_tile_fits(const Lay &L) { return L.split && L.n % kRX == 0 && L.n % kRY == 0; }
+
+int resid_tile_slots(int device, int mode) {
+    int occ = 0, cus = 0;
+    const void *fn = mode == RT_RESTRICT ? (const void *)k_resid_tile<RT_RESTRICT>
+                     : mode == RT_CAST   ? (const void *)k_resid_tile<RT_CAST>
+                                         : (const void *)k_resid_tile<RT_NORM>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kRT, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    return occ * cus;
+}
+
+// Plane ranges per column: the smallest count for which the launch is a
+// whole number of resident waves with at least 4 planes (2 plane pairs for
+// the restriction) per range, within the partial-result buffer.
+int resid_tile_nz(int n, int slots, int mode) {
+    const int cols = (n / kRX) * (n / kRY);
+    const int units = mode == RT_RESTRICT ? n / 2 : n;  // plane pairs or planes
+    const int minu = mode == RT_RESTRICT ? 2 : 4;
+    int nz = slots > 0 ? slots / std::gcd(cols, slots) : std::max(1, units / 16);
+    if (units / nz < minu) nz = std::max(1, units / minu);
+    while (nz > 1 && cols * nz > kMaxReduceBlocks) nz /= 2;
+    return nz;
+}
+
+int launch_resid_tile(hipStream_t s, int mode, const OpParams &op, int nz, const ResidTileArgs &a) {
+    const int n = op.lay.n;
+    const unsigned blocks = (unsigned)((n / kRX) * (n / kRY) * nz);
+    switch (mode) {
+        case RT_RESTRICT:
+            hipLaunchKernelGGL(k_resid_tile<RT_RESTRICT>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+            break;
+        case RT_CAST:
+            hipLaunchKernelGGL(k_resid_tile<RT_CAST>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+            break;
+        default:
+            hipLaunchKernelGGL(k_resid_tile<RT_NORM>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+    }
+    return (int)blocks;
+}
+
+}  // namespace pfc

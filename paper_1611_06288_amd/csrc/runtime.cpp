@@ -217,8 +217,19 @@ void cycle64(pfc_handle *H, int l, bool fcycle) {
     Level &B = H->lev[l + 1];
     for (int s = 0; s < H->cfg.nu1; ++s) sweep64(H, l);
     H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
-    launch_resid_restrict<double, false>(H->stream, op_of(H, l), B.lay, cst(A.u), cst(A.f), A.phk,
-                                         nullptr, B.ubar, B.f);
+    if (A.rt) {
+        ResidTileArgs ra;
+        ra.u = cst(A.u);
+        ra.f = cst(A.f);
+        ra.phk = A.phk;
+        ra.LC = B.lay;
+        ra.ubar = B.ubar;
+        ra.rr = B.f;
+        launch_resid_tile(H->stream, RT_RESTRICT, op_of(H, l), A.rt_nz[RT_RESTRICT], ra);
+    } else {
+        launch_resid_restrict<double, false>(H->stream, op_of(H, l), B.lay, cst(A.u), cst(A.f),
+                                             A.phk, nullptr, B.ubar, B.f);
+    }
     H->end_timed();
     launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f, B.u, B.phk, nullptr);
     cycle64(H, l + 1, fcycle);
@@ -250,8 +261,18 @@ pfc_status read_norm(pfc_handle *H, int partials, double *out) {
 pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out) {
     Level &A = H->lev[0];
     H->begin_timed(PFC_KERNEL_NORM0, 0);
-    const int cnt = launch_resid_max<double, false>(H->stream, op_of(H, 0), cst(A.u), cst(A.f),
-                                                    A.phk, nullptr, r, H->partial);
+    int cnt;
+    if (A.rt && !r.a) {
+        ResidTileArgs ra;
+        ra.u = cst(A.u);
+        ra.f = cst(A.f);
+        ra.phk = A.phk;
+        ra.partial = H->partial;
+        cnt = launch_resid_tile(H->stream, RT_NORM, op_of(H, 0), A.rt_nz[RT_NORM], ra);
+    } else {
+        cnt = launch_resid_max<double, false>(H->stream, op_of(H, 0), cst(A.u), cst(A.f), A.phk,
+                                              nullptr, r, H->partial);
+    }
     H->end_timed();
     return read_norm(H, cnt, out);
 }
@@ -327,6 +348,8 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) device = 0;
     const int slots = fused_slots(device);
+    int rt_slots[3];
+    for (int m = 0; m < 3; ++m) rt_slots[m] = resid_tile_slots(device, m);
     bool ok = true;
     for (int l = 0; l < H->nlev && ok; ++l) {
         Level &A = H->lev[l];
@@ -342,6 +365,8 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
         A.u = Tri<double>{u, u + A.P, u + 2 * A.P};
         A.f = Tri<double>{f, f + A.P, f + 2 * A.P};
         A.ubar = Tri<double>{ub, ub + A.P, ub + 2 * A.P};
+        A.rt = resid_tile_fits(A.lay);
+        for (int m = 0; m < 3; ++m) A.rt_nz[m] = resid_tile_nz(A.n, rt_slots[m], m);
         A.fused = l < H->nlev - 1 && fused_fits(A.n);
         if (A.fused) {
             A.nz = fused_nz(A.n, slots);
@@ -528,8 +553,18 @@ pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const do
     launch_to_lay<double, double>(h->stream, A.lay, phk, A.phk, 1);
     Tri<double> r{nullptr, nullptr, nullptr};
     if (r3) r = A.ubar;
-    const int cnt = launch_resid_max<double, false>(h->stream, op_of(h, level), cst(A.u), cst(A.f),
-                                                    A.phk, nullptr, r, h->partial);
+    int cnt;
+    if (!r3 && A.rt) {  // norm only: the column-tile kernel the cycles use
+        ResidTileArgs ra;
+        ra.u = cst(A.u);
+        ra.f = cst(A.f);
+        ra.phk = A.phk;
+        ra.partial = h->partial;
+        cnt = launch_resid_tile(h->stream, RT_NORM, op_of(h, level), A.rt_nz[RT_NORM], ra);
+    } else {
+        cnt = launch_resid_max<double, false>(h->stream, op_of(h, level), cst(A.u), cst(A.f), A.phk,
+                                              nullptr, r, h->partial);
+    }
     if (r3) launch_from_lay<double, double>(h->stream, A.lay, A.ubar.a, r3, 3);
     HIP_TRY(h, hipGetLastError());
     double m = 0;

@@ -27,6 +27,8 @@ struct Level {
     double *phk = nullptr;                        // phi^kappa on this level
     bool fused = false;                           // smoothed by the fused red-black sweep
     int nz = 1;                                   // its plane ranges per column
+    bool rt = false;                              // residuals by column tiles
+    int rt_nz[3] = {1, 1, 1};                     // their plane ranges, per epilogue
 };
 
 // One level of the FP32 correction cycle of the mixed-precision form.

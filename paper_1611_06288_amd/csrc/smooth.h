@@ -1,0 +1,83 @@
+// Pointwise relaxation shared by the smoother kernels (smooth.hip) and the
+// batched form (kernels.hip): the 3x3 solve at one point and the half-sweep
+// update of one point in colour-split storage.
+#pragma once
+
+#include "device_common.h"
+
+namespace pfc {
+
+// ------------------------------------------------------------- smoothing
+//
+// Pointwise solve of the three equations of N(u) = f at one point with the
+// six neighbours held (Section 5 smoothing scheme, M = 1):
+//     phi + A mu             = r1     A = 6 tau/h^2, r1 = f1 + tau S_mu/h^2
+//    -c phi + mu + B omega   = r2     B = 6/h^2,     r2 = f2 + S_om/h^2 + (lin.)
+//     Dd phi + omega         = r3     Dd = 3/h^2,    r3 = f3 + S_phi/(2h^2)
+// c is the linearised slope of the cubic term; eliminating omega and mu gives
+// phi = (r1 - A r2 + A B r3) / (1 + A (c + B Dd)).
+// One thread per point of colour `colour` (colour-split storage only).
+template <bool DELTA>
+__device__ __forceinline__ void point_solve(const OpParams &op, int picard, double phin, double a,
+                                            double b, double f1, double f2, double f3, double smu,
+                                            double som, double sphi, double &phi, double &mu,
+                                            double &om) {
+    const double h2inv = op.h2inv, tau = op.tau, lin_c = 0.5 * (1.0 - op.eps);
+    double c, r2;
+    if (!DELTA && picard) {
+        const double qq = 0.25 * (phin * phin + a * a);
+        c = qq + lin_c;
+        r2 = f2 + som * h2inv + qq * a;
+    } else {
+        const double gp = Cubic<DELTA>::dg(phin, a, b);
+        c = gp + lin_c;
+        r2 = f2 + som * h2inv + (Cubic<DELTA>::g(phin, a, b) - gp * phin);
+    }
+    const double r1 = f1 + tau * smu * h2inv;
+    const double r3 = f3 + 0.5 * sphi * h2inv;
+    const double A = 6.0 * tau * h2inv, B = 6.0 * h2inv, Dd = 3.0 * h2inv;
+    phi = (r1 - A * r2 + A * B * r3) / (1.0 + A * (c + B * Dd));
+    om = r3 - Dd * phi;
+    mu = r2 + c * phi - B * om;
+}
+
+template <typename T, bool DELTA>
+__device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int picard, Tri<T> u,
+                                            Tri<const T> f, const T *__restrict__ phk,
+                                            const T *__restrict__ base, unsigned t) {
+    const Lay &L = op.lay;
+    const int n = L.n, hn = n >> 1;
+    const unsigned H = (unsigned)((size_t)n * n * n / 2);
+    if (t >= H) return;
+    const unsigned row = L.dh.q(t);
+    const int m = (int)(t - row * (unsigned)hn);
+    const int k = (int)L.dn.q(row);
+    const int j = (int)(row - (unsigned)k * (unsigned)n);
+    const int p = (colour + j + k) & 1;  // x parity of this point
+    // other colour: same row for x-neighbours, same m for y/z neighbours
+    const size_t oc = (size_t)(colour ^ 1) * H;
+    const size_t own = (size_t)colour * H + t;
+    const size_t rbase = oc + (size_t)row * hn;
+    const size_t xm = rbase + (p ? m : (m == 0 ? hn - 1 : m - 1));
+    const size_t xp = rbase + (p ? (m == hn - 1 ? 0 : m + 1) : m);
+    const size_t ym = oc + ((size_t)k * n + wrap_m(j, n)) * hn + m;
+    const size_t yp = oc + ((size_t)k * n + wrap_p(j, n)) * hn + m;
+    const size_t zm = oc + ((size_t)wrap_m(k, n) * n + j) * hn + m;
+    const size_t zp = oc + ((size_t)wrap_p(k, n) * n + j) * hn + m;
+
+    const double smu = ((double)u.b[xp] + (double)u.b[xm]) + ((double)u.b[yp] + (double)u.b[ym]) +
+                       ((double)u.b[zp] + (double)u.b[zm]);
+    const double som = ((double)u.c[xp] + (double)u.c[xm]) + ((double)u.c[yp] + (double)u.c[ym]) +
+                       ((double)u.c[zp] + (double)u.c[zm]);
+    const double sphi = ((double)u.a[xp] + (double)u.a[xm]) + ((double)u.a[yp] + (double)u.a[ym]) +
+                        ((double)u.a[zp] + (double)u.a[zm]);
+    double phi, mu, om;
+    point_solve<DELTA>(op, picard, (double)u.a[own], (double)phk[own],
+                       DELTA ? (double)base[own] : 0.0, (double)f.a[own], (double)f.b[own],
+                       (double)f.c[own], smu, som, sphi, phi, mu, om);
+    u.a[own] = (T)phi;
+    u.b[own] = (T)mu;
+    u.c[own] = (T)om;
+}
+
+}  // namespace pfc

@@ -1,0 +1,282 @@
+// Smoother kernels: the red-black half-sweep (one colour per launch) and the
+// fused one-pass full sweep used on large FP64 levels (Section 5 smoothing
+// scheme, red-black order; arXiv:1611.06288).
+#include "smooth.h"
+
+#include <algorithm>
+#include <numeric>
+
+namespace pfc {
+
+template <typename T, bool DELTA>
+__global__ __launch_bounds__(kBlock) void k_smooth(OpParams op, int colour, int picard, Tri<T> u,
+                                                   Tri<const T> f, const T *__restrict__ phk,
+                                                   const T *__restrict__ base) {
+    smooth_body<T, DELTA>(op, colour, picard, u, f, phk, base, xcd_block() * kBlock + threadIdx.x);
+}
+
+template <typename T, bool DELTA>
+void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
+                   Tri<const T> f, const T *phk, const T *base) {
+    const size_t H = npts_host(op.lay) / 2;
+    hipLaunchKernelGGL((k_smooth<T, DELTA>), dim3(blocks_for(H)), dim3(kBlock), 0, s, op, colour,
+                       picard, u, f, phk, base);
+}
+
+// ------------------------------------------------- fused red-black sweep
+//
+// One full red-black sweep in one pass, from u_in to u_out (two buffers;
+// colour-split storage).  A workgroup owns an x-y column of kFX x kFY points
+// and a range [z0, z1) of planes, and walks it in z.  At step k it
+//   * computes the new colour-0 values of plane k on its box plus a one-cell
+//     ring in x and y (the ring cells, and the planes z0-1 and z1, belong to
+//     other workgroups, which compute the same values; they are not written)
+//     into a 3-plane LDS ring, reading the old colour-1 neighbours from a
+//     second 3-plane LDS ring (box plus a two-cell ring) that holds every
+//     old colour-1 value of the column exactly once;
+//   * computes the new colour-1 values of plane k-1 on its box, whose six
+//     colour-0 neighbours are all in the first ring.
+// The old colour-1 plane k+2 and the own-point inputs of the next step are
+// loaded into registers while step k computes, so each thread keeps its
+// next loads in flight across both barriers.
+// Each point sees the neighbour values of the two half-sweeps (old colour 1
+// for colour 0, new colour 0 for colour 1) and the same arithmetic, so, with
+// floating-point contraction off, the result is bitwise that of two
+// launch_smooth calls, while each field is read and written once.
+constexpr int kFX = 64, kFY = 8, kFT = 256;  // column extents, threads per workgroup
+constexpr int kFSl = kFX / 2 + 1;            // colour-0 ring: points per row
+constexpr int kFRw = kFY + 2;                //                rows
+constexpr int kFCs = kFX / 2 + 2;            // colour-1 ring: points per row
+constexpr int kFCr = kFY + 4;                //                rows
+constexpr int kFNr = kFSl * kFRw, kFNb = (kFX / 2) * kFY, kFNc = kFCs * kFCr;
+constexpr int kFIr = (kFNr + kFT - 1) / kFT, kFIb = (kFNb + kFT - 1) / kFT,
+              kFIc = (kFNc + kFT - 1) / kFT;  // items per thread in each phase
+
+template <typename T, bool DELTA>
+__global__ __launch_bounds__(kFT) void k_sweep_fused(
+    OpParams op, int picard, int nz, const T *__restrict__ ua, const T *__restrict__ ub,
+    const T *__restrict__ uc, T *__restrict__ oa, T *__restrict__ ob, T *__restrict__ oc,
+    const T *__restrict__ fa, const T *__restrict__ fb, const T *__restrict__ fc,
+    const T *__restrict__ phk, const T *__restrict__ base) {
+    __shared__ T c1[3][3][kFCr][kFCs];   // [field][plane slot][row][point] old colour 1
+    __shared__ T red[3][3][kFRw][kFSl];  // [field][plane slot][row][point] new colour 0
+    const int n = op.lay.n, hn = n >> 1;
+    const unsigned un = (unsigned)n, uhn = (unsigned)hn, H = un * un * uhn;
+    const int nbx = n / kFX, nby = n / kFY;
+    const int b = (int)xcd_block();
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int x0 = bx * kFX, y0 = by * kFY;
+    const int z0 = bz * n / nz, z1 = (bz + 1) * n / nz;
+    const int tid = threadIdx.x;
+    // one-step periodic wraps (every coordinate below is within one period)
+    auto wn = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+    auto wh = [hn](int v) { return v < 0 ? v + hn : (v >= hn ? v - hn : v); };
+    auto cslot = [z0](int p) { return (p - z0 + 3) % 3; };  // colour-1 ring slot of plane p
+    auto rslot = [z0](int p) { return (p - z0 + 1) % 3; };  // colour-0 ring slot of plane p
+
+    // old colour-1 values of one plane (box plus two-cell ring), in registers
+    T cn[kFIc][3];
+    auto load_c1 = [&](int p) {
+        const unsigned pw = (unsigned)wn(p);
+#pragma unroll
+        for (int i = 0; i < kFIc; ++i) {
+            const int c = tid + i * kFT;
+            if (c < kFNc) {
+                const int cr = c / kFCs, cs = c - cr * kFCs;
+                const unsigned g = H + (pw * un + (unsigned)wn(y0 - 2 + cr)) * uhn +
+                                   (unsigned)wh(x0 / 2 - 1 + cs);
+                cn[i][0] = ua[g];
+                cn[i][1] = ub[g];
+                cn[i][2] = uc[g];
+            }
+        }
+    };
+    auto store_c1 = [&](int p) {
+        const int s = cslot(p);
+#pragma unroll
+        for (int i = 0; i < kFIc; ++i) {
+            const int c = tid + i * kFT;
+            if (c < kFNc) {
+                const int cr = c / kFCs, cs = c - cr * kFCs;
+                c1[0][s][cr][cs] = cn[i][0];
+                c1[1][s][cr][cs] = cn[i][1];
+                c1[2][s][cr][cs] = cn[i][2];
+            }
+        }
+    };
+    // own inputs of the colour-0 points of plane k (box plus ring)
+    T ro[kFIr][6];
+    unsigned rg[kFIr];
+    auto load_red = [&](int k) {
+        const unsigned kw = (unsigned)wn(k);
+#pragma unroll
+        for (int i = 0; i < kFIr; ++i) {
+            const int q = tid + i * kFT;
+            if (q < kFNr) {
+                const int r = q / kFSl, sl = q - r * kFSl;
+                const int y = y0 - 1 + r;
+                const int x = x0 - 1 + ((x0 - 1 + y + k) & 1) + 2 * sl;
+                const unsigned g = (kw * un + (unsigned)wn(y)) * uhn + (unsigned)(wn(x) >> 1);
+                rg[i] = g;
+                ro[i][0] = ua[g];
+                ro[i][1] = phk[g];
+                ro[i][2] = DELTA ? base[g] : (T)0;
+                ro[i][3] = fa[g];
+                ro[i][4] = fb[g];
+                ro[i][5] = fc[g];
+            }
+        }
+    };
+    // own inputs of the colour-1 points of plane kb (box); old phi comes from LDS
+    T bo[kFIb][5];
+    T bphi[kFIb];
+    auto load_black = [&](int kb) {
+#pragma unroll
+        for (int i = 0; i < kFIb; ++i) {
+            const int q = tid + i * kFT;
+            if (q < kFNb) {
+                const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
+                const int y = y0 + rb;
+                const int x = x0 + ((x0 + y + kb + 1) & 1) + 2 * s;
+                const unsigned g = H + ((unsigned)kb * un + (unsigned)y) * uhn + (unsigned)(x >> 1);
+                bo[i][0] = phk[g];
+                bo[i][1] = DELTA ? base[g] : (T)0;
+                bo[i][2] = fa[g];
+                bo[i][3] = fb[g];
+                bo[i][4] = fc[g];
+            }
+        }
+    };
+
+    load_c1(z0 - 2);
+    store_c1(z0 - 2);
+    load_c1(z0 - 1);
+    store_c1(z0 - 1);
+    load_c1(z0);
+    load_red(z0 - 1);
+    for (int k = z0 - 1; k <= z1; ++k) {
+        const int kb = k - 1;  // plane of this step's colour-1 points
+        store_c1(k + 1);       // its slot last held plane k-2, finished in the previous step
+        if (kb >= z0) load_black(kb);
+        __syncthreads();
+        // colour 0, plane k
+        const int sk = cslot(k), skm = cslot(k - 1), skp = cslot(k + 1), rq = rslot(k);
+#pragma unroll
+        for (int i = 0; i < kFIr; ++i) {
+            const int q = tid + i * kFT;
+            if (q < kFNr) {
+                const int r = q / kFSl, sl = q - r * kFSl;
+                const int y = y0 - 1 + r;
+                const int x = x0 - 1 + ((x0 - 1 + y + k) & 1) + 2 * sl;
+                // ring column of x and of its x-neighbours (colour-1 point m = x' >> 1)
+                const int cx = (x - x0 + 2) >> 1, cxm = (x - x0 + 1) >> 1, cxp = (x - x0 + 3) >> 1;
+                double s3[3];
+#pragma unroll
+                for (int fl = 0; fl < 3; ++fl)
+                    s3[fl] = ((double)c1[fl][sk][r + 1][cxp] + (double)c1[fl][sk][r + 1][cxm]) +
+                             ((double)c1[fl][sk][r + 2][cx] + (double)c1[fl][sk][r][cx]) +
+                             ((double)c1[fl][skp][r + 1][cx] + (double)c1[fl][skm][r + 1][cx]);
+                double phi, mu, om;
+                point_solve<DELTA>(op, picard, (double)ro[i][0], (double)ro[i][1],
+                                   (double)ro[i][2], (double)ro[i][3], (double)ro[i][4],
+                                   (double)ro[i][5], s3[1], s3[2], s3[0], phi, mu, om);
+                const T tphi = (T)phi, tmu = (T)mu, tom = (T)om;
+                red[0][rq][r][sl] = tphi;
+                red[1][rq][r][sl] = tmu;
+                red[2][rq][r][sl] = tom;
+                if (x >= x0 && x < x0 + kFX && y >= y0 && y < y0 + kFY && k >= z0 && k < z1) {
+                    oa[rg[i]] = tphi;
+                    ob[rg[i]] = tmu;
+                    oc[rg[i]] = tom;
+                }
+            }
+        }
+        // old phi of this step's colour-1 points, read before their slot is reused
+        if (kb >= z0) {
+            const int sb = cslot(kb);
+#pragma unroll
+            for (int i = 0; i < kFIb; ++i) {
+                const int q = tid + i * kFT;
+                if (q < kFNb) {
+                    const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
+                    const int x = x0 + ((x0 + y0 + rb + kb + 1) & 1) + 2 * s;
+                    bphi[i] = c1[0][sb][rb + 2][(x - x0 + 2) >> 1];
+                }
+            }
+        }
+        if (k + 2 <= z1 + 1) load_c1(k + 2);
+        if (k + 1 <= z1) load_red(k + 1);
+        __syncthreads();
+        // colour 1, plane kb
+        if (kb >= z0) {
+            const int qm = rslot(kb - 1), q0 = rslot(kb), qp = rq;
+#pragma unroll
+            for (int i = 0; i < kFIb; ++i) {
+                const int q = tid + i * kFT;
+                if (q < kFNb) {
+                    const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
+                    const int y = y0 + rb;
+                    const int x = x0 + ((x0 + y + kb + 1) & 1) + 2 * s;
+                    const unsigned g =
+                        H + ((unsigned)kb * un + (unsigned)y) * uhn + (unsigned)(x >> 1);
+                    const int s0 = (x - x0 + 1) >> 1, sm = (x - x0) >> 1, sp = (x - x0 + 2) >> 1;
+                    const int rr = rb + 1;
+                    double s3[3];
+#pragma unroll
+                    for (int fl = 0; fl < 3; ++fl)
+                        s3[fl] = ((double)red[fl][q0][rr][sp] + (double)red[fl][q0][rr][sm]) +
+                                 ((double)red[fl][q0][rr + 1][s0] + (double)red[fl][q0][rr - 1][s0]) +
+                                 ((double)red[fl][qp][rr][s0] + (double)red[fl][qm][rr][s0]);
+                    double phi, mu, om;
+                    point_solve<DELTA>(op, picard, (double)bphi[i], (double)bo[i][0],
+                                       (double)bo[i][1], (double)bo[i][2], (double)bo[i][3],
+                                       (double)bo[i][4], s3[1], s3[2], s3[0], phi, mu, om);
+                    oa[g] = (T)phi;
+                    ob[g] = (T)mu;
+                    oc[g] = (T)om;
+                }
+            }
+        }
+    }
+}
+
+bool fused_fits(int n) { return n % kFX == 0 && n % kFY == 0 && n >= kFusedMinN; }
+
+int fused_slots(int device) {
+    int occ = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (k_sweep_fused<double, false>), kFT, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    return occ * cus;
+}
+
+// z-split of a level: the smallest number of plane ranges for which the launch
+// is a whole number of resident waves (slots workgroups each), with at least 4
+// planes per range; a partly filled last wave costs as much as a full one.
+int fused_nz(int n, int slots) {
+    const int cols = (n / kFX) * (n / kFY);
+    if (slots <= 0) return std::max(1, n / 16);
+    int nz = slots / std::gcd(cols, slots);
+    if (n / nz < 4) nz = std::max(1, n / 4);
+    return nz;
+}
+
+template <typename T, bool DELTA>
+void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
+                        Tri<T> uout, Tri<const T> f, const T *phk, const T *base) {
+    const int n = op.lay.n;
+    const unsigned blocks = (unsigned)((n / kFX) * (n / kFY) * nz);
+    hipLaunchKernelGGL((k_sweep_fused<T, DELTA>), dim3(blocks), dim3(kFT), 0, s, op, picard, nz,
+                       uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b, f.c, phk, base);
+}
+
+template void launch_smooth<double, false>(hipStream_t, const OpParams &, int, int, Tri<double>,
+                                           Tri<const double>, const double *, const double *);
+template void launch_smooth<float, true>(hipStream_t, const OpParams &, int, int, Tri<float>,
+                                         Tri<const float>, const float *, const float *);
+template void launch_sweep_fused<double, false>(hipStream_t, const OpParams &, int, int,
+                                                Tri<const double>, Tri<double>, Tri<const double>,
+                                                const double *, const double *);
+
+}  // namespace pfc

@@ -76,6 +76,23 @@ def test_residual_kernel(n, level):
     assert m == pytest.approx(m_o, rel=1e-13)
 
 
+# Column-tile residual norm (levels with n % 64 == 0; n = 128 cuts columns
+# into uneven plane ranges) against the thread-per-point kernel and the oracle.
+@pytest.mark.parametrize("n,level", [(128, 0), (192, 0), (256, 0), (256, 1)])
+def test_residual_norm_tiles(n, level):
+    s = make(n)
+    nl = s.levels[level]
+    hl = s.L / nl
+    phk, u, f = rand_state(nl, 400 + nl)
+    ud, fd, pd = dev(u), dev(f), dev(phk)
+    _, m_tile = s.residual(level, ud, fd, pd, want_r=False)
+    r, m_thread = s.residual(level, ud, fd, pd, want_r=True)
+    assert m_tile == m_thread
+    if nl <= 128:
+        _, m_o = cfas.residual(u, f, phk, hl, s.eps, s.dt)
+        assert m_tile == pytest.approx(m_o, rel=1e-13)
+
+
 @pytest.mark.parametrize("n,level,lin", [(6, 0, "newton"), (12, 0, "newton"), (12, 1, "picard"),
                                          (48, 0, "newton"), (48, 1, "picard"), (96, 0, "newton")])
 def test_smoother_half_sweeps(n, level, lin):
@@ -132,6 +149,25 @@ def test_transfers(n, level):
     od = dev(one)
     s.prolong_add(level, dev(v[0]), None, od, 1)
     assert rel(host(od), cfas.prolong_add(v[0], one)) < KERNEL_RTOL
+
+
+# Interpolation of a coarse error onto fine levels with n % 64 == 0 runs the
+# LDS-tiled kernel; with the error passed directly (no ubar) the
+# thread-per-pair kernel runs.  The two must agree bitwise, and with the oracle.
+@pytest.mark.parametrize("n,level", [(128, 0), (192, 0), (256, 0), (256, 1)])
+def test_prolong_tiles(n, level):
+    s = make(n)
+    nf, nc = s.levels[level], s.levels[level + 1]
+    g = inputs.rng(500 + n + level)
+    fine = g.uniform(-1, 1, (3, nf, nf, nf))
+    v = g.uniform(-1, 1, (3, nc, nc, nc))
+    ub = g.uniform(-1, 1, (3, nc, nc, nc))
+    tiled, direct = dev(fine), dev(fine)
+    s.prolong_add(level, dev(v), dev(ub), tiled, 3)
+    s.prolong_add(level, dev(v - ub), None, direct, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(tiled, direct)
+    assert rel(host(tiled), cfas.prolong_add(v - ub, fine)) < KERNEL_RTOL
 
 
 @pytest.mark.parametrize("n", [4, 6, 8, 12])
