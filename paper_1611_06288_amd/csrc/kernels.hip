@@ -1,14 +1,17 @@
 // HIP kernels (gfx950) for the FAS multigrid solve of one step of the
-// second-order PFC scheme (arXiv:1611.06288, Sections 2, 3 and 5).
+// second-order PFC scheme (arXiv:1611.06288, Sections 2, 3 and 5): layouts,
+// transfers (restriction, tau correction, interpolation), the coarsest-level
+// solve, the source, energy sums, the FP32/FP64 conversions of the
+// mixed-precision form and the batched kernels.  The smoothers live in
+// smooth.hip, the column-tile residuals in residual.hip.
 //
 // Every kernel is a 7-point stencil, a transfer or a reduction: memory bound,
 // no matrix-core work.  Smoothed levels store each field colour-split (all
 // points of colour 0 = (i+j+k) even, then all of colour 1), so a red-black
 // half-sweep streams only the colour it updates plus the other colour's three
-// fields: 44 bytes per grid point instead of the ~80 an interleaved layout
-// drags through the caches.  Threads walk the storage order (coalesced);
-// workgroup ids are remapped so each of the 8 XCDs gets a contiguous range of
-// z-planes, whose neighbours then meet in that XCD's L2.
+// fields.  Threads walk the storage order (coalesced); workgroup ids are
+// remapped so each of the 8 XCDs gets a contiguous range of z-planes, whose
+// neighbours then meet in that XCD's L2.
 //
 // Storage type T is double (FP64 path) or float (the correction cycle of the
 // mixed-precision form); operator arithmetic and the pointwise 3x3 solve run
