@@ -8,15 +8,21 @@
 //     G(e) = g(b + e; phi^k) - g(b; phi^k)
 //          = 1/4 [e (b^2 + (phi^k)^2) + (b + e + phi^k)(2 b e + e^2)],
 // b = phi of the current FP64 iterate rounded to FP32 (restricted to the
-// coarse levels), written without cancellation.  Then u += e in FP64.  The
-// smoother's pointwise 3x3 solve, the residual and all reductions run in
-// FP64 arithmetic; only stored fields of the correction cycle are FP32.
+// coarse levels), written without cancellation.  Then u += e in FP64 (on
+// levels with column tiles, inside the next defect pass).  While the residual
+// is far above tol two FP32 cycles run per defect.  The smoother's pointwise
+// 3x3 solve, the residual and all reductions run in FP64 arithmetic; only
+// stored fields of the correction cycle are FP32.
 #include <cmath>
 #include <utility>
 
 #include "runtime_internal.h"
 
 namespace pfc {
+
+// Two FP32 cycles per FP64 defect only while the predicted residual after
+// both exceeds this multiple of tol.
+constexpr double kTwoCycleMargin = 10.0;
 
 pfc_status mixed_init(pfc_handle *H) {
     for (int l = 0; l < H->nlev; ++l) {
@@ -56,8 +62,20 @@ static void cycle32(pfc_handle *H, int l, bool fcycle) {
     const Lay &LB = H->lev[l + 1].lay;
     for (int s = 0; s < H->cfg.nu1; ++s) sweep32(H, l);
     H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
-    launch_resid_restrict<float, true>(H->stream, op_of(H, l), LB, cst(A.e), cst(A.f), A.phk,
-                                       A.base, B.ebar, B.f);
+    if (H->lev[l].rt) {
+        ResidTileArgs ra;
+        ra.e32 = cst(A.e);
+        ra.f32 = cst(A.f);
+        ra.phk32 = A.phk;
+        ra.b32 = A.base;
+        ra.LC = LB;
+        ra.ebar32 = B.ebar;
+        ra.rr32 = B.f;
+        launch_resid_tile(H->stream, RT_RESTRICT32, op_of(H, l), H->lev[l].rt_nz[RT_RESTRICT32], ra);
+    } else {
+        launch_resid_restrict<float, true>(H->stream, op_of(H, l), LB, cst(A.e), cst(A.f), A.phk,
+                                           A.base, B.ebar, B.f);
+    }
     H->end_timed();
     launch_tau<float, true>(H->stream, op_of(H, l + 1), cst(B.ebar), B.f, B.e, B.phk, B.base);
     cycle32(H, l + 1, fcycle);
@@ -79,24 +97,37 @@ pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_c
                                H->lev32[l + 1].phk);
     HIP_TRY(H, hipGetLastError());
     int c = 0;
-    double rho = 0, rho0 = 0;
+    double rho = 0, rho0 = 0, rho_prev = 0;
+    int inner_prev = 1;
+    bool pending = false;  // a correction e waits to be added to u
     pfc_status status = PFC_OK;
     for (;;) {
         H->begin_timed(PFC_KERNEL_NORM0, 0);
         int cnt;
         if (A.rt) {
             ResidTileArgs ra;
-            ra.u = cst(A.u);
             ra.f = cst(A.f);
             ra.phk = A.phk;
             ra.r32 = A32.f;
             ra.base32 = A32.base;
             ra.partial = H->partial;
-            cnt = launch_resid_tile(H->stream, RT_CAST, op_of(H, 0), A.rt_nz[RT_CAST], ra);
+            if (pending) {  // u2 = u + e, defect and casts of u2, in one pass
+                ra.u = cst(A.u);
+                ra.e = cst(A32.e);
+                ra.uout = A.u2;
+                cnt = launch_resid_tile(H->stream, RT_CAST_CORR, op_of(H, 0),
+                                        A.rt_nz[RT_CAST_CORR], ra);
+                std::swap(A.u, A.u2);
+            } else {
+                ra.u = cst(A.u);
+                cnt = launch_resid_tile(H->stream, RT_CAST, op_of(H, 0), A.rt_nz[RT_CAST], ra);
+            }
         } else {
+            if (pending) launch_add_correction(H->stream, A.P, A.u, cst(A32.e));
             cnt = launch_resid_cast(H->stream, op_of(H, 0), cst(A.u), cst(A.f), A.phk, A32.f,
                                     A32.base, H->partial);
         }
+        pending = false;
         H->end_timed();
         const pfc_status st = read_norm(H, cnt, &rho);
         if (st != PFC_OK) return st;
@@ -106,17 +137,29 @@ pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_c
             break;
         }
         if (rho <= H->cfg.tol) break;
-        if (c == H->cfg.max_cycles) {
+        if (c >= H->cfg.max_cycles) {
             status = PFC_ERR_NOT_CONVERGED;
             break;
+        }
+        // FP32 cycles on this defect: two while the observed contraction per
+        // cycle predicts that the residual after both is still well above
+        // tol (so the second cycle is one the FP64 loop would run anyway),
+        // otherwise one.  Each FP64 defect pass saved is a full-level
+        // FP64 read of u, f and phi^k.
+        int inner = 1;
+        if (rho_prev > 0 && rho < rho_prev && c + 2 <= H->cfg.max_cycles) {
+            const double q = std::pow(rho / rho_prev, 1.0 / inner_prev);
+            if (rho * q * q > kTwoCycleMargin * H->cfg.tol) inner = 2;
         }
         for (int l = 0; l + 1 < H->nlev; ++l)
             launch_restrict<float>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev32[l].base,
                                    H->lev32[l + 1].base);
         launch_zero(H->stream, A32.e.a, 3 * A.P);
-        cycle32(H, 0, H->cfg.cycle == PFC_CYCLE_F);
-        launch_add_correction(H->stream, A.P, A.u, cst(A32.e));
-        ++c;
+        for (int i = 0; i < inner; ++i) cycle32(H, 0, H->cfg.cycle == PFC_CYCLE_F);
+        pending = true;
+        c += inner;
+        rho_prev = rho;
+        inner_prev = inner;
     }
     step_end(H, phi_next, mu, omega);
     HIP_TRY(H, hipGetLastError());
@@ -138,7 +181,10 @@ pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_c
 // per point.  A half-sweep launch updates one colour: the other colour's
 // three fields and its own old phi, f, phi^k and new u, i.e. 44 B per point
 // of the level in FP64, and 24 B in the FP32 correction form (4 B values,
-// plus the base).
+// plus the base).  The mixed form's FP64 defect pass reads u, f, phi^k and
+// writes r and phi in FP32 (72 B); on column-tile levels it also reads the
+// pending FP32 correction and writes u + e (108 B), which is all but the
+// first pass of each step, so 108 is credited there.
 double algorithmic_bytes(const pfc_handle *H, int kernel) {
     const double P = (double)H->lev[0].P;
     const bool mixed = H->cfg.precision == PFC_MIXED;
@@ -147,7 +193,7 @@ double algorithmic_bytes(const pfc_handle *H, int kernel) {
         case PFC_KERNEL_SMOOTH0: return smooth * P;
         case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0) * P;
         case PFC_KERNEL_PROLONG0: return (mixed ? 27.0 : 54.0) * P;
-        case PFC_KERNEL_NORM0: return (mixed ? 72.0 : 56.0) * P;
+        case PFC_KERNEL_NORM0: return (mixed ? (H->lev[0].rt ? 108.0 : 72.0) : 56.0) * P;
         default: return 0.0;
     }
 }

@@ -75,18 +75,25 @@ int fused_slots(int device);      // resident fused-sweep workgroups on the devi
 int fused_nz(int n, int slots);   // plane ranges per column for a level of size n
 constexpr int kFusedMinN = 128;  // smaller levels use the half-sweeps
 
-// Residual of a large FP64 level by z-marching column tiles (residual.hip),
-// with one of three epilogues.
-enum { RT_NORM = 0, RT_RESTRICT = 1, RT_CAST = 2 };
+// Residual of a large level by z-marching column tiles (residual.hip), with
+// one of five epilogues.
+enum { RT_NORM = 0, RT_RESTRICT = 1, RT_CAST = 2, RT_CAST_CORR = 3, RT_RESTRICT32 = 4, RT_MODES = 5 };
 struct ResidTileArgs {
+    // FP64 operator: RT_NORM, RT_RESTRICT, RT_CAST, RT_CAST_CORR
     Tri<const double> u{nullptr, nullptr, nullptr}, f{nullptr, nullptr, nullptr};
     const double *phk = nullptr;
-    Lay LC{};                                  // RT_RESTRICT: the coarse level
     Tri<double> ubar{nullptr, nullptr, nullptr};  // RT_RESTRICT: I u
     Tri<double> rr{nullptr, nullptr, nullptr};    // RT_RESTRICT: I r
-    Tri<float> r32{nullptr, nullptr, nullptr};    // RT_CAST: r in FP32
-    float *base32 = nullptr;                      // RT_CAST: phi in FP32
-    unsigned long long *partial = nullptr;        // RT_NORM, RT_CAST: per-workgroup max |r|
+    Tri<float> r32{nullptr, nullptr, nullptr};    // RT_CAST*: r in FP32
+    float *base32 = nullptr;                      // RT_CAST*: phi in FP32
+    Tri<const float> e{nullptr, nullptr, nullptr};  // RT_CAST_CORR: correction added to u
+    Tri<double> uout{nullptr, nullptr, nullptr};    // RT_CAST_CORR: u + e (distinct from u)
+    // FP32 correction operator: RT_RESTRICT32
+    Tri<const float> e32{nullptr, nullptr, nullptr}, f32{nullptr, nullptr, nullptr};
+    const float *phk32 = nullptr, *b32 = nullptr;
+    Tri<float> ebar32{nullptr, nullptr, nullptr}, rr32{nullptr, nullptr, nullptr};
+    Lay LC{};                               // restrictions: the coarse level
+    unsigned long long *partial = nullptr;  // RT_NORM, RT_CAST*: per-workgroup max |r|
 };
 bool resid_tile_fits(const Lay &L);
 int resid_tile_slots(int device, int mode);   // resident workgroups (0 on error)

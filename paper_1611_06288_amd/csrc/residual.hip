@@ -1,24 +1,31 @@
-// Residual kernels for large FP64 levels (colour-split storage, n a multiple
-// of 64): r = f - N(u) with N of the scheme's operator (scheme-PFC-o1..o3,
-// M = 1), followed by one of three epilogues:
-//   RT_NORM      max |r| over the level (stop test of the cycle loop),
-//   RT_RESTRICT  8-child means of r and u onto the coarse level (the FAS
-//                restriction, Section 3),
-//   RT_CAST      max |r|, plus r and phi rounded to FP32 (the defect and the
-//                base of the mixed-precision correction cycle).
+// Residual kernels for large colour-split levels (n a multiple of 64):
+// r = f - N(u) with N of the scheme's operator (scheme-PFC-o1..o3, M = 1), or
+// of its correction form in the mixed-precision cycle (the cubic term as the
+// difference G(e) = g(b + e) - g(b)), followed by one of these epilogues:
+//   RT_NORM        max |r| over the level (stop test of the cycle loop),
+//   RT_RESTRICT    8-child means of r and u onto the coarse level (the FAS
+//                  restriction, Section 3),
+//   RT_CAST        max |r|, plus r and phi rounded to FP32 (the defect and the
+//                  base of the mixed-precision correction cycle),
+//   RT_CAST_CORR   as RT_CAST on u + e, the FP64 iterate with the pending FP32
+//                  correction added while the planes are staged; u + e is
+//                  written to a second buffer (other columns read this one's
+//                  u as their ring in the same launch),
+//   RT_RESTRICT32  RT_RESTRICT for the FP32 correction operator.
 // A workgroup owns an x-y column of kRX x kRY points and a range of planes and
 // walks it in z.  Three planes of u (box plus a one-cell ring, all three
 // fields) sit in an LDS ring; the next plane and the next step's f and phi^k
 // are loaded into registers while the current plane computes, so every value
 // is fetched from HBM once per column instead of up to seven times through an
 // L2 that cannot hold the reuse distance.  Each thread owns an x-pair of
-// points per plane.  The arithmetic and, for RT_RESTRICT, the order of the
-// 8-child sums equal those of the thread-per-point kernels, so results agree
-// bitwise with them.
+// points per plane.  The arithmetic and, for the restrictions, the order of
+// the 8-child sums equal those of the thread-per-point kernels (and u + e that
+// of the separate correction kernel), so results agree bitwise with them.
 #include "device_common.h"
 
 #include <algorithm>
 #include <numeric>
+#include <type_traits>
 
 namespace pfc {
 
@@ -28,10 +35,30 @@ constexpr int kRN = kRC * kRR, kRI = (kRN + kRT - 1) / kRT;  // ring points, per
 
 template <int MODE>
 __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTileArgs a) {
-    __shared__ double t[3][3][kRR][kRC];  // [field][plane slot][row][x]
-    const double *__restrict__ ua = a.u.a;
-    const double *__restrict__ ub = a.u.b;
-    const double *__restrict__ uc = a.u.c;
+    constexpr bool F32 = MODE == RT_RESTRICT32;
+    constexpr bool DELTA = F32;
+    constexpr bool RESTRICT = MODE == RT_RESTRICT || MODE == RT_RESTRICT32;
+    constexpr bool CAST = MODE == RT_CAST || MODE == RT_CAST_CORR;
+    constexpr bool CORR = MODE == RT_CAST_CORR;
+    using T = typename std::conditional<F32, float, double>::type;
+    __shared__ T t[3][3][kRR][kRC];  // [field][plane slot][row][x]
+    Tri<const T> u, f;
+    const T *phk, *bs = nullptr;
+    Tri<T> ubar, rr;
+    if constexpr (F32) {
+        u = a.e32;
+        f = a.f32;
+        phk = a.phk32;
+        bs = a.b32;
+        ubar = a.ebar32;
+        rr = a.rr32;
+    } else {
+        u = a.u;
+        f = a.f;
+        phk = a.phk;
+        ubar = a.ubar;
+        rr = a.rr;
+    }
     const int n = op.lay.n, hn = n >> 1;
     const unsigned un = (unsigned)n, uhn = (unsigned)hn, H = un * un * uhn;
     const int nbx = n / kRX, nby = n / kRY;
@@ -39,7 +66,7 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int x0 = bx * kRX, y0 = by * kRY;
     int z0, z1;
-    if (MODE == RT_RESTRICT) {  // plane pairs stay in one workgroup
+    if (RESTRICT) {  // plane pairs stay in one workgroup
         z0 = 2 * (bz * (n / 2) / nz);
         z1 = 2 * ((bz + 1) * (n / 2) / nz);
     } else {
@@ -51,7 +78,7 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
     auto wn = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
     auto slot = [z0](int p) { return (p - z0 + 3) % 3; };  // p >= z0 - 1
 
-    double pre[kRI][3];
+    T pre[kRI][3];
     auto load_plane = [&](int p) {
         const int pw = wn(p);
 #pragma unroll
@@ -62,9 +89,14 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
                 const int yy = wn(y0 - 1 + r), xx = wn(x0 - 1 + col);
                 const unsigned g = (unsigned)((xx + yy + pw) & 1) * H +
                                    ((unsigned)pw * un + (unsigned)yy) * uhn + (unsigned)(xx >> 1);
-                pre[i][0] = ua[g];
-                pre[i][1] = ub[g];
-                pre[i][2] = uc[g];
+                pre[i][0] = u.a[g];
+                pre[i][1] = u.b[g];
+                pre[i][2] = u.c[g];
+                if constexpr (CORR) {
+                    pre[i][0] += (double)a.e.a[g];
+                    pre[i][1] += (double)a.e.b[g];
+                    pre[i][2] += (double)a.e.c[g];
+                }
             }
         }
     };
@@ -81,20 +113,22 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
             }
         }
     };
-    // f (3 fields) and phi^k at the thread's two points of plane p
+    // f (3 fields), phi^k and (correction form) the base at the thread's two points of plane p
     auto own_index = [&](int p, int e) {
         const int x = xe + e;
         return (unsigned)((x + y + p) & 1) * H + ((unsigned)p * un + (unsigned)y) * uhn +
                (unsigned)(x >> 1);
     };
-    auto load_own = [&](int p, double (&o)[2][4]) {
+    constexpr int NO = DELTA ? 5 : 4;
+    auto load_own = [&](int p, T (&o)[2][NO]) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const unsigned g = own_index(p, e);
-            o[e][0] = a.f.a[g];
-            o[e][1] = a.f.b[g];
-            o[e][2] = a.f.c[g];
-            o[e][3] = a.phk[g];
+            o[e][0] = f.a[g];
+            o[e][1] = f.b[g];
+            o[e][2] = f.c[g];
+            o[e][3] = phk[g];
+            if constexpr (DELTA) o[e][4] = bs[g];
         }
     };
 
@@ -103,7 +137,7 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
     load_plane(z0);
     store_plane(z0);
     load_plane(z0 + 1);
-    double cur[2][4];
+    T cur[2][NO];
     load_own(z0, cur);
     store_plane(z0 + 1);
     __syncthreads();
@@ -112,7 +146,7 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
     double sr[3] = {0.0, 0.0, 0.0}, su[3] = {0.0, 0.0, 0.0};
     const double h2inv = op.h2inv, tau = op.tau, lin_c = 0.5 * (1.0 - op.eps);
     for (int p = z0; p < z1; ++p) {
-        double nxt[2][4];
+        T nxt[2][NO];
         if (p + 1 < z1) {
             load_plane(p + 2);
             load_own(p + 1, nxt);
@@ -125,18 +159,21 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
             double ls[3];
 #pragma unroll
             for (int fl = 0; fl < 3; ++fl) {
-                uu[e][fl] = t[fl][s0][row][col];
-                const double nsum = (t[fl][s0][row][col + 1] + t[fl][s0][row][col - 1]) +
-                                    (t[fl][s0][row + 1][col] + t[fl][s0][row - 1][col]) +
-                                    (t[fl][sp][row][col] + t[fl][sm][row][col]);
+                uu[e][fl] = (double)t[fl][s0][row][col];
+                const double nsum =
+                    ((double)t[fl][s0][row][col + 1] + (double)t[fl][s0][row][col - 1]) +
+                    ((double)t[fl][s0][row + 1][col] + (double)t[fl][s0][row - 1][col]) +
+                    ((double)t[fl][sp][row][col] + (double)t[fl][sm][row][col]);
                 ls[fl] = (nsum - 6.0 * uu[e][fl]) * h2inv;
             }
-            const double phi = uu[e][0], mu = uu[e][1], om = uu[e][2], ak = cur[e][3];
-            r[e][0] = cur[e][0] - (phi - tau * ls[1]);
-            r[e][1] = cur[e][1] - (mu - Cubic<false>::g(phi, ak, 0.0) - lin_c * phi - ls[2]);
-            r[e][2] = cur[e][2] - (om - 0.5 * ls[0]);
+            const double phi = uu[e][0], mu = uu[e][1], om = uu[e][2], ak = (double)cur[e][3];
+            const double bb = DELTA ? (double)cur[e][NO - 1] : 0.0;
+            r[e][0] = (double)cur[e][0] - (phi - tau * ls[1]);
+            r[e][1] = (double)cur[e][1] -
+                      (mu - Cubic<DELTA>::g(phi, ak, bb) - lin_c * phi - ls[2]);
+            r[e][2] = (double)cur[e][2] - (om - 0.5 * ls[0]);
         }
-        if (MODE == RT_RESTRICT) {
+        if constexpr (RESTRICT) {
             // children in the order (x, y, z) = 000, 100, 010, 110, 001, ...: this
             // row's pair, then the odd row's pair (lane + 32 of the same wave)
 #pragma unroll
@@ -154,12 +191,12 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
             }
             if ((p & 1) && !(qy & 1)) {
                 const unsigned c = sidx32(a.LC, xe >> 1, y >> 1, p >> 1);
-                a.rr.a[c] = 0.125 * sr[0];
-                a.rr.b[c] = 0.125 * sr[1];
-                a.rr.c[c] = 0.125 * sr[2];
-                a.ubar.a[c] = 0.125 * su[0];
-                a.ubar.b[c] = 0.125 * su[1];
-                a.ubar.c[c] = 0.125 * su[2];
+                rr.a[c] = (T)(0.125 * sr[0]);
+                rr.b[c] = (T)(0.125 * sr[1]);
+                rr.c[c] = (T)(0.125 * sr[2]);
+                ubar.a[c] = (T)(0.125 * su[0]);
+                ubar.b[c] = (T)(0.125 * su[1]);
+                ubar.c[c] = (T)(0.125 * su[2]);
             }
             if (p & 1) {
 #pragma unroll
@@ -169,12 +206,17 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 m = umax(m, umax(abs_bits(r[e][0]), umax(abs_bits(r[e][1]), abs_bits(r[e][2]))));
-                if (MODE == RT_CAST) {
+                if constexpr (CAST) {
                     const unsigned g = own_index(p, e);
                     a.r32.a[g] = (float)r[e][0];
                     a.r32.b[g] = (float)r[e][1];
                     a.r32.c[g] = (float)r[e][2];
                     a.base32[g] = (float)uu[e][0];
+                    if constexpr (CORR) {
+                        a.uout.a[g] = uu[e][0];
+                        a.uout.b[g] = uu[e][1];
+                        a.uout.c[g] = uu[e][2];
+                    }
                 }
             }
         }
@@ -184,11 +226,11 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
 #pragma unroll
             for (int e = 0; e < 2; ++e)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) cur[e][v] = nxt[e][v];
+                for (int v = 0; v < NO; ++v) cur[e][v] = nxt[e][v];
         }
         __syncthreads();  // plane p + 2 visible
     }
-    if (MODE != RT_RESTRICT) {
+    if constexpr (!RESTRICT) {
         m = block_max_u64(m);
         if (threadIdx.x == 0) a.partial[blockIdx.x] = m;
     }
@@ -196,12 +238,20 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
 
 bool resid_tile_fits(const Lay &L) { return L.split && L.n % kRX == 0 && L.n % kRY == 0; }
 
+static const void *resid_tile_fn(int mode) {
+    switch (mode) {
+        case RT_RESTRICT: return (const void *)k_resid_tile<RT_RESTRICT>;
+        case RT_CAST: return (const void *)k_resid_tile<RT_CAST>;
+        case RT_CAST_CORR: return (const void *)k_resid_tile<RT_CAST_CORR>;
+        case RT_RESTRICT32: return (const void *)k_resid_tile<RT_RESTRICT32>;
+        default: return (const void *)k_resid_tile<RT_NORM>;
+    }
+}
+
 int resid_tile_slots(int device, int mode) {
     int occ = 0, cus = 0;
-    const void *fn = mode == RT_RESTRICT ? (const void *)k_resid_tile<RT_RESTRICT>
-                     : mode == RT_CAST   ? (const void *)k_resid_tile<RT_CAST>
-                                         : (const void *)k_resid_tile<RT_NORM>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kRT, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, resid_tile_fn(mode), kRT, 0) !=
+            hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
     return occ * cus;
@@ -212,8 +262,9 @@ int resid_tile_slots(int device, int mode) {
 // the restriction) per range, within the partial-result buffer.
 int resid_tile_nz(int n, int slots, int mode) {
     const int cols = (n / kRX) * (n / kRY);
-    const int units = mode == RT_RESTRICT ? n / 2 : n;  // plane pairs or planes
-    const int minu = mode == RT_RESTRICT ? 2 : 4;
+    const bool pairs = mode == RT_RESTRICT || mode == RT_RESTRICT32;
+    const int units = pairs ? n / 2 : n;  // plane pairs or planes
+    const int minu = pairs ? 2 : 4;
     int nz = slots > 0 ? slots / std::gcd(cols, slots) : std::max(1, units / 16);
     if (units / nz < minu) nz = std::max(1, units / minu);
     while (nz > 1 && cols * nz > kMaxReduceBlocks) nz /= 2;
@@ -229,6 +280,12 @@ int launch_resid_tile(hipStream_t s, int mode, const OpParams &op, int nz, const
             break;
         case RT_CAST:
             hipLaunchKernelGGL(k_resid_tile<RT_CAST>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+            break;
+        case RT_CAST_CORR:
+            hipLaunchKernelGGL(k_resid_tile<RT_CAST_CORR>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+            break;
+        case RT_RESTRICT32:
+            hipLaunchKernelGGL(k_resid_tile<RT_RESTRICT32>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
             break;
         default:
             hipLaunchKernelGGL(k_resid_tile<RT_NORM>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);

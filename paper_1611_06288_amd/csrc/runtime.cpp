@@ -348,8 +348,8 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) device = 0;
     const int slots = fused_slots(device);
-    int rt_slots[3];
-    for (int m = 0; m < 3; ++m) rt_slots[m] = resid_tile_slots(device, m);
+    int rt_slots[RT_MODES];
+    for (int m = 0; m < RT_MODES; ++m) rt_slots[m] = resid_tile_slots(device, m);
     bool ok = true;
     for (int l = 0; l < H->nlev && ok; ++l) {
         Level &A = H->lev[l];
@@ -366,9 +366,9 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
         A.f = Tri<double>{f, f + A.P, f + 2 * A.P};
         A.ubar = Tri<double>{ub, ub + A.P, ub + 2 * A.P};
         A.rt = resid_tile_fits(A.lay);
-        for (int m = 0; m < 3; ++m) A.rt_nz[m] = resid_tile_nz(A.n, rt_slots[m], m);
+        for (int m = 0; m < RT_MODES; ++m) A.rt_nz[m] = resid_tile_nz(A.n, rt_slots[m], m);
         A.fused = l < H->nlev - 1 && fused_fits(A.n);
-        if (A.fused) {
+        if (A.fused || (l == 0 && A.rt)) {
             A.nz = fused_nz(A.n, slots);
             double *u2;
             ok = dalloc(H, &u2, 3 * A.P);

@@ -23,12 +23,12 @@ struct Level {
     Tri<double> u{nullptr, nullptr, nullptr};     // iterate
     Tri<double> f{nullptr, nullptr, nullptr};     // right-hand side
     Tri<double> ubar{nullptr, nullptr, nullptr};  // restricted fine iterate I u (scratch on level 0)
-    Tri<double> u2{nullptr, nullptr, nullptr};    // second iterate buffer (fused sweeps ping-pong)
+    Tri<double> u2{nullptr, nullptr, nullptr};    // second iterate buffer (fused sweeps, fused correction)
     double *phk = nullptr;                        // phi^kappa on this level
     bool fused = false;                           // smoothed by the fused red-black sweep
     int nz = 1;                                   // its plane ranges per column
     bool rt = false;                              // residuals by column tiles
-    int rt_nz[3] = {1, 1, 1};                     // their plane ranges, per epilogue
+    int rt_nz[RT_MODES] = {1, 1, 1, 1, 1};        // their plane ranges, per epilogue
 };
 
 // One level of the FP32 correction cycle of the mixed-precision form.
