@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="grid size (256 is the benchmark)")
     ap.add_argument("--cycle", default="V", choices=["V", "F"])
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-fcycle", action="store_true",
+                    help="skip the FP64 F(2,2) run of the same steps (reported beside V)")
     ap.add_argument("--cpu-cycles", type=int, default=3,
                     help="oracle cycles timed for the CPU baseline (0 disables it)")
     ap.add_argument("--batch-steps", type=int, default=6,
@@ -270,6 +272,23 @@ def main():
     print(f"fp64: {fp64['steps_per_s']:.3f} steps/s, cycles {fp64['cycles_per_step']}",
           file=sys.stderr, flush=True)
 
+    fcyc = None
+    if args.cycle == "V" and not args.no_fcycle:
+        # the same steps solved to the same tolerance with F(2,2) cycles; on
+        # this workload the point smoother is divergent on smooth modes and
+        # the F-cycle's second coarse visit needs about a third of the cycles
+        fres, phisf = run_path(Solver, abi, torch, "fp64", state0, p, args.steps, args.warmup, "F")
+        fcyc = {
+            "steps_per_s": round(fres["steps_per_s"], 4),
+            "f_cycles_per_s": round(fres["v_cycles_per_s"], 3),
+            "ms_per_step": round(fres["ms_per_step"], 3),
+            "cycles_per_step": fres["cycles_per_step"],
+            "speedup_vs_v_per_step": round(fres["steps_per_s"] / fp64["steps_per_s"], 4),
+            "max_abs_diff_vs_v_per_step": [float((a - b).abs().max()) for a, b in zip(phisf, phis64)],
+        }
+        print(f"fp64 F-cycles: {fres['steps_per_s']:.3f} steps/s, cycles {fres['cycles_per_step']}",
+              file=sys.stderr, flush=True)
+
     mixed = None
     if not args.no_mixed:
         try:
@@ -340,6 +359,7 @@ def main():
         "v_cycles_per_s": round(fp64["v_cycles_per_s"], 3),
         "cycles_per_step": fp64["cycles_per_step"],
         "kernels": fp64["kernels"],
+        "fp64_fcycle": fcyc,
         "mixed": mixed,
         "batched": batched,
         "adjoint": adjoint,
