@@ -10,7 +10,7 @@
 // b = phi of the current FP64 iterate rounded to FP32 (restricted to the
 // coarse levels), written without cancellation.  Then u += e in FP64 (on
 // levels with column tiles, inside the next defect pass).  While the residual
-// is far above tol two FP32 cycles run per defect.  The smoother's pointwise
+// is far above tol up to three FP32 cycles run per defect.  The smoother's pointwise
 // 3x3 solve, the residual and all reductions run in FP64 arithmetic; only
 // stored fields of the correction cycle are FP32.
 #include <cmath>
@@ -20,9 +20,10 @@
 
 namespace pfc {
 
-// Two FP32 cycles per FP64 defect only while the predicted residual after
-// both exceeds this multiple of tol.
-constexpr double kTwoCycleMargin = 10.0;
+// Up to kMaxInnerCycles FP32 cycles per FP64 defect, each extra one only
+// while the predicted residual after it still exceeds this multiple of tol.
+constexpr int kMaxInnerCycles = 12;
+constexpr double kInnerCycleMargin = 3.0;
 
 pfc_status mixed_init(pfc_handle *H) {
     for (int l = 0; l < H->nlev; ++l) {
@@ -141,15 +142,19 @@ pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_c
             status = PFC_ERR_NOT_CONVERGED;
             break;
         }
-        // FP32 cycles on this defect: two while the observed contraction per
-        // cycle predicts that the residual after both is still well above
-        // tol (so the second cycle is one the FP64 loop would run anyway),
-        // otherwise one.  Each FP64 defect pass saved is a full-level
-        // FP64 read of u, f and phi^k.
+        // FP32 cycles on this defect: as many (up to kMaxInnerCycles) as the
+        // observed contraction per cycle predicts the FP64 loop would run
+        // anyway before reaching tol (with a margin), at least one.  Each
+        // FP64 defect pass saved is a full-level FP64 read of u, f and phi^k.
         int inner = 1;
-        if (rho_prev > 0 && rho < rho_prev && c + 2 <= H->cfg.max_cycles) {
+        if (rho_prev > 0 && rho < rho_prev) {
             const double q = std::pow(rho / rho_prev, 1.0 / inner_prev);
-            if (rho * q * q > kTwoCycleMargin * H->cfg.tol) inner = 2;
+            double pred = rho * q;
+            while (inner < kMaxInnerCycles && c + inner + 1 <= H->cfg.max_cycles &&
+                   pred * q > kInnerCycleMargin * H->cfg.tol) {
+                ++inner;
+                pred *= q;
+            }
         }
         for (int l = 0; l + 1 < H->nlev; ++l)
             launch_restrict<float>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev32[l].base,
