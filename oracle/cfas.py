@@ -54,6 +54,17 @@ def lib():
         L.orc_initial_guess.argtypes = [i, d, d, _dp, _dp, _dp]
         L.orc_energy.argtypes = [i, d, d, _dp, _dp, _dp]
         L.orc_num_threads.restype = i
+        mob = [d, d, d, d]
+        L.orc_apply_N_m.argtypes = [i, d, d, d, _dp, _dp, _dp] + mob + [_dp]
+        L.orc_residual_m.argtypes = [i, d, d, d, _dp, _dp, _dp, _dp] + mob + [_dp]
+        L.orc_residual_m.restype = d
+        L.orc_local_solve_m.argtypes = [d, d, d, i, d, d, d, d, d, d, d, d, d, _dp, _dp, _dp]
+        L.orc_smooth_half_m.argtypes = [i, d, d, d, i, i, _dp, _dp, _dp, _dp] + mob
+        L.orc_coarse_solve_m.argtypes = [i, d, d, d, _dp, _dp, _dp, _dp] + mob
+        L.orc_coarse_solve_m.restype = i
+        L.orc_set_mobility.argtypes = [vp] + mob
+        L.orc_cycle_m.argtypes = [vp, _dp, _dp, _dp, _dp]
+        L.orc_cycle_m.restype = d
         _lib = L
     return _lib
 
@@ -153,6 +164,47 @@ def coarse_solve(u, f, phk, h, eps, tau):
     return u, it
 
 
+# ------------------------------------------------------------------
+# Variable mobility M(v) = max(mmin, m0 + m1 v + m2 v^2) on the faces,
+# evaluated at the face average of phi* (mob = (m0, m1, m2, mmin)).
+
+def apply_N_m(u, phk, phs, h, eps, tau, mob):
+    u, phk, phs = _f64(u), _f64(phk), _f64(phs)
+    out = np.empty_like(u)
+    lib().orc_apply_N_m(phk.shape[0], h, eps, tau, _p(u), _p(phk), _p(phs), *mob, _p(out))
+    return out
+
+
+def residual_m(u, f, phk, phs, h, eps, tau, mob):
+    """Returns (r, max|r|)."""
+    u, f, phk, phs = _f64(u), _f64(f), _f64(phk), _f64(phs)
+    r = np.empty_like(u)
+    m = lib().orc_residual_m(phk.shape[0], h, eps, tau, _p(u), _p(f), _p(phk), _p(phs), *mob, _p(r))
+    return r, m
+
+
+def local_solve_m(h, eps, tau, picard, phin, phk, f1, f2, f3, msum, smu, som, sphi):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_local_solve_m(h, eps, tau, int(picard), phin, phk, f1, f2, f3, msum, smu, som, sphi,
+                            C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value
+
+
+def smooth_half_m(u, f, phk, phs, h, eps, tau, colour, mob, picard=False):
+    u = _f64(u).copy()
+    f, phk, phs = _f64(f), _f64(phk), _f64(phs)
+    lib().orc_smooth_half_m(phk.shape[0], h, eps, tau, int(picard), int(colour), _p(u), _p(f),
+                            _p(phk), _p(phs), *mob)
+    return u
+
+
+def coarse_solve_m(u, f, phk, phs, h, eps, tau, mob):
+    u = _f64(u).copy()
+    f, phk, phs = _f64(f), _f64(phk), _f64(phs)
+    it = lib().orc_coarse_solve_m(phk.shape[0], h, eps, tau, _p(u), _p(f), _p(phk), _p(phs), *mob)
+    return u, it
+
+
 def initial_guess(phi0, h, eps):
     phi0 = _f64(phi0)
     mu = np.empty_like(phi0)
@@ -185,7 +237,7 @@ class Solver:
     """FAS solver of one time step of scheme (1.10), M = 1 (C oracle)."""
 
     def __init__(self, n, L, eps, dt, tol=1e-10, nu1=2, nu2=2, max_cycles=200,
-                 cycle="V", lin="newton"):
+                 cycle="V", lin="newton", mobility=None):
         self.n, self.L, self.eps, self.dt, self.tol = n, L, eps, dt, tol
         self.h = L / n
         self.max_cycles = max_cycles
@@ -193,6 +245,9 @@ class Solver:
                                    1 if cycle == "F" else 0, 1 if lin == "picard" else 0)
         if not self._s:
             raise OracleError(f"invalid oracle configuration n={n}")
+        self.mobility = mobility
+        if mobility is not None:
+            lib().orc_set_mobility(self._s, *[float(x) for x in mobility])
 
     def close(self):
         if self._s:
@@ -209,11 +264,15 @@ class Solver:
     def levels(self):
         return [lib().orc_level_n(self._s, l) for l in range(lib().orc_levels(self._s))]
 
-    def cycle(self, u, f, phk):
-        """One cycle from (u, f, phk); returns (u_new, residual after)."""
+    def cycle(self, u, f, phk, phs=None):
+        """One cycle from (u, f, phk) (and phi* with variable mobility);
+        returns (u_new, residual after)."""
         u = _f64(u).copy()
         f, phk = _f64(f), _f64(phk)
-        res = lib().orc_cycle(self._s, _p(u), _p(f), _p(phk))
+        if self.mobility is not None:
+            res = lib().orc_cycle_m(self._s, _p(u), _p(f), _p(phk), _p(_f64(phs)))
+        else:
+            res = lib().orc_cycle(self._s, _p(u), _p(f), _p(phk))
         return u, res
 
     def step(self, phkm1, phk, mu, omega):
@@ -230,12 +289,12 @@ class Solver:
 
 
 def simulate(phi0, L, eps, dt, steps, tol=1e-10, nu1=2, nu2=2, cycle="V", lin="newton",
-             max_cycles=400, callback=None):
+             max_cycles=400, callback=None, mobility=None):
     """Runs `steps` time steps from phi0 with the bootstrap phi^{-1} = phi^0.
 
     Returns (list of phi^0..phi^steps, list of StepInfo, final (mu, omega))."""
     n = phi0.shape[0]
-    s = Solver(n, L, eps, dt, tol, nu1, nu2, max_cycles, cycle, lin)
+    s = Solver(n, L, eps, dt, tol, nu1, nu2, max_cycles, cycle, lin, mobility)
     mu, om = initial_guess(phi0, L / n, eps)
     phis = [_f64(phi0).copy()]
     infos = []

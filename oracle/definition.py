@@ -15,6 +15,11 @@ Written from the paper (arXiv:1611.06288):
   step is well defined and any solver converging to it is comparable.
 * The adjoint of one step follows from the implicit-function theorem applied
   to ``G(u; phi^k, phi^{k-1}, eps) = N(u) - S = 0``.
+* Section 5 with a variable mobility: the first equation in flux form,
+  ``phi - tau d_x(M(A_x phi*) D_x mu) - ... ``, assembled here as the sparse
+  matrix ``d_x diag(M_face) D_x + ...`` from the face operators of Section 2
+  (``mobility_matrix``); M(v) = max(mmin, m0 + m1 v + m2 v^2) and
+  phi* = 3/2 phi^kappa - 1/2 phi^{kappa-1} (the paper leaves M open).
 
 Solvers:
 * ``solve_step_dense`` -- Newton with the dense 3n^3 Jacobian (n <= 8).
@@ -66,6 +71,78 @@ def lap_symbol(n: int, L: float) -> np.ndarray:
     r = np.arange(n)
     s1 = np.sin(np.pi * r / n) ** 2
     return -(4.0 / h ** 2) * (s1[:, None, None] + s1[None, :, None] + s1[None, None, :])
+
+
+def face_difference_matrix(n: int, h: float, axis: int) -> sp.csr_matrix:
+    """D along `axis` (Section 2): face (i + 1/2) value (v_{i+1} - v_i)/h; the
+    face i + 1/2 is stored at cell index i."""
+    idx = np.arange(n ** 3).reshape(n, n, n)
+    nb = np.roll(idx, -1, axis)     # cell i + 1 along the axis
+    P = n ** 3
+    rows = np.concatenate([idx.ravel(), idx.ravel()])
+    cols = np.concatenate([nb.ravel(), idx.ravel()])
+    vals = np.concatenate([np.full(P, 1.0 / h), np.full(P, -1.0 / h)])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(P, P))
+
+
+def face_average_matrix(n: int, axis: int) -> sp.csr_matrix:
+    """A along `axis` (Section 2): face (i + 1/2) value (v_{i+1} + v_i)/2."""
+    idx = np.arange(n ** 3).reshape(n, n, n)
+    nb = np.roll(idx, -1, axis)
+    P = n ** 3
+    rows = np.concatenate([idx.ravel(), idx.ravel()])
+    cols = np.concatenate([nb.ravel(), idx.ravel()])
+    return sp.csr_matrix((np.full(2 * P, 0.5), (rows, cols)), shape=(P, P))
+
+
+def mobility(v, mob):
+    m0, m1, m2, mmin = mob
+    return np.maximum(mmin, m0 + m1 * v + m2 * v * v)
+
+
+def mobility_matrix(n: int, h: float, phs: np.ndarray, mob) -> sp.csr_matrix:
+    """sum over axes of d (diag(M(A phs)) D), with d = -D^T (the cell
+    difference of face values, Section 2), as a sparse n^3 x n^3 matrix."""
+    Lm = sp.csr_matrix((n ** 3, n ** 3))
+    for axis in range(3):
+        D = face_difference_matrix(n, h, axis)
+        Mf = mobility(face_average_matrix(n, axis) @ phs.ravel(), mob)
+        Lm = Lm + (-D.T) @ sp.diags(Mf) @ D
+    return Lm.tocsr()
+
+
+def apply_N_mob(u, phk, phs, h, eps, tau, mob):
+    phi, mu, om = u
+    n = phk.shape[0]
+    Lm = mobility_matrix(n, h, phs, mob)
+    return np.stack([
+        phi - tau * (Lm @ mu.ravel()).reshape(phi.shape),
+        mu - g_cubic(phi, phk) - 0.5 * (1.0 - eps) * phi - lap(om, h),
+        om - 0.5 * lap(phi, h),
+    ])
+
+
+def solve_step_dense_mob(phkm1, phk, h, eps, tau, mob, guess=None, tol=1e-14, maxit=50):
+    """Newton with the dense Jacobian on N(u) = S with variable mobility
+    (n <= 8); phi* = 3/2 phk - 1/2 phkm1.  Returns u (3,n,n,n)."""
+    n = phk.shape[0]
+    P = n ** 3
+    phs = 1.5 * phk - 0.5 * phkm1
+    S = source(phk, phkm1, h, eps)
+    L = lap_matrix(n, h).toarray()
+    Lm = mobility_matrix(n, h, phs, mob).toarray()
+    I, Z = np.eye(P), np.zeros((P, P))
+    u = np.stack([phk.copy(), chemical_potential(phk, h, eps), lap(phk, h)]) if guess is None \
+        else np.array(guess, dtype=np.float64)
+    for _ in range(maxit):
+        r = (S - apply_N_mob(u, phk, phs, h, eps, tau, mob)).ravel()
+        D = np.diag((g_cubic_dphi(u[0], phk) + 0.5 * (1.0 - eps)).ravel())
+        J = np.block([[I, -tau * Lm, Z], [-D, I, -L], [-0.5 * L, Z, I]])
+        du = np.linalg.solve(J, r)
+        u = u + du.reshape(3, n, n, n)
+        if np.max(np.abs(du)) <= tol * max(1.0, np.max(np.abs(u))):
+            break
+    return u
 
 
 def g_cubic(phi, a):

@@ -8,8 +8,10 @@
  * arXiv:1611.06288):
  *   - Section 2: cell-centred periodic grid, 7-point discrete Laplacian,
  *     face differences D_x and the discrete energy F_h (PFC energy-discrete-1);
- *   - Section 3, scheme (1.10), in the form of Section 5 with mobility M = 1:
- *     operator N (scheme-PFC-o1..o3) and source S (scheme-PFC-s1..s3);
+ *   - Section 3, scheme (1.10), in the form of Section 5: operator N
+ *     (scheme-PFC-o1..o3) and source S (scheme-PFC-s1..s3), with mobility
+ *     M = 1 or a variable mobility M(A phi*) on the cell faces (the *_m
+ *     functions);
  *   - Section 5, Algorithm "Nonlinear Multigrid Method (FAS)": nonlinear
  *     red-black Gauss-Seidel smoothing with a pointwise 3x3 solve, residual,
  *     coarsening, coarse solve, correction.
@@ -24,7 +26,12 @@
  *   - the while loop of the algorithm runs at the finest level only; the
  *     residual max-norm over the three components is tested before each cycle;
  *   - local linearisation of the cubic term: Newton (default) or the paper's
- *     Picard form.
+ *     Picard form;
+ *   - variable mobility: M(v) = max(m_min, m0 + m1 v + m2 v^2) (the paper
+ *     leaves M open); its argument on a face is the face average A phi* of
+ *     phi* = 3/2 phi^kappa - 1/2 phi^{kappa-1} (the system of Section 5; the
+ *     smoothing formulas there print 1/2 weights, read as a misprint); coarse
+ *     levels take phi* by the 8-child mean and evaluate M on their own faces.
  *
  * Loops are plain and independent within a red-black colour, so OpenMP
  * "parallel for" is used on the outer z loop where iterations are independent.
@@ -211,6 +218,141 @@ void orc_sweep(int n, double h, double eps, double tau, int picard,
     orc_smooth_half(n, h, eps, tau, picard, 1, u, f, phk);
 }
 
+/* ------------------------------------------------- variable mobility --- */
+
+typedef struct {
+    double m0, m1, m2, mmin;
+} orc_mobility;
+
+static inline double mob_eval(const orc_mobility *mb, double v)
+{
+    double m = mb->m0 + mb->m1 * v + mb->m2 * v * v;
+    return m > mb->mmin ? m : mb->mmin;
+}
+
+/* Mobility on the face between cells p and q: M(A phi*) = M((phs_p + phs_q)/2). */
+static inline double face_mob(const orc_mobility *mb, const double *phs, size_t p, size_t q)
+{
+    return mob_eval(mb, 0.5 * (phs[p] + phs[q]));
+}
+
+/* The six face neighbours of (i,j,k) in the order +x, -x, +y, -y, +z, -z. */
+static inline void nbrs(int n, int i, int j, int k, size_t q[6])
+{
+    q[0] = at(n, i + 1, j, k); q[1] = at(n, i - 1, j, k);
+    q[2] = at(n, i, j + 1, k); q[3] = at(n, i, j - 1, k);
+    q[4] = at(n, i, j, k + 1); q[5] = at(n, i, j, k - 1);
+}
+
+/* Variable-coefficient Laplacian d_x(M D_x v) + d_y(M D_y v) + d_z(M D_z v)
+ * at (i,j,k): sum over the six faces of M_face (v_nbr - v) / h^2. */
+static inline double lapm_at(int n, double h, const double *v, const double *phs,
+                             const orc_mobility *mb, int i, int j, int k)
+{
+    size_t q[6], p = at(n, i, j, k);
+    nbrs(n, i, j, k, q);
+    double s = 0.0;
+    for (int f = 0; f < 6; ++f) s += face_mob(mb, phs, p, q[f]) * (v[q[f]] - v[p]);
+    return s / (h * h);
+}
+
+/* N(u) with variable mobility: N1 = phi - tau d(M D mu); N2, N3 as orc_apply_N. */
+void orc_apply_N_m(int n, double h, double eps, double tau, const double *u, const double *phk,
+                   const double *phs, double m0, double m1, double m2, double mmin, double *out)
+{
+    const orc_mobility mb = {m0, m1, m2, mmin};
+    const size_t P = npts(n);
+    const double *phi = u, *mu = u + P, *om = u + 2 * P;
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                size_t p = at(n, i, j, k);
+                out[p] = phi[p] - tau * lapm_at(n, h, mu, phs, &mb, i, j, k);
+                out[P + p] = mu[p] - g_cubic(phi[p], phk[p]) - 0.5 * (1.0 - eps) * phi[p]
+                             - lap_at(n, h, om, i, j, k);
+                out[2 * P + p] = om[p] - 0.5 * lap_at(n, h, phi, i, j, k);
+            }
+}
+
+double orc_residual_m(int n, double h, double eps, double tau, const double *u, const double *f,
+                      const double *phk, const double *phs, double m0, double m1, double m2,
+                      double mmin, double *r)
+{
+    const size_t P = npts(n);
+    double *Nu = (double *)malloc(3 * P * sizeof(double));
+    orc_apply_N_m(n, h, eps, tau, u, phk, phs, m0, m1, m2, mmin, Nu);
+    double m = 0.0;
+    int bad = 0;
+    for (size_t p = 0; p < 3 * P; ++p) {
+        double d = f[p] - Nu[p];
+        if (r) r[p] = d;
+        if (!isfinite(d)) bad = 1;
+        if (fabs(d) > m) m = fabs(d);
+    }
+    free(Nu);
+    return bad ? NAN : m;
+}
+
+/* Pointwise 3x3 solve with variable mobility: as orc_local_solve with the
+ * first equation phi + a mu = r1, a = tau msum / h^2, r1 = f1 + tau smu / h^2,
+ * where msum is the sum of the six face mobilities and smu the sum of
+ * M_face mu_nbr. */
+void orc_local_solve_m(double h, double eps, double tau, int picard, double phin, double phk,
+                       double f1, double f2, double f3, double msum, double smu, double som,
+                       double sphi, double *phi_out, double *mu_out, double *om_out)
+{
+    const double h2 = h * h;
+    const double a = msum * tau / h2, b = 6.0 / h2, d = 3.0 / h2;
+    double c, r2;
+    if (picard) {
+        double q = 0.25 * (phin * phin + phk * phk);
+        c = q + 0.5 * (1.0 - eps);
+        r2 = f2 + som / h2 + q * phk;
+    } else {
+        double gp = g_cubic_dphi(phin, phk);
+        c = gp + 0.5 * (1.0 - eps);
+        r2 = f2 + som / h2 + g_cubic(phin, phk) - gp * phin;
+    }
+    double r1 = f1 + tau * smu / h2;
+    double r3 = f3 + sphi / (2.0 * h2);
+    double det = 1.0 + a * c + a * b * d;
+    double phi = (r1 - a * r2 + a * b * r3) / det;
+    *phi_out = phi;
+    *mu_out = r2 + c * phi - b * (r3 - d * phi);
+    *om_out = r3 - d * phi;
+}
+
+void orc_smooth_half_m(int n, double h, double eps, double tau, int picard, int colour, double *u,
+                       const double *f, const double *phk, const double *phs, double m0,
+                       double m1, double m2, double mmin)
+{
+    const orc_mobility mb = {m0, m1, m2, mmin};
+    const size_t P = npts(n);
+    double *phi = u, *mu = u + P, *om = u + 2 * P;
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                if (((i + j + k) & 1) != colour) continue;
+                size_t p = at(n, i, j, k), q[6];
+                nbrs(n, i, j, k, q);
+                double msum = 0.0, smu = 0.0;
+                for (int f2 = 0; f2 < 6; ++f2) {
+                    double mf = face_mob(&mb, phs, p, q[f2]);
+                    msum += mf;
+                    smu += mf * mu[q[f2]];
+                }
+                double np_, nm_, no_;
+                orc_local_solve_m(h, eps, tau, picard, phi[p], phk[p], f[p], f[P + p], f[2 * P + p],
+                                  msum, smu, nbr_sum(n, om, i, j, k), nbr_sum(n, phi, i, j, k),
+                                  &np_, &nm_, &no_);
+                phi[p] = np_;
+                mu[p] = nm_;
+                om[p] = no_;
+            }
+}
+
 /* ------------------------------------------------------------ transfers --- */
 
 /* Coarsening: coarse cell = mean of its 8 fine children.  nf = fine size. */
@@ -346,12 +488,60 @@ int orc_coarse_solve(int n, double h, double eps, double tau, double *u,
     return it;
 }
 
+/* The coarsest-level Newton solve with variable mobility: dN1/dmu is
+ * -tau times the variable-coefficient Laplacian. */
+int orc_coarse_solve_m(int n, double h, double eps, double tau, double *u, const double *f,
+                       const double *phk, const double *phs, double m0, double m1, double m2,
+                       double mmin)
+{
+    const orc_mobility mb = {m0, m1, m2, mmin};
+    const int P = (int)npts(n), m = 3 * P;
+    double *J = (double *)malloc((size_t)m * m * sizeof(double));
+    double *r = (double *)malloc((size_t)m * sizeof(double));
+    int it;
+    for (it = 1; it <= 30; ++it) {
+        orc_residual_m(n, h, eps, tau, u, f, phk, phs, m0, m1, m2, mmin, r);
+        memset(J, 0, (size_t)m * m * sizeof(double));
+        for (int p = 0; p < m; ++p) J[(size_t)p * m + p] = 1.0;
+        const double w = -tau / (h * h);                              /* dN1/dmu = -tau d(M D) */
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    size_t p = at(n, i, j, k), q[6];
+                    nbrs(n, i, j, k, q);
+                    for (int f2 = 0; f2 < 6; ++f2) {
+                        double mf = face_mob(&mb, phs, p, q[f2]);
+                        J[p * (size_t)m + P + q[f2]] += w * mf;
+                        J[p * (size_t)m + P + p] -= w * mf;
+                    }
+                }
+        for (int p = 0; p < P; ++p)
+            J[(size_t)(P + p) * m + p] -= g_cubic_dphi(u[p], phk[p]) + 0.5 * (1.0 - eps);
+        add_lap_block(n, h, -1.0, J, 1, 2);
+        add_lap_block(n, h, -0.5, J, 2, 0);
+        if (dense_solve(m, J, r)) { it = -1; break; }
+        double dmax = 0.0, umax = 0.0;
+        for (int p = 0; p < m; ++p) {
+            u[p] += r[p];
+            if (fabs(r[p]) > dmax) dmax = fabs(r[p]);
+            if (fabs(u[p]) > umax) umax = fabs(u[p]);
+        }
+        if (!(dmax == dmax)) { it = -1; break; }
+        if (dmax <= 1e-14 * (umax > 1.0 ? umax : 1.0)) break;
+    }
+    if (it > 30) it = 30;
+    free(J);
+    free(r);
+    return it;
+}
+
 /* --------------------------------------------------------------- solver --- */
 
 typedef struct {
     int n;            /* cells per axis on this level */
     double h;
     double *u, *f, *phk, *ubar, *r;
+    double *phs;      /* phi* (variable mobility only) */
 } orc_level;
 
 typedef struct {
@@ -360,6 +550,8 @@ typedef struct {
     double eps, tau, tol;
     int nu1, nu2, max_cycles, fcycle, picard;
     int coarse_iters_last;
+    int mob_on;
+    orc_mobility mob;
 } orc_solver;
 
 /* Level sizes: halve while even and the half is at least 3. */
@@ -402,9 +594,39 @@ void orc_destroy(orc_solver *s)
     if (!s) return;
     for (int l = 0; l < s->nlev; ++l) {
         free(s->lev[l].u); free(s->lev[l].f); free(s->lev[l].phk);
-        free(s->lev[l].ubar); free(s->lev[l].r);
+        free(s->lev[l].ubar); free(s->lev[l].r); free(s->lev[l].phs);
     }
     free(s);
+}
+
+/* Switches the solver to variable mobility M(v) = max(mmin, m0 + m1 v + m2 v^2). */
+void orc_set_mobility(orc_solver *s, double m0, double m1, double m2, double mmin)
+{
+    s->mob_on = 1;
+    s->mob.m0 = m0; s->mob.m1 = m1; s->mob.m2 = m2; s->mob.mmin = mmin;
+    for (int l = 0; l < s->nlev; ++l)
+        if (!s->lev[l].phs) s->lev[l].phs = (double *)calloc(npts(s->lev[l].n), sizeof(double));
+}
+
+static void sweep_lev(const orc_solver *s, const orc_level *A)
+{
+    if (s->mob_on) {
+        const orc_mobility *m = &s->mob;
+        orc_smooth_half_m(A->n, A->h, s->eps, s->tau, s->picard, 0, A->u, A->f, A->phk, A->phs,
+                          m->m0, m->m1, m->m2, m->mmin);
+        orc_smooth_half_m(A->n, A->h, s->eps, s->tau, s->picard, 1, A->u, A->f, A->phk, A->phs,
+                          m->m0, m->m1, m->m2, m->mmin);
+    } else {
+        orc_sweep(A->n, A->h, s->eps, s->tau, s->picard, A->u, A->f, A->phk);
+    }
+}
+
+static double resid_lev(const orc_solver *s, const orc_level *A, double *r)
+{
+    const orc_mobility *m = &s->mob;
+    return s->mob_on ? orc_residual_m(A->n, A->h, s->eps, s->tau, A->u, A->f, A->phk, A->phs,
+                                      m->m0, m->m1, m->m2, m->mmin, r)
+                     : orc_residual(A->n, A->h, s->eps, s->tau, A->u, A->f, A->phk, r);
 }
 
 int orc_level_n(const orc_solver *s, int l) { return s->lev[l].n; }
@@ -420,20 +642,27 @@ static void cycle(orc_solver *s, int l, int fcycle)
 {
     orc_level *A = &s->lev[l];
     const double eps = s->eps, tau = s->tau;
+    const orc_mobility *m = &s->mob;
     if (l == s->nlev - 1) {
-        s->coarse_iters_last = orc_coarse_solve(A->n, A->h, eps, tau, A->u, A->f, A->phk);
+        s->coarse_iters_last =
+            s->mob_on ? orc_coarse_solve_m(A->n, A->h, eps, tau, A->u, A->f, A->phk, A->phs, m->m0,
+                                           m->m1, m->m2, m->mmin)
+                      : orc_coarse_solve(A->n, A->h, eps, tau, A->u, A->f, A->phk);
         return;
     }
     orc_level *B = &s->lev[l + 1];
     size_t Pc = npts(B->n);
-    for (int q = 0; q < s->nu1; ++q) orc_sweep(A->n, A->h, eps, tau, s->picard, A->u, A->f, A->phk);
+    for (int q = 0; q < s->nu1; ++q) sweep_lev(s, A);
     /* residual, coarsening of residual and iterate */
-    orc_residual(A->n, A->h, eps, tau, A->u, A->f, A->phk, A->r);
+    resid_lev(s, A, A->r);
     restrict3(A->n, A->u, B->ubar);
     restrict3(A->n, A->r, B->f);               /* holds I r for now */
     /* coarse right-hand side f_c = N_c(I u) + I r */
     double *Nc = (double *)malloc(3 * Pc * sizeof(double));
-    orc_apply_N(B->n, B->h, eps, tau, B->ubar, B->phk, Nc);
+    if (s->mob_on)
+        orc_apply_N_m(B->n, B->h, eps, tau, B->ubar, B->phk, B->phs, m->m0, m->m1, m->m2, m->mmin, Nc);
+    else
+        orc_apply_N(B->n, B->h, eps, tau, B->ubar, B->phk, Nc);
     for (size_t p = 0; p < 3 * Pc; ++p) B->f[p] += Nc[p];
     free(Nc);
     memcpy(B->u, B->ubar, 3 * Pc * sizeof(double));
@@ -445,7 +674,7 @@ static void cycle(orc_solver *s, int l, int fcycle)
     size_t Pf = npts(A->n);
     for (int c = 0; c < 3; ++c) orc_prolong_add(B->n, e + c * Pc, A->u + c * Pf);
     free(e);
-    for (int q = 0; q < s->nu2; ++q) orc_sweep(A->n, A->h, eps, tau, s->picard, A->u, A->f, A->phk);
+    for (int q = 0; q < s->nu2; ++q) sweep_lev(s, A);
 }
 
 /* One multigrid cycle at the finest level on a caller-supplied iterate u,
@@ -461,7 +690,17 @@ double orc_cycle(orc_solver *s, double *u, const double *f, const double *phk)
     for (int l = 0; l + 1 < s->nlev; ++l) orc_restrict(s->lev[l].n, s->lev[l].phk, s->lev[l + 1].phk);
     cycle(s, 0, s->fcycle);
     memcpy(u, A->u, 3 * P * sizeof(double));
-    return orc_residual(A->n, A->h, s->eps, s->tau, A->u, A->f, A->phk, NULL);
+    return resid_lev(s, A, NULL);
+}
+
+/* orc_cycle with variable mobility: phs = phi* on the finest grid. */
+double orc_cycle_m(orc_solver *s, double *u, const double *f, const double *phk, const double *phs)
+{
+    if (!s->mob_on) return NAN;
+    orc_level *A = &s->lev[0];
+    memcpy(A->phs, phs, npts(A->n) * sizeof(double));
+    for (int l = 0; l + 1 < s->nlev; ++l) orc_restrict(s->lev[l].n, s->lev[l].phs, s->lev[l + 1].phs);
+    return orc_cycle(s, u, f, phk);
 }
 
 /* One time step of scheme (1.10).  Inputs phkm1 = phi^{kappa-1},
@@ -477,12 +716,17 @@ int orc_step(orc_solver *s, const double *phkm1, const double *phk, double *phi_
     orc_source(A->n, A->h, s->eps, phk, phkm1, A->f);
     memcpy(A->phk, phk, P * sizeof(double));
     for (int l = 0; l + 1 < s->nlev; ++l) orc_restrict(s->lev[l].n, s->lev[l].phk, s->lev[l + 1].phk);
+    if (s->mob_on) {  /* phi* = 3/2 phi^kappa - 1/2 phi^{kappa-1}, on every level */
+        for (size_t p = 0; p < P; ++p) A->phs[p] = 1.5 * phk[p] - 0.5 * phkm1[p];
+        for (int l = 0; l + 1 < s->nlev; ++l)
+            orc_restrict(s->lev[l].n, s->lev[l].phs, s->lev[l + 1].phs);
+    }
     memcpy(A->u, phk, P * sizeof(double));
     memcpy(A->u + P, mu, P * sizeof(double));
     memcpy(A->u + 2 * P, omega, P * sizeof(double));
     int c = 0, status = ORC_OK;
     for (;;) {
-        double rho = orc_residual(A->n, A->h, s->eps, s->tau, A->u, A->f, A->phk, NULL);
+        double rho = resid_lev(s, A, NULL);
         if (res_hist) res_hist[c] = rho;
         if (!(rho == rho) || isinf(rho)) { status = ORC_NONFINITE; break; }
         if (rho <= s->tol) break;
