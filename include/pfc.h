@@ -53,6 +53,9 @@ typedef int32_t pfc_status;
 #define PFC_LIN_NEWTON 0  /* pointwise Newton linearisation of the cubic term    */
 #define PFC_LIN_PICARD 1  /* the Picard linearisation written in Section 5       */
 
+#define PFC_MOBILITY_ONE 0        /* M = 1, the form the convergence theorem uses */
+#define PFC_MOBILITY_QUADRATIC 1  /* variable face mobility, see pfc_config       */
+
 /* Parameters of the problem statement (Sections 2, 3, 5 and 6): grid n^3,
  * box side L, epsilon, time step (tau in Section 3, s in Section 6), residual
  * tolerance, smoothing counts nu1/nu2 of Algorithm algorithm:FAS. */
@@ -64,11 +67,18 @@ typedef struct {
     int32_t cycle;      /* PFC_CYCLE_V or PFC_CYCLE_F                          */
     int32_t lin;        /* PFC_LIN_NEWTON or PFC_LIN_PICARD                    */
     int32_t precision;  /* PFC_FP64 or PFC_MIXED                               */
-    int32_t reserved;   /* must be 0                                           */
+    int32_t mobility;   /* PFC_MOBILITY_ONE or PFC_MOBILITY_QUADRATIC          */
     double L;           /* box side, > 0                                       */
     double eps;         /* epsilon of the PFC energy (energy-PFC)              */
     double dt;          /* time step, > 0                                      */
     double tol;         /* stop when max-norm of S - N(u) (3 components) <= tol */
+    /* PFC_MOBILITY_QUADRATIC: the first equation in the flux form of Section 5,
+     * phi - tau [d_x(M D_x mu) + d_y(M D_y mu) + d_z(M D_z mu)] = phi^k, with
+     * M = max(mob_min, mob_m0 + mob_m1 v + mob_m2 v^2) on each face and v the
+     * face average A phi* of phi* = 3/2 phi^k - 1/2 phi^{k-1} (the paper leaves
+     * M's form open).  mob_min > 0.  FP64 precision only; not available to the
+     * adjoint and batched forms.  Ignored with PFC_MOBILITY_ONE (M = 1). */
+    double mob_m0, mob_m1, mob_m2, mob_min;
 } pfc_config;
 
 /* Per-step report.  res0: residual max-norm before the first cycle;
@@ -87,8 +97,8 @@ typedef struct pfc_handle pfc_handle;
  * (levels n, n/2, ... down to 3 or 4, Section 5) on the current device.
  * stream: a hipStream_t (may be NULL).  Errors: INVALID_ARG for n not of the
  * form 2^k (k >= 2) or 3*2^k (k >= 1), L <= 0, dt <= 0, tol < 0, nu1 or nu2
- * < 0, nu1+nu2 == 0, max_cycles < 1, unknown enum values, Picard with MIXED;
- * OOM; HIP. */
+ * < 0, nu1+nu2 == 0, max_cycles < 1, unknown enum values, Picard with MIXED,
+ * variable mobility with MIXED or with mob_min <= 0; OOM; HIP. */
 pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out);
 pfc_status pfc_destroy(pfc_handle *h);
 pfc_status pfc_set_stream(pfc_handle *h, void *stream);
@@ -122,7 +132,8 @@ pfc_status pfc_step(pfc_handle *h, const double *phi_prev, const double *phi_cur
  * u3: triple [3][n^3] (in/out); f3: triple, right-hand side S at the finest
  * level (scheme-PFC-s1..s3 or any other); phi_cur: phi^k, n^3 (enters N).
  * res_after (host, nullable): max|f3 - N(u3)| after the cycle. Synchronises
- * if res_after is non-NULL. */
+ * if res_after is non-NULL.  With variable mobility N uses the phi* hierarchy
+ * set by pfc_set_phistar (at level 0); INVALID_ARG if none was set. */
 pfc_status pfc_fas_vcycle(pfc_handle *h, double *u3, const double *f3,
                           const double *phi_cur, double *res_after);
 
@@ -157,18 +168,29 @@ pfc_status pfc_adjoint_step(pfc_handle *h, const double *phi_prev, const double 
  * Kernel-level entry points (single multigrid building blocks).  They act on
  * level `level` of the handle's hierarchy (size n_l = pfc_level_size, spacing
  * h_l = L/n_l) and exist so that each kernel can be checked on its own.
+ * With variable mobility each of them uses the phi* stored at its level (by
+ * pfc_set_phistar or by the last pfc_step) and returns INVALID_ARG while that
+ * level holds none.
  * ------------------------------------------------------------------------- */
+
+/* Variable mobility only: stores phi* (natural order, n_l^3, device) at
+ * level l and its 8-child means at every coarser level, the hierarchy that
+ * pfc_step builds from 3/2 phi^k - 1/2 phi^{k-1} (the face mobilities of the
+ * flux form of Section 5 are M(A phi*)).  INVALID_ARG on a handle with
+ * PFC_MOBILITY_ONE.  Asynchronous. */
+pfc_status pfc_set_phistar(pfc_handle *h, int32_t level, const double *phs);
 
 /* Source S of (scheme-PFC-s1..s3) at the finest level: f3 = triple
  * (phi^k, (1-eps)/2 phi^k + 3 Delta_h phi^k - Delta_h phi^{k-1}, Delta_h phi^k / 2). */
 pfc_status pfc_source(pfc_handle *h, const double *phi_prev, const double *phi_cur, double *f3);
 
-/* r3 = f3 - N_l(u3) with N of (scheme-PFC-o1..o3), M = 1, at level l
+/* r3 = f3 - N_l(u3) with N of (scheme-PFC-o1..o3) at level l (M = 1, or the
+ * flux form with the handle's variable mobility)
  * (phk = phi^k on that level).  r3 may be NULL; maxnorm (host, nullable)
  * receives max|r| over the three components.  Synchronises if maxnorm.
  * With r3 NULL on a colour-split level with n a multiple of 64 the norm comes
- * from the column-tile kernel of the stop test; it equals the thread-per-point
- * kernel's bit for bit. */
+ * from the column-tile kernel of the stop test (M = 1 only); it equals the
+ * thread-per-point kernel's bit for bit. */
 pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const double *f3,
                         const double *phk, double *r3, double *maxnorm);
 
@@ -176,7 +198,8 @@ pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const do
  * colour `colour` ((i+j+k) mod 2) at level l, in place on u3; with colour =
  * PFC_SWEEP_FULL, one full sweep (colour 0, then colour 1), the form the
  * cycles use: on levels of at least 128^3 with n a multiple of 64 it runs as
- * a single fused pass whose result equals the two half-sweeps bit for bit. */
+ * a single fused pass whose result equals the two half-sweeps bit for bit
+ * (M = 1 only; variable mobility sweeps colour by colour). */
 #define PFC_SWEEP_FULL 2
 pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3,
                       const double *f3, const double *phk);

@@ -21,6 +21,7 @@ PFC_FP64, PFC_MIXED = 0, 1
 PFC_CYCLE_V, PFC_CYCLE_F = 0, 1
 PFC_LIN_NEWTON, PFC_LIN_PICARD = 0, 1
 PFC_SWEEP_FULL = 2
+PFC_MOBILITY_ONE, PFC_MOBILITY_QUADRATIC = 0, 1
 
 PFC_KERNEL_SMOOTH0 = 0
 PFC_KERNEL_RESIDUAL0 = 1
@@ -38,8 +39,10 @@ class HipLibraryMissing(RuntimeError):
 class PfcConfig(C.Structure):
     _fields_ = [
         ("n", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32), ("max_cycles", C.c_int32),
-        ("cycle", C.c_int32), ("lin", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+        ("cycle", C.c_int32), ("lin", C.c_int32), ("precision", C.c_int32), ("mobility", C.c_int32),
         ("L", C.c_double), ("eps", C.c_double), ("dt", C.c_double), ("tol", C.c_double),
+        ("mob_m0", C.c_double), ("mob_m1", C.c_double), ("mob_m2", C.c_double),
+        ("mob_min", C.c_double),
     ]
 
 
@@ -69,6 +72,7 @@ SIGNATURES = {
     "pfc_restrict": (_i32, [_vp, _i32, _dp, _dp, _i32]),
     "pfc_prolong_add": (_i32, [_vp, _i32, _dp, _dp, _dp, _i32]),
     "pfc_coarse_solve": (_i32, [_vp, _dp, _dp, _dp, C.POINTER(_i32)]),
+    "pfc_set_phistar": (_i32, [_vp, _i32, _dp]),
     "pfc_batch_create": (_i32, [_i32, C.POINTER(PfcConfig), _vp, C.POINTER(_vp)]),
     "pfc_batch_destroy": (_i32, [_vp]),
     "pfc_batch_set_state": (_i32, [_vp, _i32, _dp, _dp, _dp, _dp]),

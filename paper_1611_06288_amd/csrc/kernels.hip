@@ -54,13 +54,26 @@ Lay make_lay(int n, bool split) {
 // ------------------------------------------------------------ residual
 
 // r = f - N(u) at one point (scheme-PFC-o1..o3 with M = 1; DELTA: the
-// correction operator with G in place of g).
-template <typename T, bool DELTA>
+// correction operator with G in place of g; MOB: the first equation in flux
+// form with the face mobilities of op.mob).
+template <typename T, bool DELTA, bool MOB = false>
 __device__ __forceinline__ void resid_at(const OpParams &op, const Tri<const T> &u,
                                          const Tri<const T> &f, const T *phk, const T *base,
                                          const Off &q, double &r1, double &r2, double &r3) {
     const double phi = u.a[q.c], mu = u.b[q.c], om = u.c[q.c];
-    const double lmu = (nsum(u.b, q) - 6.0 * mu) * op.h2inv;
+    double lmu;
+    if constexpr (MOB) {
+        const double *ps = op.mob.phs;
+        const double pc = ps[q.c];
+        const unsigned nb6[6] = {q.xp, q.xm, q.yp, q.ym, q.zp, q.zm};
+        double sm = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+            sm += face_mob(op.mob, pc, ps[nb6[e]]) * ((double)u.b[nb6[e]] - mu);
+        lmu = sm * op.h2inv;
+    } else {
+        lmu = (nsum(u.b, q) - 6.0 * mu) * op.h2inv;
+    }
     const double lom = (nsum(u.c, q) - 6.0 * om) * op.h2inv;
     const double lphi = (nsum(u.a, q) - 6.0 * phi) * op.h2inv;
     const double a = phk[q.c];
@@ -72,7 +85,7 @@ __device__ __forceinline__ void resid_at(const OpParams &op, const Tri<const T> 
 
 // Residual at the point stored at t (written to r if r.a is set); returns the
 // largest |component| as an IEEE bit pattern.
-template <typename T, bool DELTA>
+template <typename T, bool DELTA, bool MOB = false>
 __device__ __forceinline__ unsigned long long resid_bits(const OpParams &op, const Tri<const T> &u,
                                                          const Tri<const T> &f, const T *phk,
                                                          const T *base, const Tri<T> &r,
@@ -81,7 +94,7 @@ __device__ __forceinline__ unsigned long long resid_bits(const OpParams &op, con
     decode(op.lay, t, i, j, k);
     const Off q = offs(op.lay, i, j, k);
     double r1, r2, r3;
-    resid_at<T, DELTA>(op, u, f, phk, base, q, r1, r2, r3);
+    resid_at<T, DELTA, MOB>(op, u, f, phk, base, q, r1, r2, r3);
     if (r.a) {
         r.a[q.c] = (T)r1;
         r.b[q.c] = (T)r2;
@@ -90,7 +103,7 @@ __device__ __forceinline__ unsigned long long resid_bits(const OpParams &op, con
     return umax(abs_bits(r1), umax(abs_bits(r2), abs_bits(r3)));
 }
 
-template <typename T, bool DELTA>
+template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(kBlock) void k_resid_max(OpParams op, Tri<const T> u, Tri<const T> f,
                                                       const T *__restrict__ phk,
                                                       const T *__restrict__ base, Tri<T> r,
@@ -99,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_max(OpParams op, Tri<const T> 
     const unsigned total = (unsigned)npts(L);
     unsigned long long m = 0;
     for (unsigned t = xcd_block() * kBlock + threadIdx.x; t < total; t += gridDim.x * kBlock)
-        m = umax(m, resid_bits<T, DELTA>(op, u, f, phk, base, r, t));
+        m = umax(m, resid_bits<T, DELTA, MOB>(op, u, f, phk, base, r, t));
     m = block_max_u64(m);
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
@@ -108,8 +121,15 @@ template <typename T, bool DELTA>
 int launch_resid_max(hipStream_t s, const OpParams &op, Tri<const T> u, Tri<const T> f,
                      const T *phk, const T *base, Tri<T> r, unsigned long long *partial) {
     const unsigned blocks = reduce_blocks(npts_host(op.lay));
-    hipLaunchKernelGGL((k_resid_max<T, DELTA>), dim3(blocks), dim3(kBlock), 0, s, op, u, f, phk,
-                       base, r, partial);
+    if constexpr (!DELTA) {
+        if (op.mob.phs) {
+            hipLaunchKernelGGL((k_resid_max<T, false, true>), dim3(blocks), dim3(kBlock), 0, s, op,
+                               u, f, phk, base, r, partial);
+            return (int)blocks;
+        }
+    }
+    hipLaunchKernelGGL((k_resid_max<T, DELTA, false>), dim3(blocks), dim3(kBlock), 0, s, op, u, f,
+                       phk, base, r, partial);
     return (int)blocks;
 }
 
@@ -129,7 +149,7 @@ void launch_max_final(hipStream_t s, const unsigned long long *partial, int coun
 //
 // One thread per coarse cell: residual at its 8 children, then the coarse
 // cell's restricted residual I r and restricted iterate I u (8-child means).
-template <typename T, bool DELTA>
+template <typename T, bool DELTA, bool MOB = false>
 __device__ __forceinline__ void resid_restrict_body(const OpParams &op, const Lay &LC,
                                                     Tri<const T> u, Tri<const T> f,
                                                     const T *__restrict__ phk,
@@ -146,7 +166,7 @@ __device__ __forceinline__ void resid_restrict_body(const OpParams &op, const La
     for (int ch = 0; ch < 8; ++ch) {
         const Off q = offs(op.lay, 2 * I + (ch & 1), 2 * J + ((ch >> 1) & 1), 2 * K + (ch >> 2));
         double r1, r2, r3;
-        resid_at<T, DELTA>(op, u, f, phk, base, q, r1, r2, r3);
+        resid_at<T, DELTA, MOB>(op, u, f, phk, base, q, r1, r2, r3);
         s1 += r1;
         s2 += r2;
         s3 += r3;
@@ -162,20 +182,27 @@ __device__ __forceinline__ void resid_restrict_body(const OpParams &op, const La
     ubar_c.c[t] = (T)(0.125 * uc);
 }
 
-template <typename T, bool DELTA>
+template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict(OpParams op, Lay LC, Tri<const T> u,
                                                            Tri<const T> f,
                                                            const T *__restrict__ phk,
                                                            const T *__restrict__ base,
                                                            Tri<T> ubar_c, Tri<T> rr_c) {
-    resid_restrict_body<T, DELTA>(op, LC, u, f, phk, base, ubar_c, rr_c,
-                                  xcd_block() * kBlock + threadIdx.x);
+    resid_restrict_body<T, DELTA, MOB>(op, LC, u, f, phk, base, ubar_c, rr_c,
+                                       xcd_block() * kBlock + threadIdx.x);
 }
 
 template <typename T, bool DELTA>
 void launch_resid_restrict(hipStream_t s, const OpParams &op, const Lay &coarse, Tri<const T> u,
                            Tri<const T> f, const T *phk, const T *base, Tri<T> ubar_c, Tri<T> rr_c) {
-    hipLaunchKernelGGL((k_resid_restrict<T, DELTA>), dim3(blocks_for(npts_host(coarse))),
+    if constexpr (!DELTA) {
+        if (op.mob.phs) {
+            hipLaunchKernelGGL((k_resid_restrict<T, false, true>), dim3(blocks_for(npts_host(coarse))),
+                               dim3(kBlock), 0, s, op, coarse, u, f, phk, base, ubar_c, rr_c);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_resid_restrict<T, DELTA, false>), dim3(blocks_for(npts_host(coarse))),
                        dim3(kBlock), 0, s, op, coarse, u, f, phk, base, ubar_c, rr_c);
 }
 
@@ -207,7 +234,7 @@ void launch_restrict(hipStream_t s, const Lay &fine, const Lay &coarse, const T 
 //
 // Coarse right-hand side of the FAS: f_c = N_c(I u) + I r (f holds I r on
 // entry); also starts the coarse iterate at I u.
-template <typename T, bool DELTA>
+template <typename T, bool DELTA, bool MOB = false>
 __device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                                          const T *__restrict__ phk, const T *__restrict__ base,
                                          unsigned t) {
@@ -217,7 +244,19 @@ __device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, 
     decode(L, t, i, j, k);
     const Off q = offs(L, i, j, k);
     const double phi = ubar.a[t], mu = ubar.b[t], om = ubar.c[t];
-    const double lmu = (nsum(ubar.b, q) - 6.0 * mu) * op.h2inv;
+    double lmu;
+    if constexpr (MOB) {
+        const double *ps = op.mob.phs;
+        const double pc = ps[q.c];
+        const unsigned nb6[6] = {q.xp, q.xm, q.yp, q.ym, q.zp, q.zm};
+        double sm = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+            sm += face_mob(op.mob, pc, ps[nb6[e]]) * ((double)ubar.b[nb6[e]] - mu);
+        lmu = sm * op.h2inv;
+    } else {
+        lmu = (nsum(ubar.b, q) - 6.0 * mu) * op.h2inv;
+    }
     const double lom = (nsum(ubar.c, q) - 6.0 * om) * op.h2inv;
     const double lphi = (nsum(ubar.a, q) - 6.0 * phi) * op.h2inv;
     const double a = phk[t];
@@ -233,18 +272,25 @@ __device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, 
     u.c[t] = ubar.c[t];
 }
 
-template <typename T, bool DELTA>
+template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(kBlock) void k_tau(OpParams op, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                                                 const T *__restrict__ phk,
                                                 const T *__restrict__ base) {
-    tau_body<T, DELTA>(op, ubar, f, u, phk, base, xcd_block() * kBlock + threadIdx.x);
+    tau_body<T, DELTA, MOB>(op, ubar, f, u, phk, base, xcd_block() * kBlock + threadIdx.x);
 }
 
 template <typename T, bool DELTA>
 void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                 const T *phk, const T *base) {
-    hipLaunchKernelGGL((k_tau<T, DELTA>), dim3(blocks_for(npts_host(opc.lay))), dim3(kBlock), 0, s,
-                       opc, ubar, f, u, phk, base);
+    if constexpr (!DELTA) {
+        if (opc.mob.phs) {
+            hipLaunchKernelGGL((k_tau<T, false, true>), dim3(blocks_for(npts_host(opc.lay))),
+                               dim3(kBlock), 0, s, opc, ubar, f, u, phk, base);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_tau<T, DELTA, false>), dim3(blocks_for(npts_host(opc.lay))), dim3(kBlock),
+                       0, s, opc, ubar, f, u, phk, base);
 }
 
 // ------------------------------------------------- interpolation + correction
@@ -417,12 +463,17 @@ void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const
 // rebuilt at the current iterate (which makes that step a Newton step).  The
 // inverse comes from Gauss-Jordan elimination with partial pivoting in LDS.
 // Stops when max|update| <= 1e-14 max(1, max|phi|) (or after 60 iterations).
-template <typename T, bool DELTA>
+// MOB (variable mobility): the outer Lap of the first equation becomes the
+// flux operator L_M = d(M D), so F(phi) = phi - tau L_M(g(phi) + (1-eps)/2 phi)
+// - tau/2 L_M Lap^2 phi - b with b = f1 + tau L_M(f2 + Lap f3); its Jacobian
+// uses the dense Lap^2 (lap2) for the L_M Lap^2 block.
+template <typename T, bool DELTA, bool MOB = false>
 __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<const T> f,
                                             const T *__restrict__ phk, const T *__restrict__ base,
                                             const double *__restrict__ lap1,
                                             const double *__restrict__ lap3, double *minv,
-                                            int *valid, int *iters) {
+                                            int *valid, int *iters,
+                                            const double *__restrict__ lap2 = nullptr) {
     __shared__ double A[64 * 64];  // column-major: A[col * P + row]
     __shared__ double vec[64];
     __shared__ double dvec[64];
@@ -447,6 +498,26 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
         return ((vec[nb[0]] + vec[nb[1]]) + (vec[nb[2]] + vec[nb[3]]) + (vec[nb[4]] + vec[nb[5]]) -
                 6.0 * own) * h2inv;
     };
+    // face mobilities of point p (MOB), and L_M of the field held in vec[]
+    double mf[6] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0}, msum = 6.0;
+    if constexpr (MOB) {
+        if (act) {
+            msum = 0.0;
+            for (int e = 0; e < 6; ++e) {
+                mf[e] = face_mob(op.mob, op.mob.phs[p], op.mob.phs[nb[e]]);
+                msum += mf[e];
+            }
+        }
+    }
+    auto lapo_lds = [&](double own) -> double {  // the first equation's outer operator
+        if constexpr (MOB) {
+            double sm = 0.0;
+            for (int e = 0; e < 6; ++e) sm += mf[e] * (vec[nb[e]] - own);
+            return sm * h2inv;
+        } else {
+            return lap_lds(own);
+        }
+    };
     const double a = act ? (double)phk[p] : 0.0;
     const double bs = (DELTA && act) ? (double)base[p] : 0.0;
     const double F1 = act ? (double)f.a[p] : 0.0;
@@ -460,7 +531,7 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
     __syncthreads();
     vec[p] = F2 + t3;
     __syncthreads();
-    const double bp = F1 + tau * (act ? lap_lds(F2 + t3) : 0.0);
+    const double bp = F1 + tau * (act ? lapo_lds(F2 + t3) : 0.0);
     __syncthreads();
 
     // Builds Minv = F'(x)^{-1} into global memory.
@@ -470,7 +541,18 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
         if (act)
             for (int q = 0; q < P; ++q) {
                 const int o = q * P + p;
-                A[o] = (q == p ? 1.0 : 0.0) - tau * lap1[o] * dvec[q] - 0.5 * tau * lap3[o];
+                if constexpr (MOB) {
+                    // row p of L_M and of L_M Lap^2 (lap2 column-major: [col * P + row])
+                    double lm = q == p ? -msum : 0.0, lmd2 = -msum * lap2[q * P + p];
+                    for (int e = 0; e < 6; ++e) {
+                        if (nb[e] == q) lm += mf[e];
+                        lmd2 += mf[e] * lap2[q * P + nb[e]];
+                    }
+                    A[o] = (q == p ? 1.0 : 0.0) - tau * (lm * h2inv) * dvec[q] -
+                           0.5 * tau * (lmd2 * h2inv);
+                } else {
+                    A[o] = (q == p ? 1.0 : 0.0) - tau * lap1[o] * dvec[q] - 0.5 * tau * lap3[o];
+                }
             }
         __syncthreads();
         gj_invert(A, P, perm);
@@ -490,7 +572,7 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
         const double w = Cubic<DELTA>::g(x, a, bs) + lc * x;
         vec[p] = w;
         __syncthreads();
-        const double lw = act ? lap_lds(w) : 0.0;
+        const double lw = act ? lapo_lds(w) : 0.0;
         __syncthreads();
         vec[p] = x;
         __syncthreads();
@@ -502,7 +584,7 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
         __syncthreads();
         vec[p] = l2;
         __syncthreads();
-        const double l3 = act ? lap_lds(l2) : 0.0;
+        const double l3 = act ? lapo_lds(l2) : 0.0;
         __syncthreads();
         dvec[p] = act ? (x - tau * lw - 0.5 * tau * l3 - bp) : 0.0;
         __syncthreads();
@@ -544,22 +626,30 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
     }
 }
 
-template <typename T, bool DELTA>
+template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const T> f,
                                                const T *__restrict__ phk,
                                                const T *__restrict__ base,
                                                const double *__restrict__ lap1,
                                                const double *__restrict__ lap3, double *minv,
-                                               int *valid, int *iters) {
-    coarse_body<T, DELTA>(op, u, f, phk, base, lap1, lap3, minv, valid, iters);
+                                               int *valid, int *iters,
+                                               const double *__restrict__ lap2) {
+    coarse_body<T, DELTA, MOB>(op, u, f, phk, base, lap1, lap3, minv, valid, iters, lap2);
 }
 
 template <typename T, bool DELTA>
 void launch_coarse(hipStream_t s, const OpParams &op, Tri<T> u, Tri<const T> f, const T *phk,
                    const T *base, const double *lap1, const double *lap3, double *minv, int *,
-                   int *valid, int *iters) {
-    hipLaunchKernelGGL((k_coarse<T, DELTA>), dim3(1), dim3(64), 0, s, op, u, f, phk, base, lap1,
-                       lap3, minv, valid, iters);
+                   int *valid, int *iters, const double *lap2) {
+    if constexpr (!DELTA) {
+        if (op.mob.phs) {
+            hipLaunchKernelGGL((k_coarse<T, false, true>), dim3(1), dim3(64), 0, s, op, u, f, phk,
+                               base, lap1, lap3, minv, valid, iters, lap2);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_coarse<T, DELTA, false>), dim3(1), dim3(64), 0, s, op, u, f, phk, base,
+                       lap1, lap3, minv, valid, iters, lap2);
 }
 
 // --------------------------------------------------------------- source
@@ -589,6 +679,25 @@ void launch_source(hipStream_t s, const OpParams &op, const double *phk, const d
     const Lay nat = make_lay(op.lay.n, false);
     hipLaunchKernelGGL(k_source, dim3(blocks_for(npts_host(nat))), dim3(kBlock), 0, s, op, nat, phk,
                        phkm1, f);
+}
+
+// phi* = 3/2 phi^k - 1/2 phi^{k-1}, the extrapolation at which the variable
+// mobility is evaluated (second order in tau); t runs over storage offsets.
+__global__ __launch_bounds__(kBlock) void k_phistar(Lay L, const double *__restrict__ phk,
+                                                    const double *__restrict__ phkm1,
+                                                    double *__restrict__ out) {
+    const unsigned t = xcd_block() * kBlock + threadIdx.x;
+    if (t >= (unsigned)npts(L)) return;
+    int i, j, k;
+    decode(L, t, i, j, k);
+    const size_t nat = ((size_t)k * L.n + j) * L.n + i;
+    out[t] = 1.5 * phk[nat] - 0.5 * phkm1[nat];
+}
+
+void launch_phistar(hipStream_t s, const Lay &L, const double *phk, const double *phkm1,
+                    double *out) {
+    hipLaunchKernelGGL(k_phistar, dim3(blocks_for(npts_host(L))), dim3(kBlock), 0, s, L, phk, phkm1,
+                       out);
 }
 
 __global__ __launch_bounds__(kBlock) void k_lap(OpParams op, const double *__restrict__ v,
@@ -1000,7 +1109,7 @@ void launch_batch_reset(hipStream_t s, BState st, int count, int **valid) {
                                             unsigned long long *);                                \
     template void launch_coarse<T, DELTA>(hipStream_t, const OpParams &, Tri<T>, Tri<const T>,    \
                                           const T *, const T *, const double *, const double *,   \
-                                          double *, int *, int *, int *);
+                                          double *, int *, int *, int *, const double *);
 
 PFC_INST(double, false)
 PFC_INST(float, true)

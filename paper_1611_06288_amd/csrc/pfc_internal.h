@@ -45,12 +45,21 @@ Lay make_lay(int n, bool split);
 
 inline size_t npts_host(const Lay &L) { return (size_t)L.n * L.n * L.n; }
 
+// Variable mobility M(v) = max(mmin, m0 + m1 v + m2 v^2) of the first
+// equation's flux form, evaluated on each face at the face average of phi*
+// (phi* in the level's layout; null: M = 1).
+struct Mobility {
+    const double *phs = nullptr;
+    double m0 = 1.0, m1 = 0.0, m2 = 0.0, mmin = 0.0;
+};
+
 // Scalar parameters of one level's operator.
 struct OpParams {
     Lay lay;
     double h2inv;  // 1 / h_l^2
     double tau;    // time step
     double eps;    // epsilon
+    Mobility mob{};
 };
 
 constexpr int kBlock = 256;
@@ -131,7 +140,11 @@ void launch_max_final(hipStream_t s, const unsigned long long *partial, int coun
 template <typename T, bool DELTA>
 void launch_coarse(hipStream_t s, const OpParams &op, Tri<T> u, Tri<const T> f, const T *phk,
                    const T *base, const double *lap1, const double *lap3, double *lu, int *piv,
-                   int *lu_valid, int *iters);
+                   int *lu_valid, int *iters, const double *lap2 = nullptr);
+
+// phi* = 3/2 phi^k - 1/2 phi^{k-1} from natural-layout inputs into layout L.
+void launch_phistar(hipStream_t s, const Lay &L, const double *phk, const double *phkm1,
+                    double *out);
 
 // Finest-level source from natural-layout phi^k, phi^{k-1} into layout `op.lay`.
 void launch_source(hipStream_t s, const OpParams &op, const double *phk, const double *phkm1,

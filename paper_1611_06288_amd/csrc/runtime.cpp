@@ -60,12 +60,20 @@ std::string validate_config(const pfc_config *c) {
     if (c->precision != PFC_FP64 && c->precision != PFC_MIXED) return "unknown precision";
     if (c->precision == PFC_MIXED && c->lin != PFC_LIN_NEWTON)
         return "the mixed-precision form uses Newton linearisation only";
-    if (c->reserved != 0) return "reserved must be 0";
+    if (c->mobility != PFC_MOBILITY_ONE && c->mobility != PFC_MOBILITY_QUADRATIC)
+        return "unknown mobility";
+    if (c->mobility == PFC_MOBILITY_QUADRATIC) {
+        if (c->precision != PFC_FP64) return "variable mobility is available in FP64 precision only";
+        if (!std::isfinite(c->mob_m0) || !std::isfinite(c->mob_m1) || !std::isfinite(c->mob_m2))
+            return "mobility coefficients must be finite";
+        if (!(c->mob_min > 0) || !std::isfinite(c->mob_min)) return "mob_min must be > 0";
+    }
     return "";
 }
 
-// Dense Lap and Lap^3 (column-major, n^3 x n^3) on the coarsest level.
-void coarse_matrices(int n, double h, std::vector<double> &l1, std::vector<double> &l3) {
+// Dense Lap, Lap^2 and Lap^3 (column-major, n^3 x n^3) on the coarsest level.
+void coarse_matrices(int n, double h, std::vector<double> &l1, std::vector<double> &l2,
+                     std::vector<double> &l3) {
     const int P = n * n * n;
     auto id = [n](int i, int j, int k) {
         i = (i + n) % n;
@@ -98,10 +106,12 @@ void coarse_matrices(int n, double h, std::vector<double> &l1, std::vector<doubl
             for (int c = 0; c < P; ++c) A3[(size_t)r * P + c] += v * A[(size_t)m * P + c];
         }
     l1.assign((size_t)P * P, 0.0);
+    l2.assign((size_t)P * P, 0.0);
     l3.assign((size_t)P * P, 0.0);
     for (int r = 0; r < P; ++r)
         for (int c = 0; c < P; ++c) {
             l1[(size_t)c * P + r] = A[(size_t)r * P + c];
+            l2[(size_t)c * P + r] = A2[(size_t)r * P + c];
             l3[(size_t)c * P + r] = A3[(size_t)r * P + c];
         }
 }
@@ -119,7 +129,10 @@ pfc_status hip_fail(pfc_handle *H, hipError_t e, const char *what) {
 }
 
 OpParams op_of(const pfc_handle *H, int l) {
-    return OpParams{H->lev[l].lay, H->lev[l].h2inv, H->cfg.dt, H->cfg.eps};
+    OpParams op{H->lev[l].lay, H->lev[l].h2inv, H->cfg.dt, H->cfg.eps};
+    if (H->cfg.mobility == PFC_MOBILITY_QUADRATIC)
+        op.mob = Mobility{H->lev[l].phs, H->cfg.mob_m0, H->cfg.mob_m1, H->cfg.mob_m2, H->cfg.mob_min};
+    return op;
 }
 
 void invalidate_coarse(pfc_handle *H) {
@@ -210,7 +223,8 @@ void cycle64(pfc_handle *H, int l, bool fcycle) {
     if (l == H->nlev - 1) {
         H->begin_timed(PFC_KERNEL_COARSE, l);
         launch_coarse<double, false>(H->stream, op_of(H, l), A.u, cst(A.f), A.phk, nullptr,
-                                     H->lap1, H->lap3, H->minv64, nullptr, H->valid64, H->d_iters);
+                                     H->lap1, H->lap3, H->minv64, nullptr, H->valid64, H->d_iters,
+                                     H->lap2);
         H->end_timed();
         return;
     }
@@ -245,6 +259,16 @@ void restrict_phk(pfc_handle *H) {
         launch_restrict<double>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev[l].phk,
                                 H->lev[l + 1].phk);
 }
+
+// phi* of the variable mobility on every level below `from` by 8-child means.
+static void restrict_phs(pfc_handle *H, int from) {
+    for (int l = from; l + 1 < H->nlev; ++l)
+        launch_restrict<double>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev[l].phs,
+                                H->lev[l + 1].phs);
+    for (int l = from; l < H->nlev; ++l) H->lev[l].phs_set = true;
+}
+
+static bool mobility_on(const pfc_handle *H) { return H->cfg.mobility == PFC_MOBILITY_QUADRATIC; }
 
 pfc_status read_norm(pfc_handle *H, int partials, double *out) {
     launch_max_final(H->stream, H->partial, partials, H->d_scal);
@@ -304,6 +328,10 @@ void step_begin(pfc_handle *H, const double *phi_prev, const double *phi_cur, co
     to_level0(H, phi_cur, mu, omega);
     launch_to_lay<double, double>(H->stream, A.lay, phi_cur, A.phk, 1);
     restrict_phk(H);
+    if (mobility_on(H)) {
+        launch_phistar(H->stream, A.lay, phi_cur, phi_prev, A.phs);
+        restrict_phs(H, 0);
+    }
 }
 void step_end(pfc_handle *H, double *phi_next, double *mu, double *omega) {
     from_level0(H, phi_next, mu, omega);
@@ -361,13 +389,17 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
         double *u, *f, *ub;
         ok = dalloc(H, &u, 3 * A.P) && dalloc(H, &f, 3 * A.P) && dalloc(H, &ub, 3 * A.P) &&
              dalloc(H, &A.phk, A.P);
+        if (ok && cfg->mobility == PFC_MOBILITY_QUADRATIC) ok = dalloc(H, &A.phs, A.P);
         if (!ok) break;
         A.u = Tri<double>{u, u + A.P, u + 2 * A.P};
         A.f = Tri<double>{f, f + A.P, f + 2 * A.P};
         A.ubar = Tri<double>{ub, ub + A.P, ub + 2 * A.P};
-        A.rt = resid_tile_fits(A.lay);
+        // the column-tile residuals and the fused sweep are written for M = 1;
+        // variable mobility runs the pointwise kernels
+        const bool mob = cfg->mobility == PFC_MOBILITY_QUADRATIC;
+        A.rt = !mob && resid_tile_fits(A.lay);
         for (int m = 0; m < RT_MODES; ++m) A.rt_nz[m] = resid_tile_nz(A.n, rt_slots[m], m);
-        A.fused = l < H->nlev - 1 && fused_fits(A.n);
+        A.fused = !mob && l < H->nlev - 1 && fused_fits(A.n);
         if (A.fused || (l == 0 && A.rt)) {
             A.nz = fused_nz(A.n, slots);
             double *u2;
@@ -382,11 +414,12 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
     ok = ok && dalloc(H, &H->minv64, 64 * 64) && dalloc(H, &H->minv32, 64 * 64) &&
          dalloc(H, &H->valid64, 4) && dalloc(H, &H->valid32, 4) &&
          dalloc(H, &H->minv_adj, 64 * 64) && dalloc(H, &H->valid_adj, 4);
-    std::vector<double> l1, l3;
+    std::vector<double> l1, l2, l3;
     if (ok) {
         const Level &C = H->lev[H->nlev - 1];
-        coarse_matrices(C.n, C.h, l1, l3);
-        ok = dalloc(H, &H->lap1, l1.size()) && dalloc(H, &H->lap3, l3.size());
+        coarse_matrices(C.n, C.h, l1, l2, l3);
+        ok = dalloc(H, &H->lap1, l1.size()) && dalloc(H, &H->lap2, l2.size()) &&
+             dalloc(H, &H->lap3, l3.size());
     }
     if (ok && hipHostMalloc((void **)&H->h_pin, 64 * sizeof(double), 0) != hipSuccess) {
         H->h_pin = nullptr;
@@ -397,6 +430,8 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
         return fail(nullptr, PFC_ERR_OOM, "device or pinned allocation failed");
     }
     if (hipMemcpy(H->lap1, l1.data(), l1.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(H->lap2, l2.data(), l2.size() * sizeof(double), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(H->lap3, l3.data(), l3.size() * sizeof(double), hipMemcpyHostToDevice) !=
             hipSuccess ||
@@ -494,6 +529,8 @@ pfc_status pfc_fas_vcycle(pfc_handle *h, double *u3, const double *f3, const dou
                           double *res_after) {
     if (!h) return PFC_ERR_INVALID_ARG;
     if (!u3 || !f3 || !phi_cur) return fail(h, PFC_ERR_INVALID_ARG, "NULL field pointer");
+    if (mobility_on(h) && !h->lev[0].phs_set)
+        return fail(h, PFC_ERR_INVALID_ARG, "variable mobility: phi* not set at level 0");
     Level &A = h->lev[0];
     launch_to_lay<double, double>(h->stream, A.lay, u3, A.u.a, 3);
     launch_to_lay<double, double>(h->stream, A.lay, f3, A.f.a, 3);
@@ -547,6 +584,8 @@ pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const do
                         const double *phk, double *r3, double *maxnorm) {
     if (!h) return PFC_ERR_INVALID_ARG;
     if (!level_ok(h, level) || !u3 || !f3 || !phk) return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
+    if (mobility_on(h) && !h->lev[level].phs_set)
+        return fail(h, PFC_ERR_INVALID_ARG, "variable mobility: phi* not set at this level");
     Level &A = h->lev[level];
     launch_to_lay<double, double>(h->stream, A.lay, u3, A.u.a, 3);
     launch_to_lay<double, double>(h->stream, A.lay, f3, A.f.a, 3);
@@ -580,6 +619,8 @@ pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3, 
     if (!level_ok(h, level) || colour < 0 || colour > PFC_SWEEP_FULL || !u3 || !f3 || !phk ||
         !h->lev[level].lay.split)
         return fail(h, PFC_ERR_INVALID_ARG, "bad argument (level must be a smoothed level)");
+    if (mobility_on(h) && !h->lev[level].phs_set)
+        return fail(h, PFC_ERR_INVALID_ARG, "variable mobility: phi* not set at this level");
     Level &A = h->lev[level];
     launch_to_lay<double, double>(h->stream, A.lay, u3, A.u.a, 3);
     launch_to_lay<double, double>(h->stream, A.lay, f3, A.f.a, 3);
@@ -637,11 +678,13 @@ pfc_status pfc_coarse_solve(pfc_handle *h, double *u3, const double *f3, const d
     if (!h) return PFC_ERR_INVALID_ARG;
     if (!u3 || !f3 || !phk) return fail(h, PFC_ERR_INVALID_ARG, "NULL pointer");
     const int l = h->nlev - 1;
+    if (mobility_on(h) && !h->lev[l].phs_set)
+        return fail(h, PFC_ERR_INVALID_ARG, "variable mobility: phi* not set at the coarsest level");
     const size_t P = h->lev[l].P;
     invalidate_coarse(h);
     launch_coarse<double, false>(h->stream, op_of(h, l), Tri<double>{u3, u3 + P, u3 + 2 * P},
                                  Tri<const double>{f3, f3 + P, f3 + 2 * P}, phk, nullptr, h->lap1,
-                                 h->lap3, h->minv64, nullptr, h->valid64, h->d_iters);
+                                 h->lap3, h->minv64, nullptr, h->valid64, h->d_iters, h->lap2);
     HIP_TRY(h, hipGetLastError());
     if (iters) {
         HIP_TRY(h, hipMemcpyAsync(h->h_pin, h->d_iters, sizeof(int), hipMemcpyDeviceToHost,
@@ -649,6 +692,17 @@ pfc_status pfc_coarse_solve(pfc_handle *h, double *u3, const double *f3, const d
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         std::memcpy(iters, h->h_pin, sizeof(int));
     }
+    return PFC_OK;
+}
+
+pfc_status pfc_set_phistar(pfc_handle *h, int32_t level, const double *phs) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    if (!mobility_on(h)) return fail(h, PFC_ERR_INVALID_ARG, "the handle has constant mobility");
+    if (!level_ok(h, level) || !phs) return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
+    invalidate_coarse(h);
+    launch_to_lay<double, double>(h->stream, h->lev[level].lay, phs, h->lev[level].phs, 1);
+    restrict_phs(h, level);
+    HIP_TRY(h, hipGetLastError());
     return PFC_OK;
 }
 

@@ -25,6 +25,8 @@ struct Level {
     Tri<double> ubar{nullptr, nullptr, nullptr};  // restricted fine iterate I u (scratch on level 0)
     Tri<double> u2{nullptr, nullptr, nullptr};    // second iterate buffer (fused sweeps, fused correction)
     double *phk = nullptr;                        // phi^kappa on this level
+    double *phs = nullptr;                        // phi* of the variable mobility (else null)
+    bool phs_set = false;                         // phs holds a field
     bool fused = false;                           // smoothed by the fused red-black sweep
     int nz = 1;                                   // its plane ranges per column
     bool rt = false;                              // residuals by column tiles
@@ -47,7 +49,8 @@ struct TimedLaunch {
 
 bool level_sizes(int n, std::vector<int> &out);
 std::string validate_config(const pfc_config *c);
-void coarse_matrices(int n, double h, std::vector<double> &l1, std::vector<double> &l3);
+void coarse_matrices(int n, double h, std::vector<double> &l1, std::vector<double> &l2,
+                     std::vector<double> &l3);
 
 }  // namespace pfc
 
@@ -63,7 +66,7 @@ struct pfc_handle {
     double *d_scal = nullptr;
     int *d_iters = nullptr;
     double *h_pin = nullptr;
-    double *lap1 = nullptr, *lap3 = nullptr;
+    double *lap1 = nullptr, *lap2 = nullptr, *lap3 = nullptr;
     double *minv64 = nullptr, *minv32 = nullptr;  // cached coarsest Newton inverses
     int *valid64 = nullptr, *valid32 = nullptr;
     double *minv_adj = nullptr;  // cached coarsest inverse of the adjoint solve

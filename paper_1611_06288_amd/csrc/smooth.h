@@ -41,7 +41,40 @@ __device__ __forceinline__ void point_solve(const OpParams &op, int picard, doub
     mu = r2 + c * phi - B * om;
 }
 
-template <typename T, bool DELTA>
+// Mobility on the face between two cells: M of the average of their phi*.
+__device__ __forceinline__ double face_mob(const Mobility &mb, double pa, double pb) {
+    const double v = 0.5 * (pa + pb);
+    const double m = mb.m0 + mb.m1 * v + mb.m2 * v * v;
+    return m > mb.mmin ? m : mb.mmin;
+}
+
+// Pointwise solve with variable mobility: the first equation becomes
+// phi + A mu = r1 with A = tau msum / h^2 and r1 = f1 + tau smu / h^2, msum the
+// sum of the six face mobilities, smu the sum of M_face mu_nbr.
+__device__ __forceinline__ void point_solve_mob(const OpParams &op, int picard, double phin,
+                                                double a, double f1, double f2, double f3,
+                                                double msum, double smu, double som, double sphi,
+                                                double &phi, double &mu, double &om) {
+    const double h2inv = op.h2inv, tau = op.tau, lin_c = 0.5 * (1.0 - op.eps);
+    double c, r2;
+    if (picard) {
+        const double qq = 0.25 * (phin * phin + a * a);
+        c = qq + lin_c;
+        r2 = f2 + som * h2inv + qq * a;
+    } else {
+        const double gp = Cubic<false>::dg(phin, a, 0.0);
+        c = gp + lin_c;
+        r2 = f2 + som * h2inv + (Cubic<false>::g(phin, a, 0.0) - gp * phin);
+    }
+    const double r1 = f1 + tau * smu * h2inv;
+    const double r3 = f3 + 0.5 * sphi * h2inv;
+    const double A = msum * tau * h2inv, B = 6.0 * h2inv, Dd = 3.0 * h2inv;
+    phi = (r1 - A * r2 + A * B * r3) / (1.0 + A * (c + B * Dd));
+    om = r3 - Dd * phi;
+    mu = r2 + c * phi - B * om;
+}
+
+template <typename T, bool DELTA, bool MOB = false>
 __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int picard, Tri<T> u,
                                             Tri<const T> f, const T *__restrict__ phk,
                                             const T *__restrict__ base, unsigned t) {
@@ -72,9 +105,24 @@ __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int 
     const double sphi = ((double)u.a[xp] + (double)u.a[xm]) + ((double)u.a[yp] + (double)u.a[ym]) +
                         ((double)u.a[zp] + (double)u.a[zm]);
     double phi, mu, om;
-    point_solve<DELTA>(op, picard, (double)u.a[own], (double)phk[own],
-                       DELTA ? (double)base[own] : 0.0, (double)f.a[own], (double)f.b[own],
-                       (double)f.c[own], smu, som, sphi, phi, mu, om);
+    if constexpr (MOB) {  // flux form of the first equation (FP64 only)
+        const double *ps = op.mob.phs;
+        const double pc = ps[own];
+        const size_t nb6[6] = {xp, xm, yp, ym, zp, zm};
+        double msum = 0.0, smm = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double mf = face_mob(op.mob, pc, ps[nb6[q]]);
+            msum += mf;
+            smm += mf * (double)u.b[nb6[q]];
+        }
+        point_solve_mob(op, picard, (double)u.a[own], (double)phk[own], (double)f.a[own],
+                        (double)f.b[own], (double)f.c[own], msum, smm, som, sphi, phi, mu, om);
+    } else {
+        point_solve<DELTA>(op, picard, (double)u.a[own], (double)phk[own],
+                           DELTA ? (double)base[own] : 0.0, (double)f.a[own], (double)f.b[own],
+                           (double)f.c[own], smu, som, sphi, phi, mu, om);
+    }
     u.a[own] = (T)phi;
     u.b[own] = (T)mu;
     u.c[own] = (T)om;

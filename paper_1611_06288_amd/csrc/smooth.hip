@@ -8,19 +8,27 @@
 
 namespace pfc {
 
-template <typename T, bool DELTA>
+template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(kBlock) void k_smooth(OpParams op, int colour, int picard, Tri<T> u,
                                                    Tri<const T> f, const T *__restrict__ phk,
                                                    const T *__restrict__ base) {
-    smooth_body<T, DELTA>(op, colour, picard, u, f, phk, base, xcd_block() * kBlock + threadIdx.x);
+    smooth_body<T, DELTA, MOB>(op, colour, picard, u, f, phk, base,
+                               xcd_block() * kBlock + threadIdx.x);
 }
 
 template <typename T, bool DELTA>
 void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
                    Tri<const T> f, const T *phk, const T *base) {
     const size_t H = npts_host(op.lay) / 2;
-    hipLaunchKernelGGL((k_smooth<T, DELTA>), dim3(blocks_for(H)), dim3(kBlock), 0, s, op, colour,
-                       picard, u, f, phk, base);
+    if constexpr (!DELTA) {
+        if (op.mob.phs) {  // variable mobility
+            hipLaunchKernelGGL((k_smooth<T, false, true>), dim3(blocks_for(H)), dim3(kBlock), 0, s,
+                               op, colour, picard, u, f, phk, base);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_smooth<T, DELTA, false>), dim3(blocks_for(H)), dim3(kBlock), 0, s, op,
+                       colour, picard, u, f, phk, base);
 }
 
 // ------------------------------------------------- fused red-black sweep

@@ -48,11 +48,14 @@ class Solver:
     """One time step of scheme (1.10) by FAS multigrid on an n^3 periodic grid.
 
     Parameters follow the paper's statement of the problem: n, L, eps, time
-    step dt, residual tolerance tol, smoothing counts nu1/nu2."""
+    step dt, residual tolerance tol, smoothing counts nu1/nu2.  ``mobility``
+    (m0, m1, m2, mmin) selects the flux form of the first equation with face
+    mobility M(v) = max(mmin, m0 + m1 v + m2 v^2) at the face average v of
+    phi* = 3/2 phi^k - 1/2 phi^{k-1}; None is M = 1."""
 
     def __init__(self, n: int, L: float, eps: float, dt: float, tol: float = 1e-10,
                  nu1: int = 2, nu2: int = 2, max_cycles: int = 400, cycle: str = "V",
-                 lin: str = "newton", precision: str = "fp64", device=None):
+                 lin: str = "newton", precision: str = "fp64", device=None, mobility=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the PFC solver needs a GPU (torch.cuda.is_available() is False)")
         self.lib = abi.lib()
@@ -65,8 +68,13 @@ class Solver:
         cfg.cycle = {"V": abi.PFC_CYCLE_V, "F": abi.PFC_CYCLE_F}[cycle]
         cfg.lin = {"newton": abi.PFC_LIN_NEWTON, "picard": abi.PFC_LIN_PICARD}[lin]
         cfg.precision = {"fp64": abi.PFC_FP64, "mixed": abi.PFC_MIXED}[precision]
-        cfg.reserved = 0
         cfg.L, cfg.eps, cfg.dt, cfg.tol = self.L, self.eps, self.dt, self.tol
+        self.mobility = None if mobility is None else tuple(float(x) for x in mobility)
+        if self.mobility is None:
+            cfg.mobility = abi.PFC_MOBILITY_ONE
+        else:
+            cfg.mobility = abi.PFC_MOBILITY_QUADRATIC
+            cfg.mob_m0, cfg.mob_m1, cfg.mob_m2, cfg.mob_min = self.mobility
         self.cfg = cfg
         self._h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -213,6 +221,12 @@ class Solver:
                                              _ptr(coarse_ubar, ncomp * nc ** 3, "ubar"),
                                              _ptr(fine, ncomp * nf ** 3, "fine"), ncomp))
 
+    def set_phistar(self, level, phs):
+        """Variable mobility: phi* at `level` (and its 8-child means below)."""
+        self._sync_stream()
+        P = self.level_n(level) ** 3
+        self._check(self.lib.pfc_set_phistar(self._h, level, _ptr(phs, P, "phs")))
+
     def coarse_solve(self, u3, f3, phk):
         self._sync_stream()
         nc = self.levels[-1]
@@ -254,7 +268,7 @@ class Batch:
             c.n, c.nu1, c.nu2, c.max_cycles = int(p["n"]), nu1, nu2, max_cycles
             c.cycle = {"V": abi.PFC_CYCLE_V, "F": abi.PFC_CYCLE_F}[cycle]
             c.lin = {"newton": abi.PFC_LIN_NEWTON, "picard": abi.PFC_LIN_PICARD}[lin]
-            c.precision, c.reserved = abi.PFC_FP64, 0
+            c.precision, c.mobility = abi.PFC_FP64, abi.PFC_MOBILITY_ONE
             c.L, c.eps, c.dt, c.tol = float(p["L"]), float(p["eps"]), float(p["dt"]), float(tol)
         self._b = C.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream

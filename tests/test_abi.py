@@ -2,6 +2,8 @@
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -49,7 +51,7 @@ def test_status_strings_and_create_errors_without_gpu_work():
     L = _lib.lib()
     assert L.pfc_status_string(0) == b"ok"
     assert b"converged" in L.pfc_status_string(2)
-    cfg = _lib.PfcConfig(n=10, nu1=2, nu2=2, max_cycles=10, cycle=0, lin=0, precision=0, reserved=0,
+    cfg = _lib.PfcConfig(n=10, nu1=2, nu2=2, max_cycles=10, cycle=0, lin=0, precision=0, mobility=0,
                          L=10.0, eps=0.1, dt=0.1, tol=1e-10)
     h = ctypes.c_void_p()
     # validation happens before any device call
@@ -64,7 +66,39 @@ def test_status_strings_and_create_errors_without_gpu_work():
     c = _lib.PfcConfig.from_buffer_copy(cfg)
     c.n, c.precision, c.lin = 16, _lib.PFC_MIXED, _lib.PFC_LIN_PICARD
     assert L.pfc_create(ctypes.byref(c), None, ctypes.byref(h)) == _lib.PFC_ERR_INVALID_ARG
+    # variable mobility: enum, FP64 only, mob_min > 0, finite coefficients
+    for field, bad, why in (("mobility", 7, b"unknown mobility"),
+                            ("precision", _lib.PFC_MIXED, b"FP64"),
+                            ("mob_min", 0.0, b"mob_min"),
+                            ("mob_m1", float("inf"), b"finite")):
+        c = _lib.PfcConfig.from_buffer_copy(cfg)
+        c.n, c.mobility, c.mob_m0, c.mob_min = 16, _lib.PFC_MOBILITY_QUADRATIC, 1.0, 0.05
+        setattr(c, field, bad)
+        assert L.pfc_create(ctypes.byref(c), None, ctypes.byref(h)) == _lib.PFC_ERR_INVALID_ARG
+        assert why in L.pfc_last_error(None), (field, L.pfc_last_error(None))
     assert L.pfc_step(None, None, None, None, None, None, None) == _lib.PFC_ERR_INVALID_ARG
+
+
+def test_config_struct_layout_matches_the_header():
+    """Offsets and size of pfc_config as the C compiler lays it out."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in _lib.PfcConfig._fields_]
+    src = "#include <stddef.h>\n#include <stdio.h>\n#include \"pfc.h\"\nint main(void){\n"
+    src += 'printf("%zu\\n", sizeof(pfc_config));\n'
+    for f in fields:
+        src += f'printf("%zu\\n", offsetof(pfc_config, {f}));\n'
+    src += "return 0;}\n"
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        c_path, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(c_path, "w").write(src)
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), c_path, "-o", exe], check=True)
+        out = [int(x) for x in subprocess.run([exe], check=True, capture_output=True,
+                                              text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(_lib.PfcConfig)
+    assert out[1:] == [getattr(_lib.PfcConfig, f).offset for f in fields]
 
 
 def test_solver_refuses_without_gpu():
