@@ -8,7 +8,8 @@ an FP64 residual of 1e-10, synthetic inputs resident in HBM before timing.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 Prints one JSON line: time steps/s of the FP64 path (`value`), its V-cycles/s,
-the same for the mixed-precision form when available, the finest-level
+the same for the mixed-precision form and for the variable-mobility form of
+the same steps, the batched and adjoint forms, the finest-level
 smoother's achieved HBM bandwidth against the 8 TB/s peak (kernel durations
 from HIP events recorded by the library on its stream), and the CPU oracle
 timed on a bounded sample on this host.
@@ -39,6 +40,8 @@ SMOOTHER_TRAFFIC = {"sources_sha256_16": "b6fa55da3c5a3a86", "n": 256,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 SMOOTHER_SOURCES = ("smooth.hip", "smooth.h", "device_common.h")
 METRIC = "time-steps/s & V-cycles/s at 256^3 (FP64 vs mixed); smoother HBM GB/s %peak"
+# (m0, m1, m2, mmin) of the variable-mobility run: M(v) = max(0.05, 1 - v^2)
+MOBILITY = (1.0, 0.0, -1.0, 0.05)
 
 
 def parse():
@@ -49,6 +52,12 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="grid size (256 is the benchmark)")
     ap.add_argument("--cycle", default="V", choices=["V", "F"])
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-mobility", action="store_true",
+                    help="skip the variable-mobility run of the same steps")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="skip the graph-driven time loop runs (pfc_run)")
+    ap.add_argument("--long-steps", type=int, default=2000,
+                    help="steps of the Section 6.2 long-run leg (64^3, tau = 0.01)")
     ap.add_argument("--no-fcycle", action="store_true",
                     help="skip the FP64 F(2,2) run of the same steps (reported beside V)")
     ap.add_argument("--cpu-cycles", type=int, default=3,
@@ -112,11 +121,11 @@ def kernel_stats(s, abi):
     return out
 
 
-def run_path(Solver, abi, torch, precision, state0, p, steps, warmup, cycle):
+def run_path(Solver, abi, torch, precision, state0, p, steps, warmup, cycle, mobility=None):
     """Runs warmup + timed steps from state0 = (prev, cur, mu, om); returns a
     dict of results and the list of phi after every timed step (on device)."""
     s = Solver(p.n, p.L, p.eps, p.dt, tol=p.tol, nu1=p.nu1, nu2=p.nu2, cycle=cycle,
-               precision=precision, max_cycles=1000)
+               precision=precision, max_cycles=1000, mobility=mobility)
     prev, cur, mu, om = (t.clone() for t in state0)
     spare = torch.empty_like(cur)
     for _ in range(warmup):
@@ -146,6 +155,61 @@ def run_path(Solver, abi, torch, precision, state0, p, steps, warmup, cycle):
     }
     s.close()
     return res, phis
+
+
+def run_loop(Solver, torch, state0, p, steps, warmup, cycle):
+    """The same steps through the graph-driven time loop (pfc_run)."""
+    s = Solver(p.n, p.L, p.eps, p.dt, tol=p.tol, nu1=p.nu1, nu2=p.nu2, cycle=cycle, max_cycles=1000)
+    prev, cur, mu, om = (t.clone() for t in state0)
+    if warmup:
+        s.run(prev, cur, mu, om, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = s.run(prev, cur, mu, om, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.close()
+    return {"steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps,
+            "cycles_per_step": [i.cycles for i in infos]}, cur
+
+
+def run_long(Solver, torch, inputs, steps, plain_steps=200):
+    """Section 6.2 growth run (eqn init2, eps = 0.25, [0, 64]^3 at 64^3, tau =
+    0.01): steps/s of the graph-driven loop against the step-by-step driver,
+    from the state at t = 1."""
+    n, L, eps, dt = 64, 64.0, 0.25, 0.01
+    s = Solver(n, L, eps, dt, tol=1e-10)
+    phi0 = torch.from_numpy(inputs.paper_init2(n, seed=11)).cuda()
+    mu, om = s.init_guess(phi0)
+    prev, cur = phi0.clone(), phi0.clone()
+    s.run(prev, cur, mu, om, 100)
+    state = [t.clone() for t in (prev, cur, mu, om)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    spare = torch.empty_like(cur)
+    for _ in range(plain_steps):
+        nxt, _ = s.step(prev, cur, mu, om, out=spare)
+        spare, prev, cur = prev, cur, nxt
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    prev, cur, mu, om = state
+    t0 = time.perf_counter()
+    infos = s.run(prev, cur, mu, om, steps)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    cyc = [i.cycles for i in infos]
+    rate = steps / t_loop
+    s.close()
+    return {
+        "workload": "eqn init2 (0.2 + 0.005 U[0,1], seed 11), 64^3 on [0,64]^3, eps=0.25, "
+                    "tau=0.01, V(2,2) to 1e-10, from t = 1",
+        "steps": steps,
+        "graph_loop_steps_per_s": round(rate, 2),
+        "step_loop_steps_per_s": round(plain_steps / t_plain, 2),
+        "speedup": round(rate / (plain_steps / t_plain), 3),
+        "mean_cycles_per_step": round(sum(cyc) / len(cyc), 3),
+        "hours_for_t_12000": round(1.2e6 / rate / 3600, 2),
+    }
 
 
 def run_batched(torch, inputs, steps, warmup=1):
@@ -308,6 +372,40 @@ def main():
         except PFCError as e:
             mixed = {"unavailable": str(e)}
 
+    mobility = None
+    if not args.no_mobility:
+        # the same steps with the flux form of the first equation and face
+        # mobility M = max(0.05, 1 - v^2) at the face average v of phi*
+        mres, _ = run_path(Solver, abi, torch, "fp64", state0, p, args.steps, args.warmup,
+                           args.cycle, mobility=MOBILITY)
+        mobility = {
+            "mobility": {"m0": MOBILITY[0], "m1": MOBILITY[1], "m2": MOBILITY[2],
+                         "mmin": MOBILITY[3]},
+            "steps_per_s": round(mres["steps_per_s"], 4),
+            "v_cycles_per_s": round(mres["v_cycles_per_s"], 3),
+            "ms_per_step": round(mres["ms_per_step"], 3),
+            "cycles_per_step": mres["cycles_per_step"],
+            "kernels": mres["kernels"],
+        }
+        print(f"variable mobility: {mres['steps_per_s']:.3f} steps/s, cycles "
+              f"{mres['cycles_per_step']}", file=sys.stderr, flush=True)
+
+    loop = None
+    if not args.no_loop:
+        lres, cur_l = run_loop(Solver, torch, state0, p, args.steps, args.warmup, args.cycle)
+        loop = {
+            "steps_per_s": round(lres["steps_per_s"], 4),
+            "ms_per_step": round(lres["ms_per_step"], 3),
+            "cycles_per_step": lres["cycles_per_step"],
+            "speedup_vs_step_loop": round(lres["steps_per_s"] / fp64["steps_per_s"], 4),
+            "max_abs_diff_vs_step_loop": float((cur_l - phis64[-1]).abs().max()),
+        }
+        print(f"graph loop: {lres['steps_per_s']:.3f} steps/s", file=sys.stderr, flush=True)
+        if args.long_steps > 0:
+            loop["long_run"] = run_long(Solver, torch, inputs, args.long_steps)
+            print(f"long run: {loop['long_run']['graph_loop_steps_per_s']} steps/s", file=sys.stderr,
+                  flush=True)
+
     batched = run_batched(torch, inputs, args.batch_steps) if args.batch_steps > 0 else None
     if batched:
         print(f"batched: {batched['instance_steps_per_s']} instance-steps/s", file=sys.stderr, flush=True)
@@ -361,6 +459,8 @@ def main():
         "kernels": fp64["kernels"],
         "fp64_fcycle": fcyc,
         "mixed": mixed,
+        "variable_mobility": mobility,
+        "fp64_graph_loop": loop,
         "batched": batched,
         "adjoint": adjoint,
         "roofline": roofline,

@@ -127,6 +127,23 @@ pfc_status pfc_init_guess(pfc_handle *h, const double *phi0, double *mu, double 
 pfc_status pfc_step(pfc_handle *h, const double *phi_prev, const double *phi_cur,
                     double *phi_next, double *mu, double *omega, pfc_step_info *info);
 
+/* Time loop: advances (phi_prev, phi_cur) = (phi^{k-1}, phi^k) by `steps`
+ * steps of pfc_step, in place: on return phi_prev and phi_cur hold the last
+ * two states and mu, omega the last step's chemical potential and omega (the
+ * next step's guess).  phi_prev and phi_cur must be distinct buffers (for the
+ * bootstrap step copy phi^0 into both).  infos (host, nullable): `steps`
+ * entries.  In FP64 precision one cycle of Algorithm algorithm:FAS and the
+ * residual test before it are recorded once as a hipGraph on a stream the
+ * handle owns and replayed, the loop's decisions taken by a kernel; results
+ * equal those of calling pfc_step `steps` times, bit for bit (a configuration
+ * whose fused sweeps would not return to their buffers over a cycle, odd
+ * nu1 + nu2 at n >= 128, and the mixed form run the pfc_step loop instead).
+ * Per-kernel timing is not recorded by this call.  Stops at the first step
+ * that fails and returns its status (NOT_CONVERGED, NONFINITE: that step's
+ * last iterate is the new phi_cur).  Synchronises once or twice per step. */
+pfc_status pfc_run(pfc_handle *h, double *phi_prev, double *phi_cur, double *mu, double *omega,
+                   int32_t steps, pfc_step_info *infos);
+
 /* Exactly one FP64 multigrid cycle (Algorithm algorithm:FAS, one pass of its
  * loop body at the finest level) on a caller-supplied iterate.
  * u3: triple [3][n^3] (in/out); f3: triple, right-hand side S at the finest

@@ -63,6 +63,7 @@ SIGNATURES = {
     "pfc_level_size": (_i32, [_vp, _i32]),
     "pfc_init_guess": (_i32, [_vp, _dp, _dp, _dp]),
     "pfc_step": (_i32, [_vp, _dp, _dp, _dp, _dp, _dp, C.POINTER(PfcStepInfo)]),
+    "pfc_run": (_i32, [_vp, _dp, _dp, _dp, _dp, _i32, C.POINTER(PfcStepInfo)]),
     "pfc_fas_vcycle": (_i32, [_vp, _dp, _dp, _dp, C.POINTER(C.c_double)]),
     "pfc_energy": (_i32, [_vp, _dp, _dp, C.POINTER(C.c_double)]),
     "pfc_adjoint_step": (_i32, [_vp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _d, C.POINTER(_i32)]),

@@ -23,6 +23,9 @@ __device__ __forceinline__ unsigned xcd_block() {
     return b;
 }
 
+// True when a cycle gate is set and closed (see OpParams::gate).
+__device__ __forceinline__ bool gate_closed(const int *gate) { return gate && *gate == 0; }
+
 __device__ __forceinline__ int wrap_p(int i, int n) { return i == n - 1 ? 0 : i + 1; }
 __device__ __forceinline__ int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 

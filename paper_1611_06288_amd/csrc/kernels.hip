@@ -108,6 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_max(OpParams op, Tri<const T> 
                                                       const T *__restrict__ phk,
                                                       const T *__restrict__ base, Tri<T> r,
                                                       unsigned long long *partial) {
+    if (gate_closed(op.gate)) return;
     const Lay &L = op.lay;
     const unsigned total = (unsigned)npts(L);
     unsigned long long m = 0;
@@ -134,15 +135,59 @@ int launch_resid_max(hipStream_t s, const OpParams &op, Tri<const T> u, Tri<cons
 }
 
 __global__ __launch_bounds__(kBlock) void k_max_final(const unsigned long long *partial, int count,
-                                                      double *out) {
+                                                      double *out, const int *gate) {
+    if (gate_closed(gate)) return;
     unsigned long long m = 0;
     for (int b = threadIdx.x; b < count; b += kBlock) m = umax(m, partial[b]);
     m = block_max_u64(m);
     if (threadIdx.x == 0) out[0] = __longlong_as_double((long long)m);
 }
 
-void launch_max_final(hipStream_t s, const unsigned long long *partial, int count, double *out) {
-    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, partial, count, out);
+void launch_max_final(hipStream_t s, const unsigned long long *partial, int count, double *out,
+                      const int *gate) {
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, partial, count, out, gate);
+}
+
+// ------------------------------------------------ stop test of the time loop
+
+__global__ void k_run_reset(RunState st) {
+    if (threadIdx.x == 0) {
+        *st.active = 1;
+        *st.cycles = 0;
+        *st.status = 0;
+        *st.res0 = 0.0;
+        *st.res = 0.0;
+    }
+}
+
+void launch_run_reset(hipStream_t s, RunState st) {
+    hipLaunchKernelGGL(k_run_reset, dim3(1), dim3(64), 0, s, st);
+}
+
+// The decision the host loop of a time step takes before each cycle: stop on
+// a non-finite norm, on norm <= tol, or when max_cycles cycles have run;
+// otherwise count the cycle that follows.
+__global__ void k_stop_test(const double *rho, double tol, int max_cycles, RunState st) {
+    if (threadIdx.x != 0 || *st.active == 0) return;
+    const double r = *rho;
+    const int c = *st.cycles;
+    if (c == 0) *st.res0 = r;
+    *st.res = r;
+    if (!isfinite(r)) {
+        *st.status = 3;  // PFC_ERR_NONFINITE
+        *st.active = 0;
+    } else if (r <= tol) {
+        *st.active = 0;
+    } else if (c == max_cycles) {
+        *st.status = 2;  // PFC_ERR_NOT_CONVERGED
+        *st.active = 0;
+    } else {
+        *st.cycles = c + 1;
+    }
+}
+
+void launch_stop_test(hipStream_t s, const double *rho, double tol, int max_cycles, RunState st) {
+    hipLaunchKernelGGL(k_stop_test, dim3(1), dim3(64), 0, s, rho, tol, max_cycles, st);
 }
 
 // ------------------------------------------------ residual + coarsening
@@ -188,6 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(OpParams op, Lay LC, 
                                                            const T *__restrict__ phk,
                                                            const T *__restrict__ base,
                                                            Tri<T> ubar_c, Tri<T> rr_c) {
+    if (gate_closed(op.gate)) return;
     resid_restrict_body<T, DELTA, MOB>(op, LC, u, f, phk, base, ubar_c, rr_c,
                                        xcd_block() * kBlock + threadIdx.x);
 }
@@ -276,6 +322,7 @@ template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(kBlock) void k_tau(OpParams op, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                                                 const T *__restrict__ phk,
                                                 const T *__restrict__ base) {
+    if (gate_closed(op.gate)) return;
     tau_body<T, DELTA, MOB>(op, ubar, f, u, phk, base, xcd_block() * kBlock + threadIdx.x);
 }
 
@@ -354,13 +401,16 @@ __device__ __forceinline__ void coarse_err_body(size_t P, Tri<const T> v, Tri<T>
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarse_err(size_t P, Tri<const T> v, Tri<T> ubar) {
+__global__ __launch_bounds__(kBlock) void k_coarse_err(size_t P, Tri<const T> v, Tri<T> ubar,
+                                                       const int *gate) {
+    if (gate_closed(gate)) return;
     coarse_err_body<T>(P, v, ubar, xcd_block() * kBlock + threadIdx.x);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T> v, Tri<const T> ubar,
-                                                    Tri<T> fine) {
+                                                    Tri<T> fine, const int *gate) {
+    if (gate_closed(gate)) return;
     prolong_body<T>(LC, LF, v, ubar, fine, xcd_block() * kBlock + threadIdx.x);
 }
 
@@ -375,8 +425,9 @@ constexpr int kPX = 64, kPY = 8;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_tile(Lay LC, Lay LF, Tri<const T> e,
-                                                         Tri<T> fine) {
+                                                         Tri<T> fine, const int *gate) {
     __shared__ double ce[3][3][kPY / 2 + 2][kPX / 2 + 2];  // [field][K-1..K+1][Y][X]
+    if (gate_closed(gate)) return;
     const int nc = LC.n, nf = LF.n;
     const int nbx = nf / kPX, nby = nf / kPY;
     const int b = (int)xcd_block();
@@ -427,26 +478,26 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tile(Lay LC, Lay LF, Tri<con
 
 template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
-                    Tri<const T> ubar, Tri<T> fine_u) {
+                    Tri<const T> ubar, Tri<T> fine_u, const int *gate) {
     const size_t pairs = (size_t)coarse.n * fine.n * fine.n;
     if (ubar.a && fine_u.b) {
         // e = v - ubar once on the coarse level (in place of ubar), so the
         // fine-level pass loads one coarse array instead of two
         Tri<T> e{const_cast<T *>(ubar.a), const_cast<T *>(ubar.b), const_cast<T *>(ubar.c)};
         hipLaunchKernelGGL((k_coarse_err<T>), dim3(blocks_for(npts_host(coarse))), dim3(kBlock), 0, s,
-                           npts_host(coarse), v, e);
+                           npts_host(coarse), v, e, gate);
         if (fine.split && fine.n % kPX == 0 && fine.n % kPY == 0) {
             const unsigned blocks = (unsigned)((fine.n / kPX) * (fine.n / kPY) * coarse.n);
             hipLaunchKernelGGL((k_prolong_tile<T>), dim3(blocks), dim3(kBlock), 0, s, coarse, fine,
-                               cst(e), fine_u);
+                               cst(e), fine_u, gate);
         } else {
             hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse,
-                               fine, cst(e), Tri<const T>{nullptr, nullptr, nullptr}, fine_u);
+                               fine, cst(e), Tri<const T>{nullptr, nullptr, nullptr}, fine_u, gate);
         }
         return;
     }
     hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine, v,
-                       ubar, fine_u);
+                       ubar, fine_u, gate);
 }
 
 // ------------------------------------------------------ coarsest solve
@@ -634,6 +685,7 @@ __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const 
                                                const double *__restrict__ lap3, double *minv,
                                                int *valid, int *iters,
                                                const double *__restrict__ lap2) {
+    if (gate_closed(op.gate)) return;
     coarse_body<T, DELTA, MOB>(op, u, f, phk, base, lap1, lap3, minv, valid, iters, lap2);
 }
 
@@ -1116,9 +1168,9 @@ PFC_INST(float, true)
 template void launch_restrict<double>(hipStream_t, const Lay &, const Lay &, const double *, double *);
 template void launch_restrict<float>(hipStream_t, const Lay &, const Lay &, const float *, float *);
 template void launch_prolong<double>(hipStream_t, const Lay &, const Lay &, Tri<const double>,
-                                     Tri<const double>, Tri<double>);
+                                     Tri<const double>, Tri<double>, const int *);
 template void launch_prolong<float>(hipStream_t, const Lay &, const Lay &, Tri<const float>,
-                                    Tri<const float>, Tri<float>);
+                                    Tri<const float>, Tri<float>, const int *);
 template void launch_to_lay<double, double>(hipStream_t, const Lay &, const double *, double *, int);
 template void launch_from_lay<double, double>(hipStream_t, const Lay &, const double *, double *, int);
 template void launch_to_lay<double, float>(hipStream_t, const Lay &, const double *, float *, int);

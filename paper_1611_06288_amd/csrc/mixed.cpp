@@ -193,12 +193,14 @@ pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_c
 double algorithmic_bytes(const pfc_handle *H, int kernel) {
     const double P = (double)H->lev[0].P;
     const bool mixed = H->cfg.precision == PFC_MIXED;
-    const double smooth = mixed ? 24.0 : (H->lev[0].fused ? 72.0 : 44.0);
+    // variable mobility (FP64 only) reads phi* once more: 8 B/pt per pass
+    const double mob = H->cfg.mobility == PFC_MOBILITY_QUADRATIC ? 8.0 : 0.0;
+    const double smooth = mixed ? 24.0 : (H->lev[0].fused ? 72.0 : 44.0 + mob);
     switch (kernel) {
         case PFC_KERNEL_SMOOTH0: return smooth * P;
-        case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0) * P;
+        case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0 + mob) * P;
         case PFC_KERNEL_PROLONG0: return (mixed ? 27.0 : 54.0) * P;
-        case PFC_KERNEL_NORM0: return (mixed ? (H->lev[0].rt ? 108.0 : 72.0) : 56.0) * P;
+        case PFC_KERNEL_NORM0: return (mixed ? (H->lev[0].rt ? 108.0 : 72.0) : 56.0 + mob) * P;
         default: return 0.0;
     }
 }

@@ -60,6 +60,9 @@ struct OpParams {
     double tau;    // time step
     double eps;    // epsilon
     Mobility mob{};
+    // Cycle gate (time loop replayed as a graph): when set and *gate == 0 the
+    // cycle's kernels return at once, so cycles after convergence do nothing.
+    const int *gate = nullptr;
 };
 
 constexpr int kBlock = 256;
@@ -124,7 +127,7 @@ void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f,
 // fine += P (v - ubar); ubar.a may be null; fine.b null: one field only.
 template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
-                    Tri<const T> ubar, Tri<T> fine_u);
+                    Tri<const T> ubar, Tri<T> fine_u, const int *gate = nullptr);
 
 // Residual r = f - N(u) (r.a may be null) and per-block maxima of |r| as
 // IEEE bit patterns; returns the number of partials written.
@@ -132,7 +135,23 @@ template <typename T, bool DELTA>
 int launch_resid_max(hipStream_t s, const OpParams &op, Tri<const T> u, Tri<const T> f,
                      const T *phk, const T *base, Tri<T> r, unsigned long long *partial);
 
-void launch_max_final(hipStream_t s, const unsigned long long *partial, int count, double *out);
+void launch_max_final(hipStream_t s, const unsigned long long *partial, int count, double *out,
+                      const int *gate = nullptr);
+
+// Device-side stop test of the time loop: the cycle loop's decision on the
+// norm *rho (the residual max-norm before a cycle), made on the GPU so that a
+// replayed graph of cycles needs no host round trip.  active: cycles still
+// wanted (the gate of the cycle kernels); cycles: cycles started; status: a
+// pfc_status; res0/res: first and latest norm.
+struct RunState {
+    int *active;
+    int *cycles;
+    int *status;
+    double *res0;
+    double *res;
+};
+void launch_run_reset(hipStream_t s, RunState st);
+void launch_stop_test(hipStream_t s, const double *rho, double tol, int max_cycles, RunState st);
 
 // Coarsest level (natural layout, n = 3 or 4).  lu/piv: cached factorisation
 // of the Newton matrix (device scratch of 64*64 doubles and 64 ints), reused

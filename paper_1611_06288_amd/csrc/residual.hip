@@ -42,6 +42,7 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
     constexpr bool CORR = MODE == RT_CAST_CORR;
     using T = typename std::conditional<F32, float, double>::type;
     __shared__ T t[3][3][kRR][kRC];  // [field][plane slot][row][x]
+    if (gate_closed(op.gate)) return;
     Tri<const T> u, f;
     const T *phk, *bs = nullptr;
     Tri<T> ubar, rr;

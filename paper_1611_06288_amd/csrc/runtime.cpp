@@ -132,6 +132,7 @@ OpParams op_of(const pfc_handle *H, int l) {
     OpParams op{H->lev[l].lay, H->lev[l].h2inv, H->cfg.dt, H->cfg.eps};
     if (H->cfg.mobility == PFC_MOBILITY_QUADRATIC)
         op.mob = Mobility{H->lev[l].phs, H->cfg.mob_m0, H->cfg.mob_m1, H->cfg.mob_m2, H->cfg.mob_min};
+    op.gate = H->gate;
     return op;
 }
 
@@ -191,6 +192,11 @@ pfc_handle::~pfc_handle() {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : pool) (void)hipEventDestroy(e);
+    if (run_stream) (void)hipStreamSynchronize(run_stream);
+    if (run_exec) (void)hipGraphExecDestroy(run_exec);
+    if (run_graph) (void)hipGraphDestroy(run_graph);
+    if (run_ev) (void)hipEventDestroy(run_ev);
+    if (run_stream) (void)hipStreamDestroy(run_stream);
     for (void *p : allocs) (void)hipFree(p);
     if (h_pin) (void)hipHostFree(h_pin);
 }
@@ -249,7 +255,7 @@ void cycle64(pfc_handle *H, int l, bool fcycle) {
     cycle64(H, l + 1, fcycle);
     if (fcycle) cycle64(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
-    launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u);
+    launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u, H->gate);
     H->end_timed();
     for (int s = 0; s < H->cfg.nu2; ++s) sweep64(H, l);
 }
@@ -281,8 +287,9 @@ pfc_status read_norm(pfc_handle *H, int partials, double *out) {
     return PFC_OK;
 }
 
-// Residual max-norm at the finest level (r.a may be null).  Synchronises.
-pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out) {
+// Per-workgroup maxima of |S - N(u)| at the finest level into H->partial
+// (written to r too if r.a is set); returns their count.
+static int enqueue_norm(pfc_handle *H, Tri<double> r) {
     Level &A = H->lev[0];
     H->begin_timed(PFC_KERNEL_NORM0, 0);
     int cnt;
@@ -298,7 +305,14 @@ pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out) {
                                               nullptr, r, H->partial);
     }
     H->end_timed();
-    return read_norm(H, cnt, out);
+    return cnt;
+}
+
+int enqueue_norm64(pfc_handle *H) { return enqueue_norm(H, Tri<double>{nullptr, nullptr, nullptr}); }
+
+// Residual max-norm at the finest level (r.a may be null).  Synchronises.
+pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out) {
+    return read_norm(H, enqueue_norm(H, r), out);
 }
 
 }  // namespace pfc
@@ -491,6 +505,16 @@ pfc_status pfc_step(pfc_handle *h, const double *phi_prev, const double *phi_cur
         return fail(h, PFC_ERR_INVALID_ARG, "phi_next aliases an input");
     if (h->cfg.precision == PFC_MIXED)
         return mixed_step(h, phi_prev, phi_cur, phi_next, mu, omega, info);
+    return step64(h, phi_prev, phi_cur, phi_next, mu, omega, info);
+}
+
+}  // extern "C"
+
+namespace pfc {
+// One FP64 time step with the cycle loop on the host (one 8-byte read-back
+// per cycle).
+pfc_status step64(pfc_handle *h, const double *phi_prev, const double *phi_cur, double *phi_next,
+                  double *mu, double *omega, pfc_step_info *info) {
     step_begin(h, phi_prev, phi_cur, mu, omega);
     HIP_TRY(h, hipGetLastError());
     int c = 0;
@@ -524,6 +548,9 @@ pfc_status pfc_step(pfc_handle *h, const double *phi_prev, const double *phi_cur
     if (status != PFC_OK) fail(h, status, pfc_status_string(status));
     return status;
 }
+}  // namespace pfc
+
+extern "C" {
 
 pfc_status pfc_fas_vcycle(pfc_handle *h, double *u3, const double *f3, const double *phi_cur,
                           double *res_after) {

@@ -72,6 +72,17 @@ struct pfc_handle {
     double *minv_adj = nullptr;  // cached coarsest inverse of the adjoint solve
     int *valid_adj = nullptr;
     double *energy_part = nullptr;
+    // graph-driven time loop (pfc_run)
+    const int *gate = nullptr;            // cycle gate, set only while its graph is recorded
+    hipStream_t run_stream = nullptr;     // the loop's own stream (capturable)
+    hipEvent_t run_ev = nullptr;
+    int *d_run = nullptr;                 // active, cycles, status of the current step
+    double *d_runres = nullptr;           // res0, res of the current step
+    hipGraph_t run_graph = nullptr;       // norm, stop test, one gated cycle
+    hipGraphExec_t run_exec = nullptr;
+    const void *run_key[pfc::kMaxLevels] = {};  // level iterates the graph was recorded with
+    double *spare = nullptr;              // third phi buffer of the loop
+    int last_cycles = 0;                  // cycles of the previous step (launch count guess)
     std::string err;
     // instrumentation
     bool timing = false;
@@ -92,8 +103,11 @@ OpParams op_of(const pfc_handle *H, int l);
 void cycle64(pfc_handle *H, int l, bool fcycle);
 void restrict_phk(pfc_handle *H);
 pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out);
+int enqueue_norm64(pfc_handle *H);
 pfc_status read_norm(pfc_handle *H, int partials, double *out);
 pfc_status mixed_init(pfc_handle *H);
+pfc_status step64(pfc_handle *h, const double *phi_prev, const double *phi_cur, double *phi_next,
+                  double *mu, double *omega, pfc_step_info *info);
 pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_cur,
                       double *phi_next, double *mu, double *omega, pfc_step_info *info);
 double algorithmic_bytes(const pfc_handle *H, int kernel);

@@ -12,6 +12,7 @@ template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(kBlock) void k_smooth(OpParams op, int colour, int picard, Tri<T> u,
                                                    Tri<const T> f, const T *__restrict__ phk,
                                                    const T *__restrict__ base) {
+    if (gate_closed(op.gate)) return;
     smooth_body<T, DELTA, MOB>(op, colour, picard, u, f, phk, base,
                                xcd_block() * kBlock + threadIdx.x);
 }
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
     const T *__restrict__ phk, const T *__restrict__ base) {
     __shared__ T c1[3][3][kFCr][kFCs];   // [field][plane slot][row][point] old colour 1
     __shared__ T red[3][3][kFRw][kFSl];  // [field][plane slot][row][point] new colour 0
+    if (gate_closed(op.gate)) return;
     const int n = op.lay.n, hn = n >> 1;
     const unsigned un = (unsigned)n, uhn = (unsigned)hn, H = un * un * uhn;
     const int nbx = n / kFX, nby = n / kFY;

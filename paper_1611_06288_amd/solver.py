@@ -134,6 +134,19 @@ class Solver:
             self._check(st)
         return out, si
 
+    def run(self, phi_prev, phi_cur, mu, omega, steps, raise_on_error=True):
+        """Advances (phi_prev, phi_cur, mu, omega) in place by `steps` steps of
+        the graph-driven time loop; returns the list of StepInfo."""
+        self._sync_stream()
+        infos = (abi.PfcStepInfo * max(1, steps))()
+        P = self.P
+        st = self.lib.pfc_run(self._h, _ptr(phi_prev, P, "phi_prev"), _ptr(phi_cur, P, "phi_cur"),
+                              _ptr(mu, P, "mu"), _ptr(omega, P, "omega"), int(steps), infos)
+        out = [StepInfo(i.cycles, i.status, i.res0, i.res_final) for i in infos[:steps]]
+        if raise_on_error and st != abi.PFC_OK:
+            self._check(st)
+        return out
+
     def vcycle(self, u3, f3, phi_cur):
         """One multigrid cycle in place on u3; returns the residual after it."""
         self._sync_stream()
