@@ -65,6 +65,16 @@ def lib():
         L.orc_set_mobility.argtypes = [vp] + mob
         L.orc_cycle_m.argtypes = [vp, _dp, _dp, _dp, _dp]
         L.orc_cycle_m.restype = d
+        L.orc_apply_N_fo.argtypes = [i, d, d, d, _dp, _dp]
+        L.orc_source_fo.argtypes = [i, d, _dp, _dp]
+        L.orc_residual_fo.argtypes = [i, d, d, d, _dp, _dp, _dp]
+        L.orc_residual_fo.restype = d
+        L.orc_local_solve_fo.argtypes = [d, d, d, i, d, d, d, d, d, d, d, _dp, _dp, _dp]
+        L.orc_smooth_half_fo.argtypes = [i, d, d, d, i, i, _dp, _dp]
+        L.orc_coarse_solve_fo.argtypes = [i, d, d, d, _dp, _dp]
+        L.orc_coarse_solve_fo.restype = i
+        L.orc_set_first_order.argtypes = [vp]
+        L.orc_set_first_order.restype = i
         _lib = L
     return _lib
 
@@ -205,6 +215,54 @@ def coarse_solve_m(u, f, phk, phs, h, eps, tau, mob):
     return u, it
 
 
+# ------------------------------------------------------------------
+# First-order convex-splitting scheme: N1 = phi - tau Lap mu,
+# N2 = mu - phi^3 - (1-eps) phi - Lap omega, N3 = omega - Lap phi;
+# S = (phi^k, 2 Lap phi^k, 0).
+
+def apply_N_fo(u, h, eps, tau):
+    u = _f64(u)
+    out = np.empty_like(u)
+    lib().orc_apply_N_fo(u.shape[1], h, eps, tau, _p(u), _p(out))
+    return out
+
+
+def source_fo(phk, h):
+    phk = _f64(phk)
+    f = np.empty((3,) + phk.shape)
+    lib().orc_source_fo(phk.shape[0], h, _p(phk), _p(f))
+    return f
+
+
+def residual_fo(u, f, h, eps, tau):
+    """Returns (r, max|r|)."""
+    u, f = _f64(u), _f64(f)
+    r = np.empty_like(u)
+    m = lib().orc_residual_fo(u.shape[1], h, eps, tau, _p(u), _p(f), _p(r))
+    return r, m
+
+
+def local_solve_fo(h, eps, tau, picard, phin, f1, f2, f3, smu, som, sphi):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_local_solve_fo(h, eps, tau, int(picard), phin, f1, f2, f3, smu, som, sphi,
+                             C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value
+
+
+def smooth_half_fo(u, f, h, eps, tau, colour, picard=False):
+    u = _f64(u).copy()
+    f = _f64(f)
+    lib().orc_smooth_half_fo(u.shape[1], h, eps, tau, int(picard), int(colour), _p(u), _p(f))
+    return u
+
+
+def coarse_solve_fo(u, f, h, eps, tau):
+    u = _f64(u).copy()
+    f = _f64(f)
+    it = lib().orc_coarse_solve_fo(u.shape[1], h, eps, tau, _p(u), _p(f))
+    return u, it
+
+
 def initial_guess(phi0, h, eps):
     phi0 = _f64(phi0)
     mu = np.empty_like(phi0)
@@ -234,10 +292,12 @@ class StepInfo:
 
 
 class Solver:
-    """FAS solver of one time step of scheme (1.10), M = 1 (C oracle)."""
+    """FAS solver of one time step of scheme (1.10) (C oracle); ``mobility``
+    selects the variable-mobility flux form, ``scheme=1`` the first-order
+    convex-splitting scheme."""
 
     def __init__(self, n, L, eps, dt, tol=1e-10, nu1=2, nu2=2, max_cycles=200,
-                 cycle="V", lin="newton", mobility=None):
+                 cycle="V", lin="newton", mobility=None, scheme=2):
         self.n, self.L, self.eps, self.dt, self.tol = n, L, eps, dt, tol
         self.h = L / n
         self.max_cycles = max_cycles
@@ -248,6 +308,9 @@ class Solver:
         self.mobility = mobility
         if mobility is not None:
             lib().orc_set_mobility(self._s, *[float(x) for x in mobility])
+        self.scheme = scheme
+        if scheme == 1 and lib().orc_set_first_order(self._s) != 0:
+            raise OracleError("the first-order scheme has constant mobility only")
 
     def close(self):
         if self._s:
@@ -289,12 +352,12 @@ class Solver:
 
 
 def simulate(phi0, L, eps, dt, steps, tol=1e-10, nu1=2, nu2=2, cycle="V", lin="newton",
-             max_cycles=400, callback=None, mobility=None):
+             max_cycles=400, callback=None, mobility=None, scheme=2):
     """Runs `steps` time steps from phi0 with the bootstrap phi^{-1} = phi^0.
 
     Returns (list of phi^0..phi^steps, list of StepInfo, final (mu, omega))."""
     n = phi0.shape[0]
-    s = Solver(n, L, eps, dt, tol, nu1, nu2, max_cycles, cycle, lin, mobility)
+    s = Solver(n, L, eps, dt, tol, nu1, nu2, max_cycles, cycle, lin, mobility, scheme)
     mu, om = initial_guess(phi0, L / n, eps)
     phis = [_f64(phi0).copy()]
     infos = []

@@ -235,6 +235,38 @@ def solve_step_dense(phkm1, phk, h, eps, tau, guess=None, tol=1e-14, maxit=50):
     return u
 
 
+def solve_step_fo_phi(phk, h, eps, tau, tol=1e-14, maxit=50):
+    """The first-order convex-splitting step written in phi alone (Section 1:
+    convex part of the energy at the new level, concave part at the old one):
+    phi - tau Lap(phi^3 + (1-eps) phi + Lap^2 phi) = phk + 2 tau Lap^2 phk,
+    by Newton with dense matrices (n <= 12).  Returns (phi, mu, omega) with
+    omega = Lap phi and mu = phi^3 + (1-eps) phi + 2 Lap phk + Lap omega."""
+    n = phk.shape[0]
+    P = n ** 3
+    Lm = lap_matrix(n, h).toarray()
+    L3 = Lm @ Lm @ Lm
+    b = phk.ravel() + 2.0 * tau * (Lm @ (Lm @ phk.ravel()))
+    x = phk.ravel().copy()
+    for _ in range(maxit):
+        G = x - tau * (Lm @ (x ** 3 + (1.0 - eps) * x)) - tau * (L3 @ x) - b
+        J = np.eye(P) - tau * Lm * (3.0 * x ** 2 + (1.0 - eps))[None, :] - tau * L3
+        dx = np.linalg.solve(J, -G)
+        x = x + dx
+        if np.max(np.abs(dx)) <= tol * max(1.0, np.max(np.abs(x))):
+            break
+    phi = x.reshape(n, n, n)
+    om = lap(phi, h)
+    mu = phi ** 3 + (1.0 - eps) * phi + 2.0 * lap(phk, h) + lap(om, h)
+    return np.stack([phi, mu, om])
+
+
+def fo_linear_factor(lam, eps, tau, pbar=0.0):
+    """Amplification of a Fourier mode of -Delta_h-eigenvalue lam about the
+    constant state pbar under the linearised first-order scheme:
+    (1 + 2 tau lam^2) / (1 + tau lam (3 pbar^2 + 1 - eps + lam^2))."""
+    return (1.0 + 2.0 * tau * lam * lam) / (1.0 + tau * lam * (3.0 * pbar * pbar + 1.0 - eps + lam * lam))
+
+
 def _eliminated_rhs(S, h, tau):
     """phi-equation right-hand side after eliminating omega and mu:
     f1 + tau Delta f2 + tau Delta^2 f3."""

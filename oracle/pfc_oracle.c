@@ -12,6 +12,9 @@
  *     (scheme-PFC-o1..o3) and source S (scheme-PFC-s1..s3), with mobility
  *     M = 1 or a variable mobility M(A phi*) on the cell faces (the *_m
  *     functions);
+ *   - Section 1, the first-order convex splitting of the energy (convex part
+ *     implicit, concave part -|grad phi|^2 explicit), as a second scheme on
+ *     the same solver (the *_fo functions);
  *   - Section 5, Algorithm "Nonlinear Multigrid Method (FAS)": nonlinear
  *     red-black Gauss-Seidel smoothing with a pointwise 3x3 solve, residual,
  *     coarsening, coarse solve, correction.
@@ -216,6 +219,118 @@ void orc_sweep(int n, double h, double eps, double tau, int picard,
 {
     orc_smooth_half(n, h, eps, tau, picard, 0, u, f, phk);
     orc_smooth_half(n, h, eps, tau, picard, 1, u, f, phk);
+}
+
+/* ------------------------------------ first-order convex splitting --- */
+
+/* The first-order convex-splitting scheme: the energy (energy-PFC) splits
+ * into the convex part 1/4 phi^4 + (1-eps)/2 phi^2 + 1/2 (Delta phi)^2, taken
+ * at the new time level, and the concave part -|grad phi|^2, taken at the old
+ * one (Section 1):
+ *   phi^{k+1} - phi^k = tau Delta_h mu,
+ *   mu = (phi^{k+1})^3 + (1-eps) phi^{k+1} + 2 Delta_h phi^k + Delta_h omega,
+ *   omega = Delta_h phi^{k+1}.
+ * As N(u) = S with u = (phi^{k+1}, mu, omega):
+ *   N1 = phi - tau Delta_h mu,                       S1 = phi^k,
+ *   N2 = mu - phi^3 - (1-eps) phi - Delta_h omega,   S2 = 2 Delta_h phi^k,
+ *   N3 = omega - Delta_h phi,                        S3 = 0.              */
+void orc_apply_N_fo(int n, double h, double eps, double tau, const double *u, double *out)
+{
+    const size_t P = npts(n);
+    const double *phi = u, *mu = u + P, *om = u + 2 * P;
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                size_t p = at(n, i, j, k);
+                out[p] = phi[p] - tau * lap_at(n, h, mu, i, j, k);
+                out[P + p] = mu[p] - phi[p] * phi[p] * phi[p] - (1.0 - eps) * phi[p]
+                             - lap_at(n, h, om, i, j, k);
+                out[2 * P + p] = om[p] - lap_at(n, h, phi, i, j, k);
+            }
+}
+
+void orc_source_fo(int n, double h, const double *phk, double *f)
+{
+    const size_t P = npts(n);
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                size_t p = at(n, i, j, k);
+                f[p] = phk[p];
+                f[P + p] = 2.0 * lap_at(n, h, phk, i, j, k);
+                f[2 * P + p] = 0.0;
+            }
+}
+
+double orc_residual_fo(int n, double h, double eps, double tau, const double *u, const double *f,
+                       double *r)
+{
+    const size_t P = npts(n);
+    double *Nu = (double *)malloc(3 * P * sizeof(double));
+    orc_apply_N_fo(n, h, eps, tau, u, Nu);
+    double m = 0.0;
+    int bad = 0;
+    for (size_t p = 0; p < 3 * P; ++p) {
+        double d = f[p] - Nu[p];
+        if (r) r[p] = d;
+        if (!isfinite(d)) bad = 1;
+        if (fabs(d) > m) m = fabs(d);
+    }
+    free(Nu);
+    return bad ? NAN : m;
+}
+
+/* Pointwise solve of the first-order system with the neighbours fixed:
+ *     phi + a mu            = r1,   a = 6 tau / h^2
+ *    -c phi + mu + b omega  = r2,   b = 6 / h^2
+ *     d phi + omega         = r3,   d = 6 / h^2
+ * Newton: c = 3 phi_n^2 + (1-eps), r2 includes phi_n^3 - 3 phi_n^2 phi_n;
+ * Picard: phi^3 taken as phi_n^2 phi, c = phi_n^2 + (1-eps). */
+void orc_local_solve_fo(double h, double eps, double tau, int picard, double phin, double f1,
+                        double f2, double f3, double smu, double som, double sphi,
+                        double *phi_out, double *mu_out, double *om_out)
+{
+    const double h2 = h * h;
+    const double a = 6.0 * tau / h2, b = 6.0 / h2, d = 6.0 / h2;
+    double c, r2;
+    if (picard) {
+        c = phin * phin + (1.0 - eps);
+        r2 = f2 + som / h2;
+    } else {
+        double gp = 3.0 * phin * phin;
+        c = gp + (1.0 - eps);
+        r2 = f2 + som / h2 + phin * phin * phin - gp * phin;
+    }
+    double r1 = f1 + tau * smu / h2;
+    double r3 = f3 + sphi / h2;
+    double det = 1.0 + a * c + a * b * d;
+    double phi = (r1 - a * r2 + a * b * r3) / det;
+    *phi_out = phi;
+    *om_out = r3 - d * phi;
+    *mu_out = r2 + c * phi - b * (r3 - d * phi);
+}
+
+void orc_smooth_half_fo(int n, double h, double eps, double tau, int picard, int colour,
+                        double *u, const double *f)
+{
+    const size_t P = npts(n);
+    double *phi = u, *mu = u + P, *om = u + 2 * P;
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                if (((i + j + k) & 1) != colour) continue;
+                size_t p = at(n, i, j, k);
+                double np_, nm_, no_;
+                orc_local_solve_fo(h, eps, tau, picard, phi[p], f[p], f[P + p], f[2 * P + p],
+                                   nbr_sum(n, mu, i, j, k), nbr_sum(n, om, i, j, k),
+                                   nbr_sum(n, phi, i, j, k), &np_, &nm_, &no_);
+                phi[p] = np_;
+                mu[p] = nm_;
+                om[p] = no_;
+            }
 }
 
 /* ------------------------------------------------- variable mobility --- */
@@ -488,6 +603,38 @@ int orc_coarse_solve(int n, double h, double eps, double tau, double *u,
     return it;
 }
 
+/* The coarsest-level Newton solve of the first-order system. */
+int orc_coarse_solve_fo(int n, double h, double eps, double tau, double *u, const double *f)
+{
+    const int P = (int)npts(n), m = 3 * P;
+    double *J = (double *)malloc((size_t)m * m * sizeof(double));
+    double *r = (double *)malloc((size_t)m * sizeof(double));
+    int it;
+    for (it = 1; it <= 30; ++it) {
+        orc_residual_fo(n, h, eps, tau, u, f, r);
+        memset(J, 0, (size_t)m * m * sizeof(double));
+        for (int p = 0; p < m; ++p) J[(size_t)p * m + p] = 1.0;
+        add_lap_block(n, h, -tau, J, 0, 1);                           /* dN1/dmu  = -tau Lap */
+        for (int p = 0; p < P; ++p)                                   /* dN2/dphi */
+            J[(size_t)(P + p) * m + p] -= 3.0 * u[p] * u[p] + (1.0 - eps);
+        add_lap_block(n, h, -1.0, J, 1, 2);                           /* dN2/domega = -Lap */
+        add_lap_block(n, h, -1.0, J, 2, 0);                           /* dN3/dphi = -Lap */
+        if (dense_solve(m, J, r)) { it = -1; break; }
+        double dmax = 0.0, umax = 0.0;
+        for (int p = 0; p < m; ++p) {
+            u[p] += r[p];
+            if (fabs(r[p]) > dmax) dmax = fabs(r[p]);
+            if (fabs(u[p]) > umax) umax = fabs(u[p]);
+        }
+        if (!(dmax == dmax)) { it = -1; break; }
+        if (dmax <= 1e-14 * (umax > 1.0 ? umax : 1.0)) break;
+    }
+    if (it > 30) it = 30;
+    free(J);
+    free(r);
+    return it;
+}
+
 /* The coarsest-level Newton solve with variable mobility: dN1/dmu is
  * -tau times the variable-coefficient Laplacian. */
 int orc_coarse_solve_m(int n, double h, double eps, double tau, double *u, const double *f,
@@ -552,6 +699,7 @@ typedef struct {
     int coarse_iters_last;
     int mob_on;
     orc_mobility mob;
+    int first_order;  /* the first-order convex-splitting scheme */
 } orc_solver;
 
 /* Level sizes: halve while even and the half is at least 3. */
@@ -608,9 +756,21 @@ void orc_set_mobility(orc_solver *s, double m0, double m1, double m2, double mmi
         if (!s->lev[l].phs) s->lev[l].phs = (double *)calloc(npts(s->lev[l].n), sizeof(double));
 }
 
+/* Switches the solver to the first-order convex-splitting scheme (M = 1 only).
+ * Returns 0, or -1 if variable mobility is on. */
+int orc_set_first_order(orc_solver *s)
+{
+    if (s->mob_on) return -1;
+    s->first_order = 1;
+    return 0;
+}
+
 static void sweep_lev(const orc_solver *s, const orc_level *A)
 {
-    if (s->mob_on) {
+    if (s->first_order) {
+        orc_smooth_half_fo(A->n, A->h, s->eps, s->tau, s->picard, 0, A->u, A->f);
+        orc_smooth_half_fo(A->n, A->h, s->eps, s->tau, s->picard, 1, A->u, A->f);
+    } else if (s->mob_on) {
         const orc_mobility *m = &s->mob;
         orc_smooth_half_m(A->n, A->h, s->eps, s->tau, s->picard, 0, A->u, A->f, A->phk, A->phs,
                           m->m0, m->m1, m->m2, m->mmin);
@@ -624,6 +784,7 @@ static void sweep_lev(const orc_solver *s, const orc_level *A)
 static double resid_lev(const orc_solver *s, const orc_level *A, double *r)
 {
     const orc_mobility *m = &s->mob;
+    if (s->first_order) return orc_residual_fo(A->n, A->h, s->eps, s->tau, A->u, A->f, r);
     return s->mob_on ? orc_residual_m(A->n, A->h, s->eps, s->tau, A->u, A->f, A->phk, A->phs,
                                       m->m0, m->m1, m->m2, m->mmin, r)
                      : orc_residual(A->n, A->h, s->eps, s->tau, A->u, A->f, A->phk, r);
@@ -645,7 +806,8 @@ static void cycle(orc_solver *s, int l, int fcycle)
     const orc_mobility *m = &s->mob;
     if (l == s->nlev - 1) {
         s->coarse_iters_last =
-            s->mob_on ? orc_coarse_solve_m(A->n, A->h, eps, tau, A->u, A->f, A->phk, A->phs, m->m0,
+            s->first_order ? orc_coarse_solve_fo(A->n, A->h, eps, tau, A->u, A->f)
+            : s->mob_on ? orc_coarse_solve_m(A->n, A->h, eps, tau, A->u, A->f, A->phk, A->phs, m->m0,
                                            m->m1, m->m2, m->mmin)
                       : orc_coarse_solve(A->n, A->h, eps, tau, A->u, A->f, A->phk);
         return;
@@ -659,7 +821,9 @@ static void cycle(orc_solver *s, int l, int fcycle)
     restrict3(A->n, A->r, B->f);               /* holds I r for now */
     /* coarse right-hand side f_c = N_c(I u) + I r */
     double *Nc = (double *)malloc(3 * Pc * sizeof(double));
-    if (s->mob_on)
+    if (s->first_order)
+        orc_apply_N_fo(B->n, B->h, eps, tau, B->ubar, Nc);
+    else if (s->mob_on)
         orc_apply_N_m(B->n, B->h, eps, tau, B->ubar, B->phk, B->phs, m->m0, m->m1, m->m2, m->mmin, Nc);
     else
         orc_apply_N(B->n, B->h, eps, tau, B->ubar, B->phk, Nc);
@@ -713,7 +877,10 @@ int orc_step(orc_solver *s, const double *phkm1, const double *phk, double *phi_
 {
     orc_level *A = &s->lev[0];
     size_t P = npts(A->n);
-    orc_source(A->n, A->h, s->eps, phk, phkm1, A->f);
+    if (s->first_order)
+        orc_source_fo(A->n, A->h, phk, A->f);
+    else
+        orc_source(A->n, A->h, s->eps, phk, phkm1, A->f);
     memcpy(A->phk, phk, P * sizeof(double));
     for (int l = 0; l + 1 < s->nlev; ++l) orc_restrict(s->lev[l].n, s->lev[l].phk, s->lev[l + 1].phk);
     if (s->mob_on) {  /* phi* = 3/2 phi^kappa - 1/2 phi^{kappa-1}, on every level */
