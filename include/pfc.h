@@ -53,6 +53,9 @@ typedef int32_t pfc_status;
 #define PFC_LIN_NEWTON 0  /* pointwise Newton linearisation of the cubic term    */
 #define PFC_LIN_PICARD 1  /* the Picard linearisation written in Section 5       */
 
+#define PFC_SCHEME_CS2 0  /* second-order convex splitting, scheme (1.10)         */
+#define PFC_SCHEME_CS1 1  /* first-order convex splitting (see pfc_config)       */
+
 #define PFC_MOBILITY_ONE 0        /* M = 1, the form the convergence theorem uses */
 #define PFC_MOBILITY_QUADRATIC 1  /* variable face mobility, see pfc_config       */
 
@@ -79,6 +82,15 @@ typedef struct {
      * M's form open).  mob_min > 0.  FP64 precision only; not available to the
      * adjoint and batched forms.  Ignored with PFC_MOBILITY_ONE (M = 1). */
     double mob_m0, mob_m1, mob_m2, mob_min;
+    /* PFC_SCHEME_CS2 (scheme (1.10), the default) or PFC_SCHEME_CS1: the
+     * first-order convex splitting of Section 1 (convex part of the energy
+     * implicit, -|grad phi|^2 explicit), in the same three-field form
+     *   phi - tau Lap mu = phi^k,
+     *   mu - phi^3 - (1-eps) phi - Lap omega = 2 Lap phi^k,
+     *   omega - Lap phi = 0
+     * (phi^{k-1} unused).  FP64, M = 1; not available to the adjoint and
+     * batched forms. */
+    int32_t scheme;
 } pfc_config;
 
 /* Per-step report.  res0: residual max-norm before the first cycle;
@@ -98,7 +110,8 @@ typedef struct pfc_handle pfc_handle;
  * stream: a hipStream_t (may be NULL).  Errors: INVALID_ARG for n not of the
  * form 2^k (k >= 2) or 3*2^k (k >= 1), L <= 0, dt <= 0, tol < 0, nu1 or nu2
  * < 0, nu1+nu2 == 0, max_cycles < 1, unknown enum values, Picard with MIXED,
- * variable mobility with MIXED or with mob_min <= 0; OOM; HIP. */
+ * variable mobility with MIXED or with mob_min <= 0, the first-order scheme
+ * with MIXED or variable mobility; OOM; HIP. */
 pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out);
 pfc_status pfc_destroy(pfc_handle *h);
 pfc_status pfc_set_stream(pfc_handle *h, void *stream);

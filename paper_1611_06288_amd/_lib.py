@@ -22,6 +22,7 @@ PFC_CYCLE_V, PFC_CYCLE_F = 0, 1
 PFC_LIN_NEWTON, PFC_LIN_PICARD = 0, 1
 PFC_SWEEP_FULL = 2
 PFC_MOBILITY_ONE, PFC_MOBILITY_QUADRATIC = 0, 1
+PFC_SCHEME_CS2, PFC_SCHEME_CS1 = 0, 1
 
 PFC_KERNEL_SMOOTH0 = 0
 PFC_KERNEL_RESIDUAL0 = 1
@@ -42,7 +43,7 @@ class PfcConfig(C.Structure):
         ("cycle", C.c_int32), ("lin", C.c_int32), ("precision", C.c_int32), ("mobility", C.c_int32),
         ("L", C.c_double), ("eps", C.c_double), ("dt", C.c_double), ("tol", C.c_double),
         ("mob_m0", C.c_double), ("mob_m1", C.c_double), ("mob_m2", C.c_double),
-        ("mob_min", C.c_double),
+        ("mob_min", C.c_double), ("scheme", C.c_int32),
     ]
 
 

@@ -386,6 +386,8 @@ extern "C" pfc_status pfc_adjoint_step(pfc_handle *h, const double *phi_prev, co
         return pfc::fail(h, PFC_ERR_INVALID_ARG, "adj_tol must be > 0");
     if (h->cfg.mobility != PFC_MOBILITY_ONE)
         return pfc::fail(h, PFC_ERR_INVALID_ARG, "the adjoint is derived for constant mobility");
+    if (h->cfg.scheme != PFC_SCHEME_CS2)
+        return pfc::fail(h, PFC_ERR_INVALID_ARG, "the adjoint is derived for scheme (1.10)");
     if (gbar_next == gbar_cur || gbar_next == gbar_prev)
         return pfc::fail(h, PFC_ERR_INVALID_ARG, "gbar_next aliases an output");
     return pfc::adjoint_step(h, phi_prev, phi_cur, phi_next, gbar_next, gbar_cur, gbar_prev, geps,

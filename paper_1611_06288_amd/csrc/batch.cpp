@@ -259,6 +259,8 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
         if (cfgs[i].precision != PFC_FP64) return bfail(nullptr, PFC_ERR_INVALID_ARG, "the batched form is FP64");
         if (cfgs[i].mobility != PFC_MOBILITY_ONE)
             return bfail(nullptr, PFC_ERR_INVALID_ARG, "the batched form has constant mobility");
+        if (cfgs[i].scheme != PFC_SCHEME_CS2)
+            return bfail(nullptr, PFC_ERR_INVALID_ARG, "the batched form runs scheme (1.10)");
         if (cfgs[i].nu1 != cfgs[0].nu1 || cfgs[i].nu2 != cfgs[0].nu2 || cfgs[i].cycle != cfgs[0].cycle ||
             cfgs[i].lin != cfgs[0].lin || cfgs[i].tol != cfgs[0].tol || cfgs[i].max_cycles != cfgs[0].max_cycles)
             return bfail(nullptr, PFC_ERR_INVALID_ARG, "nu1, nu2, cycle, lin, tol, max_cycles must agree");

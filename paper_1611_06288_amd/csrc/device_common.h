@@ -148,6 +148,26 @@ struct Cubic<true> {
     }
 };
 
+// The parts of N that differ between the two schemes (OpParams::fo).  The
+// first-order convex splitting takes the cubic term as x^3 and the linear one
+// as (1-eps) x in N2, and N3 = omega - Lap phi; the second-order scheme takes
+// g(x; a), (1-eps)/2 x and N3 = omega - Lap phi / 2.  (The correction form of
+// the mixed-precision cycle exists for the second-order scheme only.)
+template <bool DELTA>
+__device__ __forceinline__ double g_of(int fo, double x, double a, double b) {
+    if (!DELTA && fo) return x * x * x;
+    return Cubic<DELTA>::g(x, a, b);
+}
+template <bool DELTA>
+__device__ __forceinline__ double dg_of(int fo, double x, double a, double b) {
+    if (!DELTA && fo) return 3.0 * x * x;
+    return Cubic<DELTA>::dg(x, a, b);
+}
+__device__ __forceinline__ double lin_of(const OpParams &op) {
+    return op.fo ? 1.0 - op.eps : 0.5 * (1.0 - op.eps);
+}
+__device__ __forceinline__ double w3_of(const OpParams &op) { return op.fo ? 1.0 : 0.5; }
+
 __device__ __forceinline__ unsigned long long abs_bits(double v) {
     return (unsigned long long)__double_as_longlong(v) & 0x7fffffffffffffffull;
 }

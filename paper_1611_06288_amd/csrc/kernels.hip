@@ -79,8 +79,8 @@ __device__ __forceinline__ void resid_at(const OpParams &op, const Tri<const T> 
     const double a = phk[q.c];
     const double b = DELTA ? (double)base[q.c] : 0.0;
     r1 = (double)f.a[q.c] - (phi - op.tau * lmu);
-    r2 = (double)f.b[q.c] - (mu - Cubic<DELTA>::g(phi, a, b) - 0.5 * (1.0 - op.eps) * phi - lom);
-    r3 = (double)f.c[q.c] - (om - 0.5 * lphi);
+    r2 = (double)f.b[q.c] - (mu - g_of<DELTA>(op.fo, phi, a, b) - lin_of(op) * phi - lom);
+    r3 = (double)f.c[q.c] - (om - w3_of(op) * lphi);
 }
 
 // Residual at the point stored at t (written to r if r.a is set); returns the
@@ -308,8 +308,8 @@ __device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, 
     const double a = phk[t];
     const double b = DELTA ? (double)base[t] : 0.0;
     const double n1 = phi - op.tau * lmu;
-    const double n2 = mu - Cubic<DELTA>::g(phi, a, b) - 0.5 * (1.0 - op.eps) * phi - lom;
-    const double n3 = om - 0.5 * lphi;
+    const double n2 = mu - g_of<DELTA>(op.fo, phi, a, b) - lin_of(op) * phi - lom;
+    const double n3 = om - w3_of(op) * lphi;
     f.a[t] = (T)((double)f.a[t] + n1);
     f.b[t] = (T)((double)f.b[t] + n2);
     f.c[t] = (T)((double)f.c[t] + n3);
@@ -514,6 +514,8 @@ void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const
 // rebuilt at the current iterate (which makes that step a Newton step).  The
 // inverse comes from Gauss-Jordan elimination with partial pivoting in LDS.
 // Stops when max|update| <= 1e-14 max(1, max|phi|) (or after 60 iterations).
+// First-order scheme (op.fo): g(phi) = phi^3, (1-eps) phi, the Lap^3 term with
+// tau instead of tau/2 and omega = f3 + Lap phi.
 // MOB (variable mobility): the outer Lap of the first equation becomes the
 // flux operator L_M = d(M D), so F(phi) = phi - tau L_M(g(phi) + (1-eps)/2 phi)
 // - tau/2 L_M Lap^2 phi - b with b = f1 + tau L_M(f2 + Lap f3); its Jacobian
@@ -532,7 +534,7 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
     const int n = op.lay.n, P = n * n * n;
     const int p = threadIdx.x;
     const bool act = p < P;
-    const double h2inv = op.h2inv, tau = op.tau, lc = 0.5 * (1.0 - op.eps);
+    const double h2inv = op.h2inv, tau = op.tau, lc = lin_of(op), w3 = w3_of(op);
 
     int nb[6] = {0, 0, 0, 0, 0, 0};
     if (act) {
@@ -587,7 +589,7 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
 
     // Builds Minv = F'(x)^{-1} into global memory.
     auto rebuild = [&]() {
-        dvec[p] = Cubic<DELTA>::dg(x, a, bs) + lc;
+        dvec[p] = dg_of<DELTA>(op.fo, x, a, bs) + lc;
         __syncthreads();
         if (act)
             for (int q = 0; q < P; ++q) {
@@ -602,7 +604,7 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
                     A[o] = (q == p ? 1.0 : 0.0) - tau * (lm * h2inv) * dvec[q] -
                            0.5 * tau * (lmd2 * h2inv);
                 } else {
-                    A[o] = (q == p ? 1.0 : 0.0) - tau * lap1[o] * dvec[q] - 0.5 * tau * lap3[o];
+                    A[o] = (q == p ? 1.0 : 0.0) - tau * lap1[o] * dvec[q] - w3 * tau * lap3[o];
                 }
             }
         __syncthreads();
@@ -620,7 +622,7 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
     double dprev = 0.0;
     int it;
     for (it = 1; it <= 60; ++it) {
-        const double w = Cubic<DELTA>::g(x, a, bs) + lc * x;
+        const double w = g_of<DELTA>(op.fo, x, a, bs) + lc * x;
         vec[p] = w;
         __syncthreads();
         const double lw = act ? lapo_lds(w) : 0.0;
@@ -637,7 +639,7 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
         __syncthreads();
         const double l3 = act ? lapo_lds(l2) : 0.0;
         __syncthreads();
-        dvec[p] = act ? (x - tau * lw - 0.5 * tau * l3 - bp) : 0.0;
+        dvec[p] = act ? (x - tau * lw - w3 * tau * l3 - bp) : 0.0;
         __syncthreads();
         double d = 0.0;
         if (act)
@@ -661,11 +663,11 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
     __syncthreads();
     const double lx = act ? lap_lds(x) : 0.0;
     __syncthreads();
-    const double om = F3 + 0.5 * lx;
+    const double om = F3 + w3 * lx;
     vec[p] = om;
     __syncthreads();
     const double lom = act ? lap_lds(om) : 0.0;
-    const double mu = F2 + Cubic<DELTA>::g(x, a, bs) + lc * x + lom;
+    const double mu = F2 + g_of<DELTA>(op.fo, x, a, bs) + lc * x + lom;
     if (act) {
         u.a[p] = (T)x;
         u.b[p] = (T)mu;
@@ -708,7 +710,7 @@ void launch_coarse(hipStream_t s, const OpParams &op, Tri<T> u, Tri<const T> f, 
 
 // S of (scheme-PFC-s1..s3) from natural-layout phi^k and phi^{k-1}, written
 // in layout op.lay: f1 = phk, f2 = (1-eps)/2 phk + 3 Lap phk - Lap phkm1,
-// f3 = Lap phk / 2.
+// f3 = Lap phk / 2; for the first-order scheme (phk, 2 Lap phk, 0).
 __global__ __launch_bounds__(kBlock) void k_source(OpParams op, Lay nat, const double *__restrict__ phk,
                                                    const double *__restrict__ phkm1,
                                                    Tri<double> f) {
@@ -722,8 +724,13 @@ __global__ __launch_bounds__(kBlock) void k_source(OpParams op, Lay nat, const d
     const double lkm1 = (nsum(phkm1, q) - 6.0 * phkm1[q.c]) * op.h2inv;
     const unsigned o = sidx32(op.lay, i, j, k);
     f.a[o] = v;
-    f.b[o] = 0.5 * (1.0 - op.eps) * v + 3.0 * lk - lkm1;
-    f.c[o] = 0.5 * lk;
+    if (op.fo) {  // first-order scheme: (phi^k, 2 Lap phi^k, 0)
+        f.b[o] = 2.0 * lk;
+        f.c[o] = 0.0;
+    } else {
+        f.b[o] = 0.5 * (1.0 - op.eps) * v + 3.0 * lk - lkm1;
+        f.c[o] = 0.5 * lk;
+    }
 }
 
 void launch_source(hipStream_t s, const OpParams &op, const double *phk, const double *phkm1,

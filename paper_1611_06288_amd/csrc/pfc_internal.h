@@ -59,6 +59,9 @@ struct OpParams {
     double h2inv;  // 1 / h_l^2
     double tau;    // time step
     double eps;    // epsilon
+    // 1: the first-order convex-splitting scheme (N2 with phi^3 and (1-eps)
+    // phi, N3 = omega - Lap phi); 0: the second-order scheme of Section 5
+    int fo = 0;
     Mobility mob{};
     // Cycle gate (time loop replayed as a graph): when set and *gate == 0 the
     // cycle's kernels return at once, so cycles after convergence do nothing.

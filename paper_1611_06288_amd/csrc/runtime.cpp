@@ -68,6 +68,10 @@ std::string validate_config(const pfc_config *c) {
             return "mobility coefficients must be finite";
         if (!(c->mob_min > 0) || !std::isfinite(c->mob_min)) return "mob_min must be > 0";
     }
+    if (c->scheme != PFC_SCHEME_CS2 && c->scheme != PFC_SCHEME_CS1) return "unknown scheme";
+    if (c->scheme == PFC_SCHEME_CS1 &&
+        (c->precision != PFC_FP64 || c->mobility != PFC_MOBILITY_ONE))
+        return "the first-order scheme is available in FP64 with M = 1 only";
     return "";
 }
 
@@ -130,6 +134,7 @@ pfc_status hip_fail(pfc_handle *H, hipError_t e, const char *what) {
 
 OpParams op_of(const pfc_handle *H, int l) {
     OpParams op{H->lev[l].lay, H->lev[l].h2inv, H->cfg.dt, H->cfg.eps};
+    op.fo = H->cfg.scheme == PFC_SCHEME_CS1 ? 1 : 0;
     if (H->cfg.mobility == PFC_MOBILITY_QUADRATIC)
         op.mob = Mobility{H->lev[l].phs, H->cfg.mob_m0, H->cfg.mob_m1, H->cfg.mob_m2, H->cfg.mob_min};
     op.gate = H->gate;

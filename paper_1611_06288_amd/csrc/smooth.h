@@ -14,6 +14,7 @@ namespace pfc {
 //     phi + A mu             = r1     A = 6 tau/h^2, r1 = f1 + tau S_mu/h^2
 //    -c phi + mu + B omega   = r2     B = 6/h^2,     r2 = f2 + S_om/h^2 + (lin.)
 //     Dd phi + omega         = r3     Dd = 3/h^2,    r3 = f3 + S_phi/(2h^2)
+// (first-order scheme: Dd = 6/h^2, r3 = f3 + S_phi/h^2).
 // c is the linearised slope of the cubic term; eliminating omega and mu gives
 // phi = (r1 - A r2 + A B r3) / (1 + A (c + B Dd)).
 // One thread per point of colour `colour` (colour-split storage only).
@@ -22,20 +23,20 @@ __device__ __forceinline__ void point_solve(const OpParams &op, int picard, doub
                                             double b, double f1, double f2, double f3, double smu,
                                             double som, double sphi, double &phi, double &mu,
                                             double &om) {
-    const double h2inv = op.h2inv, tau = op.tau, lin_c = 0.5 * (1.0 - op.eps);
+    const double h2inv = op.h2inv, tau = op.tau, lin_c = lin_of(op);
     double c, r2;
-    if (!DELTA && picard) {
-        const double qq = 0.25 * (phin * phin + a * a);
+    if (!DELTA && picard) {  // second order: 1/4(phin^2 + a^2) phi; first order: phin^2 phi
+        const double qq = op.fo ? phin * phin : 0.25 * (phin * phin + a * a);
         c = qq + lin_c;
-        r2 = f2 + som * h2inv + qq * a;
+        r2 = f2 + som * h2inv + (op.fo ? 0.0 : qq * a);
     } else {
-        const double gp = Cubic<DELTA>::dg(phin, a, b);
+        const double gp = dg_of<DELTA>(op.fo, phin, a, b);
         c = gp + lin_c;
-        r2 = f2 + som * h2inv + (Cubic<DELTA>::g(phin, a, b) - gp * phin);
+        r2 = f2 + som * h2inv + (g_of<DELTA>(op.fo, phin, a, b) - gp * phin);
     }
     const double r1 = f1 + tau * smu * h2inv;
-    const double r3 = f3 + 0.5 * sphi * h2inv;
-    const double A = 6.0 * tau * h2inv, B = 6.0 * h2inv, Dd = 3.0 * h2inv;
+    const double r3 = f3 + w3_of(op) * sphi * h2inv;
+    const double A = 6.0 * tau * h2inv, B = 6.0 * h2inv, Dd = (op.fo ? 6.0 : 3.0) * h2inv;
     phi = (r1 - A * r2 + A * B * r3) / (1.0 + A * (c + B * Dd));
     om = r3 - Dd * phi;
     mu = r2 + c * phi - B * om;

@@ -51,11 +51,13 @@ class Solver:
     step dt, residual tolerance tol, smoothing counts nu1/nu2.  ``mobility``
     (m0, m1, m2, mmin) selects the flux form of the first equation with face
     mobility M(v) = max(mmin, m0 + m1 v + m2 v^2) at the face average v of
-    phi* = 3/2 phi^k - 1/2 phi^{k-1}; None is M = 1."""
+    phi* = 3/2 phi^k - 1/2 phi^{k-1}; None is M = 1.  ``scheme`` 2 is scheme
+    (1.10), 1 the first-order convex splitting (phi_prev then unused)."""
 
     def __init__(self, n: int, L: float, eps: float, dt: float, tol: float = 1e-10,
                  nu1: int = 2, nu2: int = 2, max_cycles: int = 400, cycle: str = "V",
-                 lin: str = "newton", precision: str = "fp64", device=None, mobility=None):
+                 lin: str = "newton", precision: str = "fp64", device=None, mobility=None,
+                 scheme: int = 2):
         if not torch.cuda.is_available():
             raise RuntimeError("the PFC solver needs a GPU (torch.cuda.is_available() is False)")
         self.lib = abi.lib()
@@ -69,6 +71,8 @@ class Solver:
         cfg.lin = {"newton": abi.PFC_LIN_NEWTON, "picard": abi.PFC_LIN_PICARD}[lin]
         cfg.precision = {"fp64": abi.PFC_FP64, "mixed": abi.PFC_MIXED}[precision]
         cfg.L, cfg.eps, cfg.dt, cfg.tol = self.L, self.eps, self.dt, self.tol
+        cfg.scheme = {2: abi.PFC_SCHEME_CS2, 1: abi.PFC_SCHEME_CS1}[scheme]
+        self.scheme = scheme
         self.mobility = None if mobility is None else tuple(float(x) for x in mobility)
         if self.mobility is None:
             cfg.mobility = abi.PFC_MOBILITY_ONE

@@ -66,11 +66,17 @@ def test_status_strings_and_create_errors_without_gpu_work():
     c = _lib.PfcConfig.from_buffer_copy(cfg)
     c.n, c.precision, c.lin = 16, _lib.PFC_MIXED, _lib.PFC_LIN_PICARD
     assert L.pfc_create(ctypes.byref(c), None, ctypes.byref(h)) == _lib.PFC_ERR_INVALID_ARG
+    for prec, bad in ((_lib.PFC_FP64, 5), (_lib.PFC_MIXED, _lib.PFC_SCHEME_CS1)):
+        c = _lib.PfcConfig.from_buffer_copy(cfg)
+        c.n, c.precision, c.scheme = 16, prec, bad
+        assert L.pfc_create(ctypes.byref(c), None, ctypes.byref(h)) == _lib.PFC_ERR_INVALID_ARG
+        assert b"scheme" in L.pfc_last_error(None)
     # variable mobility: enum, FP64 only, mob_min > 0, finite coefficients
     for field, bad, why in (("mobility", 7, b"unknown mobility"),
                             ("precision", _lib.PFC_MIXED, b"FP64"),
                             ("mob_min", 0.0, b"mob_min"),
-                            ("mob_m1", float("inf"), b"finite")):
+                            ("mob_m1", float("inf"), b"finite"),
+                            ("scheme", _lib.PFC_SCHEME_CS1, b"first-order")):
         c = _lib.PfcConfig.from_buffer_copy(cfg)
         c.n, c.mobility, c.mob_m0, c.mob_min = 16, _lib.PFC_MOBILITY_QUADRATIC, 1.0, 0.05
         setattr(c, field, bad)
