@@ -8,8 +8,10 @@ an FP64 residual of 1e-10, synthetic inputs resident in HBM before timing.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 Prints one JSON line: time steps/s of the FP64 path (`value`), its V-cycles/s,
-the same for the mixed-precision form and for the variable-mobility form of
-the same steps, the batched and adjoint forms, the finest-level
+the same for the mixed-precision form, the variable-mobility form and the
+first-order convex-splitting scheme on the same workload, the graph-driven
+time loop (and the long run of Section 6.2), the batched and adjoint forms,
+the finest-level
 smoother's achieved HBM bandwidth against the 8 TB/s peak (kernel durations
 from HIP events recorded by the library on its stream), and the CPU oracle
 timed on a bounded sample on this host.
@@ -35,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the smoother sources
 # it was measured on (first 16 hex digits of the sha256 of smooth.hip, smooth.h
 # and device_common.h, concatenated); otherwise reported null.
-SMOOTHER_TRAFFIC = {"sources_sha256_16": "b6fa55da3c5a3a86", "n": 256,
-                    "fetch_KiB": 467966, "write_KiB": 395553,
+SMOOTHER_TRAFFIC = {"sources_sha256_16": "386cb0f04ea9c3e7", "n": 256,
+                    "fetch_KiB": 464996, "write_KiB": 395507,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 SMOOTHER_SOURCES = ("smooth.hip", "smooth.h", "device_common.h")
 METRIC = "time-steps/s & V-cycles/s at 256^3 (FP64 vs mixed); smoother HBM GB/s %peak"
@@ -54,6 +56,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-mobility", action="store_true",
                     help="skip the variable-mobility run of the same steps")
+    ap.add_argument("--no-first-order", action="store_true",
+                    help="skip the first-order convex-splitting run of the same workload")
     ap.add_argument("--no-loop", action="store_true",
                     help="skip the graph-driven time loop runs (pfc_run)")
     ap.add_argument("--long-steps", type=int, default=2000,
@@ -121,11 +125,12 @@ def kernel_stats(s, abi):
     return out
 
 
-def run_path(Solver, abi, torch, precision, state0, p, steps, warmup, cycle, mobility=None):
+def run_path(Solver, abi, torch, precision, state0, p, steps, warmup, cycle, mobility=None,
+             scheme=2):
     """Runs warmup + timed steps from state0 = (prev, cur, mu, om); returns a
     dict of results and the list of phi after every timed step (on device)."""
     s = Solver(p.n, p.L, p.eps, p.dt, tol=p.tol, nu1=p.nu1, nu2=p.nu2, cycle=cycle,
-               precision=precision, max_cycles=1000, mobility=mobility)
+               precision=precision, max_cycles=1000, mobility=mobility, scheme=scheme)
     prev, cur, mu, om = (t.clone() for t in state0)
     spare = torch.empty_like(cur)
     for _ in range(warmup):
@@ -390,6 +395,22 @@ def main():
         print(f"variable mobility: {mres['steps_per_s']:.3f} steps/s, cycles "
               f"{mres['cycles_per_step']}", file=sys.stderr, flush=True)
 
+    first = None
+    if not args.no_first_order:
+        # the first-order convex-splitting scheme on the same workload
+        fres, _ = run_path(Solver, abi, torch, "fp64", state0, p, args.steps, args.warmup,
+                           args.cycle, scheme=1)
+        first = {
+            "scheme": "first-order convex splitting",
+            "steps_per_s": round(fres["steps_per_s"], 4),
+            "v_cycles_per_s": round(fres["v_cycles_per_s"], 3),
+            "ms_per_step": round(fres["ms_per_step"], 3),
+            "cycles_per_step": fres["cycles_per_step"],
+            "kernels": fres["kernels"],
+        }
+        print(f"first-order scheme: {fres['steps_per_s']:.3f} steps/s, cycles "
+              f"{fres['cycles_per_step']}", file=sys.stderr, flush=True)
+
     loop = None
     if not args.no_loop:
         lres, cur_l = run_loop(Solver, torch, state0, p, args.steps, args.warmup, args.cycle)
@@ -460,6 +481,7 @@ def main():
         "fp64_fcycle": fcyc,
         "mixed": mixed,
         "variable_mobility": mobility,
+        "first_order_scheme": first,
         "fp64_graph_loop": loop,
         "batched": batched,
         "adjoint": adjoint,
