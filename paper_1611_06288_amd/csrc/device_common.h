@@ -168,6 +168,13 @@ __device__ __forceinline__ double lin_of(const OpParams &op) {
 }
 __device__ __forceinline__ double w3_of(const OpParams &op) { return op.fo ? 1.0 : 0.5; }
 
+// Mobility on the face between two cells: M of the average of their phi*.
+__device__ __forceinline__ double face_mob(const Mobility &mb, double pa, double pb) {
+    const double v = 0.5 * (pa + pb);
+    const double m = mb.m0 + mb.m1 * v + mb.m2 * v * v;
+    return m > mb.mmin ? m : mb.mmin;
+}
+
 __device__ __forceinline__ unsigned long long abs_bits(double v) {
     return (unsigned long long)__double_as_longlong(v) & 0x7fffffffffffffffull;
 }

@@ -195,7 +195,7 @@ double algorithmic_bytes(const pfc_handle *H, int kernel) {
     const bool mixed = H->cfg.precision == PFC_MIXED;
     // variable mobility (FP64 only) reads phi* once more: 8 B/pt per pass
     const double mob = H->cfg.mobility == PFC_MOBILITY_QUADRATIC ? 8.0 : 0.0;
-    const double smooth = mixed ? 24.0 : (H->lev[0].fused ? 72.0 : 44.0 + mob);
+    const double smooth = mixed ? 24.0 : (H->lev[0].fused ? 72.0 : 44.0) + mob;
     switch (kernel) {
         case PFC_KERNEL_SMOOTH0: return smooth * P;
         case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0 + mob) * P;

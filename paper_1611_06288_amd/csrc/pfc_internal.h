@@ -86,7 +86,7 @@ template <typename T, bool DELTA>
 void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
                         Tri<T> uout, Tri<const T> f, const T *phk, const T *base);
 bool fused_fits(int n);           // n admits the fused sweep's column tiling
-int fused_slots(int device);      // resident fused-sweep workgroups on the device (0 on error)
+int fused_slots(int device, bool mob = false);      // resident fused-sweep workgroups on the device (0 on error)
 int fused_nz(int n, int slots);   // plane ranges per column for a level of size n
 constexpr int kFusedMinN = 128;  // smaller levels use the half-sweeps
 
@@ -111,7 +111,7 @@ struct ResidTileArgs {
     unsigned long long *partial = nullptr;  // RT_NORM, RT_CAST*: per-workgroup max |r|
 };
 bool resid_tile_fits(const Lay &L);
-int resid_tile_slots(int device, int mode);   // resident workgroups (0 on error)
+int resid_tile_slots(int device, int mode, bool mob = false);   // resident workgroups (0 on error)
 int resid_tile_nz(int n, int slots, int mode);
 int launch_resid_tile(hipStream_t s, int mode, const OpParams &op, int nz,
                       const ResidTileArgs &a);  // returns the workgroup count

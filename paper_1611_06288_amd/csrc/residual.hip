@@ -21,6 +21,8 @@
 // points per plane.  The arithmetic and, for the restrictions, the order of
 // the 8-child sums equal those of the thread-per-point kernels (and u + e that
 // of the separate correction kernel), so results agree bitwise with them.
+// MOB (variable mobility; RT_NORM and RT_RESTRICT): phi* is a fourth field of
+// the ring and the first equation takes the face-mobility flux sum.
 #include "device_common.h"
 
 #include <algorithm>
@@ -33,7 +35,7 @@ constexpr int kRX = 64, kRY = 8, kRT = 256;            // column extents, thread
 constexpr int kRC = kRX + 2, kRR = kRY + 2;            // tile with its ring
 constexpr int kRN = kRC * kRR, kRI = (kRN + kRT - 1) / kRT;  // ring points, per thread
 
-template <int MODE>
+template <int MODE, bool MOB>
 __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTileArgs a) {
     constexpr bool F32 = MODE == RT_RESTRICT32;
     constexpr bool DELTA = F32;
@@ -41,7 +43,8 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
     constexpr bool CAST = MODE == RT_CAST || MODE == RT_CAST_CORR;
     constexpr bool CORR = MODE == RT_CAST_CORR;
     using T = typename std::conditional<F32, float, double>::type;
-    __shared__ T t[3][3][kRR][kRC];  // [field][plane slot][row][x]
+    constexpr int NF = MOB ? 4 : 3;  // ring fields: phi, mu, omega (, phi*)
+    __shared__ T t[NF][3][kRR][kRC];  // [field][plane slot][row][x]
     if (gate_closed(op.gate)) return;
     Tri<const T> u, f;
     const T *phk, *bs = nullptr;
@@ -79,7 +82,7 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
     auto wn = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
     auto slot = [z0](int p) { return (p - z0 + 3) % 3; };  // p >= z0 - 1
 
-    T pre[kRI][3];
+    T pre[kRI][NF];
     auto load_plane = [&](int p) {
         const int pw = wn(p);
 #pragma unroll
@@ -93,6 +96,7 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
                 pre[i][0] = u.a[g];
                 pre[i][1] = u.b[g];
                 pre[i][2] = u.c[g];
+                if constexpr (MOB) pre[i][3] = op.mob.phs[g];
                 if constexpr (CORR) {
                     pre[i][0] += (double)a.e.a[g];
                     pre[i][1] += (double)a.e.b[g];
@@ -111,6 +115,7 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
                 t[0][s][r][col] = pre[i][0];
                 t[1][s][r][col] = pre[i][1];
                 t[2][s][r][col] = pre[i][2];
+                if constexpr (MOB) t[3][s][r][col] = pre[i][3];
             }
         }
     };
@@ -169,6 +174,21 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
             }
             const double phi = uu[e][0], mu = uu[e][1], om = uu[e][2], ak = (double)cur[e][3];
             const double bb = DELTA ? (double)cur[e][NO - 1] : 0.0;
+            if constexpr (MOB) {  // flux form, faces in the order xp, xm, yp, ym, zp, zm
+                const double pc = (double)t[3][s0][row][col];
+                double sm6 = 0.0;
+                auto face = [&](int sl3, int rw, int cl) {
+                    sm6 += face_mob(op.mob, pc, (double)t[3][sl3][rw][cl]) *
+                           ((double)t[1][sl3][rw][cl] - mu);
+                };
+                face(s0, row, col + 1);
+                face(s0, row, col - 1);
+                face(s0, row + 1, col);
+                face(s0, row - 1, col);
+                face(sp, row, col);
+                face(sm, row, col);
+                ls[1] = sm6 * h2inv;
+            }
             r[e][0] = (double)cur[e][0] - (phi - tau * ls[1]);
             r[e][1] = (double)cur[e][1] -
                       (mu - g_of<DELTA>(op.fo, phi, ak, bb) - lin_c * phi - ls[2]);
@@ -239,19 +259,23 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
 
 bool resid_tile_fits(const Lay &L) { return L.split && L.n % kRX == 0 && L.n % kRY == 0; }
 
-static const void *resid_tile_fn(int mode) {
+static const void *resid_tile_fn(int mode, bool mob) {
     switch (mode) {
-        case RT_RESTRICT: return (const void *)k_resid_tile<RT_RESTRICT>;
-        case RT_CAST: return (const void *)k_resid_tile<RT_CAST>;
-        case RT_CAST_CORR: return (const void *)k_resid_tile<RT_CAST_CORR>;
-        case RT_RESTRICT32: return (const void *)k_resid_tile<RT_RESTRICT32>;
-        default: return (const void *)k_resid_tile<RT_NORM>;
+        case RT_RESTRICT:
+            return mob ? (const void *)k_resid_tile<RT_RESTRICT, true>
+                       : (const void *)k_resid_tile<RT_RESTRICT, false>;
+        case RT_CAST: return (const void *)k_resid_tile<RT_CAST, false>;
+        case RT_CAST_CORR: return (const void *)k_resid_tile<RT_CAST_CORR, false>;
+        case RT_RESTRICT32: return (const void *)k_resid_tile<RT_RESTRICT32, false>;
+        default:
+            return mob ? (const void *)k_resid_tile<RT_NORM, true>
+                       : (const void *)k_resid_tile<RT_NORM, false>;
     }
 }
 
-int resid_tile_slots(int device, int mode) {
+int resid_tile_slots(int device, int mode, bool mob) {
     int occ = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, resid_tile_fn(mode), kRT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, resid_tile_fn(mode, mob), kRT, 0) !=
             hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
@@ -275,21 +299,35 @@ int resid_tile_nz(int n, int slots, int mode) {
 int launch_resid_tile(hipStream_t s, int mode, const OpParams &op, int nz, const ResidTileArgs &a) {
     const int n = op.lay.n;
     const unsigned blocks = (unsigned)((n / kRX) * (n / kRY) * nz);
+    const bool mob = op.mob.phs != nullptr;  // FP64 modes only (the FP32 cycle has M = 1)
     switch (mode) {
         case RT_RESTRICT:
-            hipLaunchKernelGGL(k_resid_tile<RT_RESTRICT>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+            if (mob)
+                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, true>), dim3(blocks), dim3(kRT), 0, s,
+                                   op, nz, a);
+            else
+                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, false>), dim3(blocks), dim3(kRT), 0,
+                                   s, op, nz, a);
             break;
         case RT_CAST:
-            hipLaunchKernelGGL(k_resid_tile<RT_CAST>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+            hipLaunchKernelGGL((k_resid_tile<RT_CAST, false>), dim3(blocks), dim3(kRT), 0, s, op, nz,
+                               a);
             break;
         case RT_CAST_CORR:
-            hipLaunchKernelGGL(k_resid_tile<RT_CAST_CORR>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+            hipLaunchKernelGGL((k_resid_tile<RT_CAST_CORR, false>), dim3(blocks), dim3(kRT), 0, s, op,
+                               nz, a);
             break;
         case RT_RESTRICT32:
-            hipLaunchKernelGGL(k_resid_tile<RT_RESTRICT32>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+            hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT32, false>), dim3(blocks), dim3(kRT), 0, s,
+                               op, nz, a);
             break;
         default:
-            hipLaunchKernelGGL(k_resid_tile<RT_NORM>, dim3(blocks), dim3(kRT), 0, s, op, nz, a);
+            if (mob)
+                hipLaunchKernelGGL((k_resid_tile<RT_NORM, true>), dim3(blocks), dim3(kRT), 0, s, op,
+                                   nz, a);
+            else
+                hipLaunchKernelGGL((k_resid_tile<RT_NORM, false>), dim3(blocks), dim3(kRT), 0, s, op,
+                                   nz, a);
     }
     return (int)blocks;
 }

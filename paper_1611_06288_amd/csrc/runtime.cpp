@@ -394,9 +394,10 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
     H->nlev = (int)sizes.size();
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) device = 0;
-    const int slots = fused_slots(device);
+    const bool mob = cfg->mobility == PFC_MOBILITY_QUADRATIC;
+    const int slots = fused_slots(device, mob);
     int rt_slots[RT_MODES];
-    for (int m = 0; m < RT_MODES; ++m) rt_slots[m] = resid_tile_slots(device, m);
+    for (int m = 0; m < RT_MODES; ++m) rt_slots[m] = resid_tile_slots(device, m, mob);
     bool ok = true;
     for (int l = 0; l < H->nlev && ok; ++l) {
         Level &A = H->lev[l];
@@ -413,12 +414,9 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
         A.u = Tri<double>{u, u + A.P, u + 2 * A.P};
         A.f = Tri<double>{f, f + A.P, f + 2 * A.P};
         A.ubar = Tri<double>{ub, ub + A.P, ub + 2 * A.P};
-        // the column-tile residuals and the fused sweep are written for M = 1;
-        // variable mobility runs the pointwise kernels
-        const bool mob = cfg->mobility == PFC_MOBILITY_QUADRATIC;
-        A.rt = !mob && resid_tile_fits(A.lay);
+        A.rt = resid_tile_fits(A.lay);
         for (int m = 0; m < RT_MODES; ++m) A.rt_nz[m] = resid_tile_nz(A.n, rt_slots[m], m);
-        A.fused = !mob && l < H->nlev - 1 && fused_fits(A.n);
+        A.fused = l < H->nlev - 1 && fused_fits(A.n);
         if (A.fused || (l == 0 && A.rt)) {
             A.nz = fused_nz(A.n, slots);
             double *u2;

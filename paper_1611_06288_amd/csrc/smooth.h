@@ -42,13 +42,6 @@ __device__ __forceinline__ void point_solve(const OpParams &op, int picard, doub
     mu = r2 + c * phi - B * om;
 }
 
-// Mobility on the face between two cells: M of the average of their phi*.
-__device__ __forceinline__ double face_mob(const Mobility &mb, double pa, double pb) {
-    const double v = 0.5 * (pa + pb);
-    const double m = mb.m0 + mb.m1 * v + mb.m2 * v * v;
-    return m > mb.mmin ? m : mb.mmin;
-}
-
 // Pointwise solve with variable mobility: the first equation becomes
 // phi + A mu = r1 with A = tau msum / h^2 and r1 = f1 + tau smu / h^2, msum the
 // sum of the six face mobilities, smu the sum of M_face mu_nbr.

@@ -52,6 +52,9 @@ void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tr
 // for colour 0, new colour 0 for colour 1) and the same arithmetic, so, with
 // floating-point contraction off, the result is bitwise that of two
 // launch_smooth calls, while each field is read and written once.
+// MOB (variable mobility): phi* rides along as a fourth field of both rings
+// (read-only), and the mu-sum becomes the face-mobility sum of the flux form
+// in the half-sweep's neighbour order.
 constexpr int kFX = 64, kFY = 8, kFT = 256;  // column extents, threads per workgroup
 constexpr int kFSl = kFX / 2 + 1;            // colour-0 ring: points per row
 constexpr int kFRw = kFY + 2;                //                rows
@@ -61,15 +64,17 @@ constexpr int kFNr = kFSl * kFRw, kFNb = (kFX / 2) * kFY, kFNc = kFCs * kFCr;
 constexpr int kFIr = (kFNr + kFT - 1) / kFT, kFIb = (kFNb + kFT - 1) / kFT,
               kFIc = (kFNc + kFT - 1) / kFT;  // items per thread in each phase
 
-template <typename T, bool DELTA>
+template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(kFT) void k_sweep_fused(
     OpParams op, int picard, int nz, const T *__restrict__ ua, const T *__restrict__ ub,
     const T *__restrict__ uc, T *__restrict__ oa, T *__restrict__ ob, T *__restrict__ oc,
     const T *__restrict__ fa, const T *__restrict__ fb, const T *__restrict__ fc,
     const T *__restrict__ phk, const T *__restrict__ base) {
-    __shared__ T c1[3][3][kFCr][kFCs];   // [field][plane slot][row][point] old colour 1
-    __shared__ T red[3][3][kFRw][kFSl];  // [field][plane slot][row][point] new colour 0
+    constexpr int NF = MOB ? 4 : 3;         // ring fields: phi, mu, omega (, phi*)
+    __shared__ T c1[NF][3][kFCr][kFCs];   // [field][plane slot][row][point] old colour 1
+    __shared__ T red[NF][3][kFRw][kFSl];  // [field][plane slot][row][point] new colour 0
     if (gate_closed(op.gate)) return;
+    const double *__restrict__ ps = op.mob.phs;
     const int n = op.lay.n, hn = n >> 1;
     const unsigned un = (unsigned)n, uhn = (unsigned)hn, H = un * un * uhn;
     const int nbx = n / kFX, nby = n / kFY;
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
     auto rslot = [z0](int p) { return (p - z0 + 1) % 3; };  // colour-0 ring slot of plane p
 
     // old colour-1 values of one plane (box plus two-cell ring), in registers
-    T cn[kFIc][3];
+    T cn[kFIc][NF];
     auto load_c1 = [&](int p) {
         const unsigned pw = (unsigned)wn(p);
 #pragma unroll
@@ -98,6 +103,7 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                 cn[i][0] = ua[g];
                 cn[i][1] = ub[g];
                 cn[i][2] = uc[g];
+                if constexpr (MOB) cn[i][3] = ps[g];
             }
         }
     };
@@ -111,11 +117,12 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                 c1[0][s][cr][cs] = cn[i][0];
                 c1[1][s][cr][cs] = cn[i][1];
                 c1[2][s][cr][cs] = cn[i][2];
+                if constexpr (MOB) c1[3][s][cr][cs] = cn[i][3];
             }
         }
     };
     // own inputs of the colour-0 points of plane k (box plus ring)
-    T ro[kFIr][6];
+    T ro[kFIr][MOB ? 7 : 6];
     unsigned rg[kFIr];
     auto load_red = [&](int k) {
         const unsigned kw = (unsigned)wn(k);
@@ -134,12 +141,14 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                 ro[i][3] = fa[g];
                 ro[i][4] = fb[g];
                 ro[i][5] = fc[g];
+                if constexpr (MOB) ro[i][6] = ps[g];
             }
         }
     };
     // own inputs of the colour-1 points of plane kb (box); old phi comes from LDS
     T bo[kFIb][5];
     T bphi[kFIb];
+    T bphs[kFIb];  // MOB: phi* of this step's colour-1 points
     auto load_black = [&](int kb) {
 #pragma unroll
         for (int i = 0; i < kFIb; ++i) {
@@ -187,9 +196,29 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                              ((double)c1[fl][sk][r + 2][cx] + (double)c1[fl][sk][r][cx]) +
                              ((double)c1[fl][skp][r + 1][cx] + (double)c1[fl][skm][r + 1][cx]);
                 double phi, mu, om;
-                point_solve<DELTA>(op, picard, (double)ro[i][0], (double)ro[i][1],
-                                   (double)ro[i][2], (double)ro[i][3], (double)ro[i][4],
-                                   (double)ro[i][5], s3[1], s3[2], s3[0], phi, mu, om);
+                if constexpr (MOB) {
+                    const double pc = (double)ro[i][6];
+                    double msum = 0.0, smm = 0.0;
+                    auto face = [&](int sl3, int rr3, int cc3) {
+                        const double mf = face_mob(op.mob, pc, (double)c1[3][sl3][rr3][cc3]);
+                        msum += mf;
+                        smm += mf * (double)c1[1][sl3][rr3][cc3];
+                    };
+                    face(sk, r + 1, cxp);
+                    face(sk, r + 1, cxm);
+                    face(sk, r + 2, cx);
+                    face(sk, r, cx);
+                    face(skp, r + 1, cx);
+                    face(skm, r + 1, cx);
+                    point_solve_mob(op, picard, (double)ro[i][0], (double)ro[i][1],
+                                    (double)ro[i][3], (double)ro[i][4], (double)ro[i][5], msum,
+                                    smm, s3[2], s3[0], phi, mu, om);
+                    red[3][rq][r][sl] = ro[i][6];
+                } else {
+                    point_solve<DELTA>(op, picard, (double)ro[i][0], (double)ro[i][1],
+                                       (double)ro[i][2], (double)ro[i][3], (double)ro[i][4],
+                                       (double)ro[i][5], s3[1], s3[2], s3[0], phi, mu, om);
+                }
                 const T tphi = (T)phi, tmu = (T)mu, tom = (T)om;
                 red[0][rq][r][sl] = tphi;
                 red[1][rq][r][sl] = tmu;
@@ -211,6 +240,7 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                     const int rb = q / (kFX / 2), s = q - rb * (kFX / 2);
                     const int x = x0 + ((x0 + y0 + rb + kb + 1) & 1) + 2 * s;
                     bphi[i] = c1[0][sb][rb + 2][(x - x0 + 2) >> 1];
+                    if constexpr (MOB) bphs[i] = c1[3][sb][rb + 2][(x - x0 + 2) >> 1];
                 }
             }
         }
@@ -238,9 +268,28 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                                  ((double)red[fl][q0][rr + 1][s0] + (double)red[fl][q0][rr - 1][s0]) +
                                  ((double)red[fl][qp][rr][s0] + (double)red[fl][qm][rr][s0]);
                     double phi, mu, om;
-                    point_solve<DELTA>(op, picard, (double)bphi[i], (double)bo[i][0],
-                                       (double)bo[i][1], (double)bo[i][2], (double)bo[i][3],
-                                       (double)bo[i][4], s3[1], s3[2], s3[0], phi, mu, om);
+                    if constexpr (MOB) {
+                        const double pc = (double)bphs[i];
+                        double msum = 0.0, smm = 0.0;
+                        auto face = [&](int sl3, int rr3, int cc3) {
+                            const double mf = face_mob(op.mob, pc, (double)red[3][sl3][rr3][cc3]);
+                            msum += mf;
+                            smm += mf * (double)red[1][sl3][rr3][cc3];
+                        };
+                        face(q0, rr, sp);
+                        face(q0, rr, sm);
+                        face(q0, rr + 1, s0);
+                        face(q0, rr - 1, s0);
+                        face(qp, rr, s0);
+                        face(qm, rr, s0);
+                        point_solve_mob(op, picard, (double)bphi[i], (double)bo[i][0],
+                                        (double)bo[i][2], (double)bo[i][3], (double)bo[i][4],
+                                        msum, smm, s3[2], s3[0], phi, mu, om);
+                    } else {
+                        point_solve<DELTA>(op, picard, (double)bphi[i], (double)bo[i][0],
+                                           (double)bo[i][1], (double)bo[i][2], (double)bo[i][3],
+                                           (double)bo[i][4], s3[1], s3[2], s3[0], phi, mu, om);
+                    }
                     oa[g] = (T)phi;
                     ob[g] = (T)mu;
                     oc[g] = (T)om;
@@ -252,10 +301,11 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
 
 bool fused_fits(int n) { return n % kFX == 0 && n % kFY == 0 && n >= kFusedMinN; }
 
-int fused_slots(int device) {
+int fused_slots(int device, bool mob) {
     int occ = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (k_sweep_fused<double, false>), kFT, 0) !=
-            hipSuccess ||
+    const void *fn = mob ? (const void *)k_sweep_fused<double, false, true>
+                         : (const void *)k_sweep_fused<double, false, false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kFT, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
     return occ * cus;
@@ -277,8 +327,16 @@ void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, T
                         Tri<T> uout, Tri<const T> f, const T *phk, const T *base) {
     const int n = op.lay.n;
     const unsigned blocks = (unsigned)((n / kFX) * (n / kFY) * nz);
-    hipLaunchKernelGGL((k_sweep_fused<T, DELTA>), dim3(blocks), dim3(kFT), 0, s, op, picard, nz,
-                       uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b, f.c, phk, base);
+    if constexpr (!DELTA) {
+        if (op.mob.phs) {  // variable mobility
+            hipLaunchKernelGGL((k_sweep_fused<T, false, true>), dim3(blocks), dim3(kFT), 0, s, op,
+                               picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b,
+                               f.c, phk, base);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_sweep_fused<T, DELTA, false>), dim3(blocks), dim3(kFT), 0, s, op, picard,
+                       nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b, f.c, phk, base);
 }
 
 template void launch_smooth<double, false>(hipStream_t, const OpParams &, int, int, Tri<double>,

@@ -62,8 +62,12 @@ def rand_state(n, seed, mean=0.285):
 # --------------------------------------------------------- kernel level
 
 @pytest.mark.parametrize("n,level,mob", [(12, 0, MOB), (12, 1, MOB_LIN), (12, 2, MOB),
-                                         (48, 0, MOB_LIN), (48, 2, MOB), (96, 0, MOB)])
+                                         (48, 0, MOB_LIN), (48, 2, MOB), (96, 0, MOB),
+                                         (128, 0, MOB_LIN), (256, 0, MOB)])
 def test_residual_kernel(n, level, mob):
+    """Thread-per-point residual against the oracle; on levels with n % 64 == 0
+    the norm-only call runs the column-tile kernel with its phi* ring, which
+    must give the same maximum bit for bit."""
     s = make(n, mob)
     nl = s.levels[level]
     hl = s.L / nl
@@ -110,11 +114,13 @@ def test_smoother_half_sweeps(n, level, lin, mob):
         assert rel(host(ud), ref) < KERNEL_RTOL
 
 
-def test_full_sweep_is_two_half_sweeps_at_128():
-    """With variable mobility the full sweep runs colour by colour at every size."""
+@pytest.mark.parametrize("n,lin", [(128, "newton"), (128, "picard"), (256, "newton")])
+def test_fused_sweep_equals_two_half_sweeps(n, lin):
+    """Levels of >= 128^3 with n % 64 == 0 run the fused one-pass sweep with the
+    phi* ring; it must equal two half-sweeps bit for bit, and the oracle."""
     from paper_1611_06288_amd._lib import PFC_SWEEP_FULL
-    s = make(128, MOB)
-    phk, u, f, phs = rand_state(128, 1400)
+    s = make(n, MOB, lin=lin)
+    phk, u, f, phs = rand_state(n, 1400 + n)
     s.set_phistar(0, dev(phs))
     fd, pd = dev(f), dev(phk)
     full, halves = dev(u), dev(u)
@@ -125,7 +131,8 @@ def test_full_sweep_is_two_half_sweeps_at_128():
     assert torch.equal(full, halves)
     ref = u
     for colour in (0, 1):
-        ref = cfas.smooth_half_m(ref, f, phk, phs, s.h, s.eps, s.dt, colour, MOB)
+        ref = cfas.smooth_half_m(ref, f, phk, phs, s.h, s.eps, s.dt, colour, MOB,
+                                 picard=(lin == "picard"))
     assert rel(host(full), ref) < KERNEL_RTOL
 
 
