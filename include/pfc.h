@@ -219,7 +219,7 @@ pfc_status pfc_source(pfc_handle *h, const double *phi_prev, const double *phi_c
  * (phk = phi^k on that level).  r3 may be NULL; maxnorm (host, nullable)
  * receives max|r| over the three components.  Synchronises if maxnorm.
  * With r3 NULL on a colour-split level with n a multiple of 64 the norm comes
- * from the column-tile kernel of the stop test (M = 1 only); it equals the
+ * from the column-tile kernel of the stop test; it equals the
  * thread-per-point kernel's bit for bit. */
 pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const double *f3,
                         const double *phk, double *r3, double *maxnorm);
@@ -228,8 +228,7 @@ pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const do
  * colour `colour` ((i+j+k) mod 2) at level l, in place on u3; with colour =
  * PFC_SWEEP_FULL, one full sweep (colour 0, then colour 1), the form the
  * cycles use: on levels of at least 128^3 with n a multiple of 64 it runs as
- * a single fused pass whose result equals the two half-sweeps bit for bit
- * (M = 1 only; variable mobility sweeps colour by colour). */
+ * a single fused pass whose result equals the two half-sweeps bit for bit. */
 #define PFC_SWEEP_FULL 2
 pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3,
                       const double *f3, const double *phk);

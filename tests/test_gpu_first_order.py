@@ -90,7 +90,8 @@ def test_smoother_half_sweeps(n, level, lin):
         assert rel(host(ud), ref) < KERNEL_RTOL
 
 
-@pytest.mark.parametrize("n,lin", [(128, "newton"), (128, "picard"), (256, "newton")])
+@pytest.mark.parametrize("n,lin", [(16, "newton"), (32, "picard"), (128, "newton"),
+                                   (128, "picard"), (256, "newton")])
 def test_fused_sweep(n, lin):
     from paper_1611_06288_amd._lib import PFC_SWEEP_FULL
     s = make(n, lin=lin)

@@ -110,10 +110,14 @@ def test_smoother_half_sweeps(n, level, lin):
 
 # Full sweeps: levels of >= 128^3 with n % 64 == 0 run the fused one-pass
 # sweep (n = 128 and 256 cut each column into uneven plane ranges, n = 192
-# into even ones); n = 96 runs two half-sweeps.  The fused pass must equal
-# the GPU's own two half-sweeps bitwise and the oracle's within rounding.
-@pytest.mark.parametrize("n,lin", [(96, "newton"), (128, "newton"), (128, "picard"),
-                                   (192, "newton"), (256, "newton")])
+# into even ones); smaller levels run two half-sweeps (a fused pass there is
+# latency-bound: 11-15 us against 3-5 us per half-sweep).  The full sweep
+# must equal the GPU's own two half-sweeps bitwise and the oracle's within
+# rounding.
+@pytest.mark.parametrize("n,lin", [(8, "newton"), (12, "newton"), (16, "picard"), (24, "newton"),
+                                   (32, "newton"), (48, "newton"), (64, "picard"), (96, "newton"),
+                                   (128, "newton"), (128, "picard"), (192, "newton"),
+                                   (256, "newton")])
 def test_full_sweep_fused(n, lin):
     from paper_1611_06288_amd._lib import PFC_SWEEP_FULL
     s = make(n, lin=lin)

@@ -114,10 +114,12 @@ def test_smoother_half_sweeps(n, level, lin, mob):
         assert rel(host(ud), ref) < KERNEL_RTOL
 
 
-@pytest.mark.parametrize("n,lin", [(128, "newton"), (128, "picard"), (256, "newton")])
+@pytest.mark.parametrize("n,lin", [(16, "newton"), (48, "picard"), (128, "newton"),
+                                   (128, "picard"), (256, "newton")])
 def test_fused_sweep_equals_two_half_sweeps(n, lin):
     """Levels of >= 128^3 with n % 64 == 0 run the fused one-pass sweep with the
-    phi* ring; it must equal two half-sweeps bit for bit, and the oracle."""
+    phi* ring (smaller ones two half-sweeps); the full sweep must equal two
+    half-sweeps bit for bit, and the oracle."""
     from paper_1611_06288_amd._lib import PFC_SWEEP_FULL
     s = make(n, MOB, lin=lin)
     phk, u, f, phs = rand_state(n, 1400 + n)
