@@ -10,7 +10,8 @@
 // b = phi of the current FP64 iterate rounded to FP32 (restricted to the
 // coarse levels), written without cancellation.  Then u += e in FP64 (on
 // levels with column tiles, inside the next defect pass).  While the residual
-// is far above tol up to three FP32 cycles run per defect.  The smoother's pointwise
+// is far above tol up to twelve FP32 cycles run per defect (one cycle is
+// recorded as a hipGraph and replayed).  The smoother's pointwise
 // 3x3 solve, the residual and all reductions run in FP64 arithmetic; only
 // stored fields of the correction cycle are FP32.
 #include <cmath>
@@ -87,8 +88,42 @@ static void cycle32(pfc_handle *H, int l, bool fcycle) {
     for (int s = 0; s < H->cfg.nu2; ++s) sweep32(H, l);
 }
 
+// One FP32 cycle recorded as a graph on the handle's own stream (its
+// buffers never move), replayed once per inner cycle: the cycle's ~60
+// launches, mostly on small levels, go out together.  Kernel timing is not
+// recorded inside it.
+static pfc_status record_cycle32(pfc_handle *H) {
+    const bool timing = H->timing;
+    H->timing = false;
+    hipError_t e = hipStreamBeginCapture(H->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        cycle32(H, 0, H->cfg.cycle == PFC_CYCLE_F);
+        e = hipStreamEndCapture(H->stream, &H->mix_graph);
+    }
+    H->timing = timing;
+    if (e == hipSuccess) e = hipGraphInstantiate(&H->mix_exec, H->mix_graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(H, e, "recording the FP32 cycle");
+    return PFC_OK;
+}
+
+static pfc_status mixed_step_on(pfc_handle *H, const double *phi_prev, const double *phi_cur,
+                                double *phi_next, double *mu, double *omega,
+                                pfc_step_info *info);
+
 pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_cur,
                       double *phi_next, double *mu, double *omega, pfc_step_info *info) {
+    hipStream_t user;
+    pfc_status st = own_stream_enter(H, &user);
+    if (st != PFC_OK) return st;
+    st = mixed_step_on(H, phi_prev, phi_cur, phi_next, mu, omega, info);
+    const pfc_status st2 = own_stream_leave(H, user);
+    return st != PFC_OK ? st : st2;
+}
+
+// The step on the handle's own stream.
+static pfc_status mixed_step_on(pfc_handle *H, const double *phi_prev, const double *phi_cur,
+                                double *phi_next, double *mu, double *omega,
+                                pfc_step_info *info) {
     Level &A = H->lev[0];
     Level32 &A32 = H->lev32[0];
     step_begin(H, phi_prev, phi_cur, mu, omega);
@@ -160,7 +195,12 @@ pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_c
             launch_restrict<float>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev32[l].base,
                                    H->lev32[l + 1].base);
         launch_zero(H->stream, A32.e.a, 3 * A.P);
-        for (int i = 0; i < inner; ++i) cycle32(H, 0, H->cfg.cycle == PFC_CYCLE_F);
+        HIP_TRY(H, hipGetLastError());
+        if (!H->mix_exec) {
+            const pfc_status st2 = record_cycle32(H);
+            if (st2 != PFC_OK) return st2;
+        }
+        for (int i = 0; i < inner; ++i) HIP_TRY(H, hipGraphLaunch(H->mix_exec, H->stream));
         pending = true;
         c += inner;
         rho_prev = rho;

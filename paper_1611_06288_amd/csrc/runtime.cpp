@@ -198,6 +198,8 @@ pfc_handle::~pfc_handle() {
     }
     for (auto e : pool) (void)hipEventDestroy(e);
     if (run_stream) (void)hipStreamSynchronize(run_stream);
+    if (mix_exec) (void)hipGraphExecDestroy(mix_exec);
+    if (mix_graph) (void)hipGraphDestroy(mix_graph);
     if (run_exec) (void)hipGraphExecDestroy(run_exec);
     if (run_graph) (void)hipGraphDestroy(run_graph);
     if (run_ev) (void)hipEventDestroy(run_ev);

@@ -83,6 +83,8 @@ struct pfc_handle {
     const void *run_key[pfc::kMaxLevels] = {};  // level iterates the graph was recorded with
     double *spare = nullptr;              // third phi buffer of the loop
     int last_cycles = 0;                  // cycles of the previous step (launch count guess)
+    hipGraph_t mix_graph = nullptr;       // one FP32 correction cycle (mixed form)
+    hipGraphExec_t mix_exec = nullptr;
     std::string err;
     // instrumentation
     bool timing = false;
@@ -108,6 +110,12 @@ pfc_status read_norm(pfc_handle *H, int partials, double *out);
 pfc_status mixed_init(pfc_handle *H);
 pfc_status step64(pfc_handle *h, const double *phi_prev, const double *phi_cur, double *phi_next,
                   double *mu, double *omega, pfc_step_info *info);
+// The handle's own non-blocking stream (created on first use): recorded
+// graphs need a capturable stream.  own_stream_enter makes it follow the
+// caller's stream and returns that stream; own_stream_leave makes the caller's
+// stream follow it again.
+pfc_status own_stream_enter(pfc_handle *H, hipStream_t *user);
+pfc_status own_stream_leave(pfc_handle *H, hipStream_t user);
 pfc_status mixed_step(pfc_handle *H, const double *phi_prev, const double *phi_cur,
                       double *phi_next, double *mu, double *omega, pfc_step_info *info);
 double algorithmic_bytes(const pfc_handle *H, int kernel);

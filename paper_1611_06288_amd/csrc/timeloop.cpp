@@ -121,6 +121,30 @@ pfc_status graph_step(pfc_handle *H, const double *prev, const double *cur, doub
 
 }  // namespace
 
+namespace pfc {
+pfc_status own_stream_enter(pfc_handle *H, hipStream_t *user) {
+    if (!H->run_stream) {
+        HIP_TRY(H, hipStreamCreateWithFlags(&H->run_stream, hipStreamNonBlocking));
+        HIP_TRY(H, hipEventCreateWithFlags(&H->run_ev, hipEventDisableTiming));
+    }
+    *user = H->stream;
+    if (H->stream == H->run_stream) return PFC_OK;  // already on it
+    HIP_TRY(H, hipEventRecord(H->run_ev, H->stream));
+    HIP_TRY(H, hipStreamWaitEvent(H->run_stream, H->run_ev, 0));
+    H->stream = H->run_stream;
+    return PFC_OK;
+}
+
+pfc_status own_stream_leave(pfc_handle *H, hipStream_t user) {
+    if (user == H->run_stream) return PFC_OK;
+    hipError_t e = hipEventRecord(H->run_ev, H->run_stream);
+    H->stream = user;
+    if (e == hipSuccess) e = hipStreamWaitEvent(user, H->run_ev, 0);
+    if (e != hipSuccess) return hip_fail(H, e, "own stream: hand-back");
+    return PFC_OK;
+}
+}  // namespace pfc
+
 extern "C" pfc_status pfc_run(pfc_handle *h, double *phi_prev, double *phi_cur, double *mu,
                               double *omega, int32_t steps, pfc_step_info *infos) {
     if (!h) return PFC_ERR_INVALID_ARG;
@@ -133,15 +157,12 @@ extern "C" pfc_status pfc_run(pfc_handle *h, double *phi_prev, double *phi_cur, 
             !dalloc(h, &h->d_runres, 2))
             return fail(h, PFC_ERR_OOM, "time-loop buffers");
     }
-    if (!h->run_stream) {
-        HIP_TRY(h, hipStreamCreateWithFlags(&h->run_stream, hipStreamNonBlocking));
-        HIP_TRY(h, hipEventCreateWithFlags(&h->run_ev, hipEventDisableTiming));
-    }
     // the loop's stream follows the caller's, and the caller's follows it at the end
-    const hipStream_t user = h->stream;
-    HIP_TRY(h, hipEventRecord(h->run_ev, user));
-    HIP_TRY(h, hipStreamWaitEvent(h->run_stream, h->run_ev, 0));
-    h->stream = h->run_stream;
+    hipStream_t user;
+    {
+        const pfc_status st = own_stream_enter(h, &user);
+        if (st != PFC_OK) return st;
+    }
     const bool graph = graph_usable(h);
     double *buf[3] = {phi_prev, phi_cur, h->spare};
     int ip = 0, ic = 1, in = 2;
@@ -179,9 +200,10 @@ extern "C" pfc_status pfc_run(pfc_handle *h, double *phi_prev, double *phi_cur, 
         e = hipMemcpyAsync(phi_cur, phi_prev, bytes, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(phi_prev, h->spare, bytes, hipMemcpyDeviceToDevice, h->stream);
     }
-    if (e == hipSuccess) e = hipEventRecord(h->run_ev, h->stream);
-    h->stream = user;
-    if (e == hipSuccess) e = hipStreamWaitEvent(user, h->run_ev, 0);
-    if (e != hipSuccess) return hip_fail(h, e, "time loop: final copies");
-    return status;
+    if (e != hipSuccess) {
+        (void)own_stream_leave(h, user);
+        return hip_fail(h, e, "time loop: final copies");
+    }
+    const pfc_status st = own_stream_leave(h, user);
+    return st != PFC_OK ? st : status;
 }

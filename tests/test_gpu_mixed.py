@@ -65,3 +65,35 @@ def test_mixed_constant_state():
     mu, om = s.init_guess(phi)
     out, info = s.step(phi, phi, mu, om)
     assert info.cycles == 0 and torch.equal(out, phi)
+
+
+def test_mixed_cycle_graph_replays_are_consistent():
+    """The FP32 correction cycle is recorded once as a hipGraph and replayed
+    for every inner cycle.  Replays separated by the handle's own eager work
+    (defect passes, and here kernel-level calls and energies between steps)
+    must give the same fields, bit for bit, as an undisturbed run on a fresh
+    handle, on a level with column tiles (n = 128) and without (n = 48)."""
+    from paper_1611_06288_amd import Solver
+    for n in (48, 128):
+        L = n * math.pi / 4
+        phi0 = dev(inputs.polycrystal_phi0(n, L, 2, seed=950 + n, radius_cells=4))
+        outs = []
+        for disturb in (False, True):
+            s = Solver(n, L, 0.25, 0.5, tol=1e-10, precision="mixed")
+            mu, om = s.init_guess(phi0)
+            prev, cur = phi0.clone(), phi0.clone()
+            spare = torch.empty_like(cur)
+            cycles = []
+            for k in range(3):
+                nxt, info = s.step(prev, cur, mu, om, out=spare)
+                cycles.append(info.cycles)
+                spare, prev, cur = prev, cur, nxt
+                if disturb:
+                    s.energy(cur, prev)
+                    u3 = torch.stack([cur, mu, om]).contiguous()
+                    s.residual(0, u3, s.source(prev, cur), cur, want_r=False)
+            torch.cuda.synchronize()
+            outs.append((cur.clone(), mu.clone(), om.clone(), cycles))
+        assert outs[0][3] == outs[1][3]
+        for a, b in zip(outs[0][:3], outs[1][:3]):
+            assert torch.equal(a, b)
