@@ -218,9 +218,9 @@ pfc_status pfc_source(pfc_handle *h, const double *phi_prev, const double *phi_c
  * flux form with the handle's variable mobility)
  * (phk = phi^k on that level).  r3 may be NULL; maxnorm (host, nullable)
  * receives max|r| over the three components.  Synchronises if maxnorm.
- * With r3 NULL on a colour-split level with n a multiple of 64 the norm comes
- * from the column-tile kernel of the stop test; it equals the
- * thread-per-point kernel's bit for bit. */
+ * With r3 NULL on a colour-split level with n a multiple of 64 and at least
+ * 128 the norm comes from the column-tile kernel of the stop test; it equals
+ * the thread-per-point kernel's bit for bit. */
 pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const double *f3,
                         const double *phk, double *r3, double *maxnorm);
 

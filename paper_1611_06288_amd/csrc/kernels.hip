@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <numeric>
+#include <type_traits>
 
 namespace pfc {
 
@@ -227,6 +228,10 @@ __device__ __forceinline__ void resid_restrict_body(const OpParams &op, const La
     ubar_c.c[t] = (T)(0.125 * uc);
 }
 
+// The per-level launch: eight threads per coarse cell, one per child (child
+// ch = lane & 7 in the order of resid_restrict_body), so each thread waits on
+// one child's loads rather than eight in turn; the group's first lane then
+// adds the eight children's values in that order, as the body does.
 template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict(OpParams op, Lay LC, Tri<const T> u,
                                                            Tri<const T> f,
@@ -234,22 +239,50 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(OpParams op, Lay LC, 
                                                            const T *__restrict__ base,
                                                            Tri<T> ubar_c, Tri<T> rr_c) {
     if (gate_closed(op.gate)) return;
-    resid_restrict_body<T, DELTA, MOB>(op, LC, u, f, phk, base, ubar_c, rr_c,
-                                       xcd_block() * kBlock + threadIdx.x);
+    const unsigned g = xcd_block() * kBlock + threadIdx.x;
+    const unsigned tn = g >> 3;
+    const int ch = (int)(g & 7u);
+    const bool act = tn < (unsigned)npts(LC);
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // r1, r2, r3, u.a, u.b, u.c of the child
+    unsigned t = 0;
+    if (act) {
+        int I, J, K;
+        decode_nat(LC, tn, I, J, K);
+        t = sidx32(LC, I, J, K);
+        const Off q = offs(op.lay, 2 * I + (ch & 1), 2 * J + ((ch >> 1) & 1), 2 * K + (ch >> 2));
+        resid_at<T, DELTA, MOB>(op, u, f, phk, base, q, v[0], v[1], v[2]);
+        v[3] = (double)u.a[q.c];
+        v[4] = (double)u.b[q.c];
+        v[5] = (double)u.c[q.c];
+    }
+    double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int e = 0; e < 6; ++e) s[e] += __shfl(v[e], c, 8);
+    if (act && ch == 0) {
+        rr_c.a[t] = (T)(0.125 * s[0]);
+        rr_c.b[t] = (T)(0.125 * s[1]);
+        rr_c.c[t] = (T)(0.125 * s[2]);
+        ubar_c.a[t] = (T)(0.125 * s[3]);
+        ubar_c.b[t] = (T)(0.125 * s[4]);
+        ubar_c.c[t] = (T)(0.125 * s[5]);
+    }
 }
 
 template <typename T, bool DELTA>
 void launch_resid_restrict(hipStream_t s, const OpParams &op, const Lay &coarse, Tri<const T> u,
                            Tri<const T> f, const T *phk, const T *base, Tri<T> ubar_c, Tri<T> rr_c) {
+    const unsigned blocks = blocks_for(8 * npts_host(coarse));
     if constexpr (!DELTA) {
         if (op.mob.phs) {
-            hipLaunchKernelGGL((k_resid_restrict<T, false, true>), dim3(blocks_for(npts_host(coarse))),
-                               dim3(kBlock), 0, s, op, coarse, u, f, phk, base, ubar_c, rr_c);
+            hipLaunchKernelGGL((k_resid_restrict<T, false, true>), dim3(blocks), dim3(kBlock), 0, s,
+                               op, coarse, u, f, phk, base, ubar_c, rr_c);
             return;
         }
     }
-    hipLaunchKernelGGL((k_resid_restrict<T, DELTA, false>), dim3(blocks_for(npts_host(coarse))),
-                       dim3(kBlock), 0, s, op, coarse, u, f, phk, base, ubar_c, rr_c);
+    hipLaunchKernelGGL((k_resid_restrict<T, DELTA, false>), dim3(blocks), dim3(kBlock), 0, s, op,
+                       coarse, u, f, phk, base, ubar_c, rr_c);
 }
 
 template <typename T>
@@ -369,12 +402,8 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
 #pragma unroll
             for (int x = 0; x < 3; ++x) o[z][y][x] = sidx32(LC, Ix[x], y ? J1 : J0, z ? K1 : K0);
     const unsigned f0 = sidx32(LF, 2 * I, j, k), f1 = sidx32(LF, 2 * I + 1, j, k);
-    const int ncomp = fine.b ? 3 : 1;
-#pragma unroll 1
-    for (int comp = 0; comp < ncomp; ++comp) {
-        const T *vv = comp == 0 ? v.a : (comp == 1 ? v.b : v.c);
-        const T *uu = comp == 0 ? ubar.a : (comp == 1 ? ubar.b : ubar.c);
-        T *ff = comp == 0 ? fine.a : (comp == 1 ? fine.b : fine.c);
+    // one component; all three are issued together when there are three
+    auto comp_add = [&](const T *vv, const T *uu, T *ff) {
         double w[3];  // y/z-interpolated values at x = I-1, I, I+1
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
@@ -388,6 +417,11 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
         }
         ff[f0] = (T)((double)ff[f0] + (0.75 * w[1] + 0.25 * w[0]));
         ff[f1] = (T)((double)ff[f1] + (0.75 * w[1] + 0.25 * w[2]));
+    };
+    comp_add(v.a, ubar.a, fine.a);
+    if (fine.b) {
+        comp_add(v.b, ubar.b, fine.b);
+        comp_add(v.c, ubar.c, fine.c);
     }
 }
 
@@ -480,13 +514,21 @@ template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
                     Tri<const T> ubar, Tri<T> fine_u, const int *gate) {
     const size_t pairs = (size_t)coarse.n * fine.n * fine.n;
+    const bool tile = fine.split && fine.n % kPX == 0 && fine.n % kPY == 0;
+    if (std::is_same<T, double>::value && ubar.a && fine_u.b && !tile) {
+        // small FP64 levels: one launch that forms v - ubar where it reads it
+        // (the same value the separate coarse-error pass would store)
+        hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine,
+                           v, ubar, fine_u, gate);
+        return;
+    }
     if (ubar.a && fine_u.b) {
         // e = v - ubar once on the coarse level (in place of ubar), so the
         // fine-level pass loads one coarse array instead of two
         Tri<T> e{const_cast<T *>(ubar.a), const_cast<T *>(ubar.b), const_cast<T *>(ubar.c)};
         hipLaunchKernelGGL((k_coarse_err<T>), dim3(blocks_for(npts_host(coarse))), dim3(kBlock), 0, s,
                            npts_host(coarse), v, e, gate);
-        if (fine.split && fine.n % kPX == 0 && fine.n % kPY == 0) {
+        if (tile) {
             const unsigned blocks = (unsigned)((fine.n / kPX) * (fine.n / kPY) * coarse.n);
             hipLaunchKernelGGL((k_prolong_tile<T>), dim3(blocks), dim3(kBlock), 0, s, coarse, fine,
                                cst(e), fine_u, gate);

@@ -111,6 +111,10 @@ struct ResidTileArgs {
     unsigned long long *partial = nullptr;  // RT_NORM, RT_CAST*: per-workgroup max |r|
 };
 bool resid_tile_fits(const Lay &L);
+// The stop-test norm takes the column tiles from this size on; on a 64^3
+// level each column holds a few planes and the thread-per-point norm is
+// faster (7 against 11 us), while the restriction keeps the tiles there.
+constexpr int kTileNormMinN = 128;
 int resid_tile_slots(int device, int mode, bool mob = false);   // resident workgroups (0 on error)
 int resid_tile_nz(int n, int slots, int mode);
 int launch_resid_tile(hipStream_t s, int mode, const OpParams &op, int nz,

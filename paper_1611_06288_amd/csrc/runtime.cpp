@@ -300,7 +300,7 @@ static int enqueue_norm(pfc_handle *H, Tri<double> r) {
     Level &A = H->lev[0];
     H->begin_timed(PFC_KERNEL_NORM0, 0);
     int cnt;
-    if (A.rt && !r.a) {
+    if (A.rt && A.n >= kTileNormMinN && !r.a) {
         ResidTileArgs ra;
         ra.u = cst(A.u);
         ra.f = cst(A.f);
@@ -625,7 +625,7 @@ pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const do
     Tri<double> r{nullptr, nullptr, nullptr};
     if (r3) r = A.ubar;
     int cnt;
-    if (!r3 && A.rt) {  // norm only: the column-tile kernel the cycles use
+    if (!r3 && A.rt && A.n >= kTileNormMinN) {  // norm only: the kernel the cycles use
         ResidTileArgs ra;
         ra.u = cst(A.u);
         ra.f = cst(A.f);
