@@ -234,8 +234,23 @@ __device__ __forceinline__ void gj_invert(double *A, int P, int *perm) {
         if (act) A[p * P + c] = (p == c ? 1.0 : A[p * P + c]) * pinv;  // scale pivot row
         __syncthreads();
         if (act && p != c) {
+            // full chunks of 16 columns take all their loads before their
+            // stores (the pivot row is not written in this phase), so the LDS
+            // latency is paid once per chunk; the rest goes one by one
             const double fr = A[c * P + p];
-            for (int q = 0; q < P; ++q) {
+            int q0 = 0;
+            for (; q0 + 16 <= P; q0 += 16) {
+                double own[16], piv[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    own[i] = A[(q0 + i) * P + p];
+                    piv[i] = A[(q0 + i) * P + c];
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    A[(q0 + i) * P + p] = ((q0 + i == c) ? 0.0 : own[i]) - fr * piv[i];
+            }
+            for (int q = q0; q < P; ++q) {
                 const double old = (q == c) ? 0.0 : A[q * P + p];
                 A[q * P + p] = old - fr * A[q * P + c];
             }

@@ -633,22 +633,39 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
     auto rebuild = [&]() {
         dvec[p] = dg_of<DELTA>(op.fo, x, a, bs) + lc;
         __syncthreads();
-        if (act)
-            for (int q = 0; q < P; ++q) {
-                const int o = q * P + p;
-                if constexpr (MOB) {
+        if (act && !MOB) {
+            // row p of F'(x); the dense Lap and Lap^3 come from global memory,
+            // so their loads are issued 16 at a time ahead of the stores
+            for (int q0 = 0; q0 < P; q0 += 16) {
+                double l1v[16], l3v[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int q = q0 + i;
+                    l1v[i] = q < P ? lap1[q * P + p] : 0.0;
+                    l3v[i] = q < P ? lap3[q * P + p] : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int q = q0 + i;
+                    if (q < P)
+                        A[q * P + p] =
+                            (q == p ? 1.0 : 0.0) - tau * l1v[i] * dvec[q] - w3 * tau * l3v[i];
+                }
+            }
+        }
+        if constexpr (MOB) {
+            if (act)
+                for (int q = 0; q < P; ++q) {
                     // row p of L_M and of L_M Lap^2 (lap2 column-major: [col * P + row])
                     double lm = q == p ? -msum : 0.0, lmd2 = -msum * lap2[q * P + p];
                     for (int e = 0; e < 6; ++e) {
                         if (nb[e] == q) lm += mf[e];
                         lmd2 += mf[e] * lap2[q * P + nb[e]];
                     }
-                    A[o] = (q == p ? 1.0 : 0.0) - tau * (lm * h2inv) * dvec[q] -
-                           0.5 * tau * (lmd2 * h2inv);
-                } else {
-                    A[o] = (q == p ? 1.0 : 0.0) - tau * lap1[o] * dvec[q] - w3 * tau * lap3[o];
+                    A[q * P + p] = (q == p ? 1.0 : 0.0) - tau * (lm * h2inv) * dvec[q] -
+                                   0.5 * tau * (lmd2 * h2inv);
                 }
-            }
+        }
         __syncthreads();
         gj_invert(A, P, perm);
         if (act)
