@@ -44,6 +44,10 @@ pfc_status mixed_init(pfc_handle *H) {
 static void sweep32(pfc_handle *H, int l) {
     Level32 &A = H->lev32[l];
     const OpParams op = op_of(H, l);
+    if (H->lev[l].n <= kSmallSweepN) {  // both colours in one workgroup
+        launch_sweep_small<float, true>(H->stream, op, 0, A.e, cst(A.f), A.phk, A.base);
+        return;
+    }
     for (int colour = 0; colour < 2; ++colour) {
         H->begin_timed(PFC_KERNEL_SMOOTH0, l);
         launch_smooth<float, true>(H->stream, op, colour, 0, A.e, cst(A.f), A.phk, A.base);

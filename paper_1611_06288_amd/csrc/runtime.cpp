@@ -223,6 +223,13 @@ static void sweep64(pfc_handle *H, int l) {
         std::swap(A.u, A.u2);
         return;
     }
+    if (A.n <= kSmallSweepN) {  // both colours in one workgroup
+        H->begin_timed(PFC_KERNEL_SMOOTH0, l);
+        launch_sweep_small<double, false>(H->stream, op, H->cfg.lin == PFC_LIN_PICARD, A.u,
+                                          cst(A.f), A.phk, nullptr);
+        H->end_timed();
+        return;
+    }
     for (int colour = 0; colour < 2; ++colour) {
         H->begin_timed(PFC_KERNEL_SMOOTH0, l);
         launch_smooth<double, false>(H->stream, op, colour, H->cfg.lin == PFC_LIN_PICARD, A.u,

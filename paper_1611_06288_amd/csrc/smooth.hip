@@ -32,6 +32,50 @@ void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tr
                        colour, picard, u, f, phk, base);
 }
 
+// ------------------------------------------------ small-level full sweep
+//
+// Levels of at most kSmallSweepN^3 points: one workgroup runs both colours,
+// the barrier between them standing in for a second launch (the launches of
+// such levels cost more than their work).  Same per-point body and order as
+// two launch_smooth calls, so the result is the same bit for bit.
+constexpr int kSmallSweepThreads = 1024;
+
+template <typename T, bool DELTA, bool MOB>
+__global__ __launch_bounds__(kSmallSweepThreads) void k_sweep_small(OpParams op, int picard, Tri<T> u,
+                                                                    Tri<const T> f,
+                                                                    const T *__restrict__ phk,
+                                                                    const T *__restrict__ base) {
+    if (gate_closed(op.gate)) return;
+    const unsigned H = (unsigned)(npts(op.lay) / 2);
+    for (int colour = 0; colour < 2; ++colour) {
+        for (unsigned t = threadIdx.x; t < H; t += blockDim.x)
+            smooth_body<T, DELTA, MOB>(op, colour, picard, u, f, phk, base, t);
+        __syncthreads();
+    }
+}
+
+template <typename T, bool DELTA>
+void launch_sweep_small(hipStream_t s, const OpParams &op, int picard, Tri<T> u, Tri<const T> f,
+                        const T *phk, const T *base) {
+    const size_t H = npts_host(op.lay) / 2;
+    const unsigned threads =
+        (unsigned)std::min<size_t>(kSmallSweepThreads, (H + 63) / 64 * 64);
+    if constexpr (!DELTA) {
+        if (op.mob.phs) {
+            hipLaunchKernelGGL((k_sweep_small<T, false, true>), dim3(1), dim3(threads), 0, s, op,
+                               picard, u, f, phk, base);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_sweep_small<T, DELTA, false>), dim3(1), dim3(threads), 0, s, op, picard, u,
+                       f, phk, base);
+}
+
+template void launch_sweep_small<double, false>(hipStream_t, const OpParams &, int, Tri<double>,
+                                                Tri<const double>, const double *, const double *);
+template void launch_sweep_small<float, true>(hipStream_t, const OpParams &, int, Tri<float>,
+                                              Tri<const float>, const float *, const float *);
+
 // ------------------------------------------------- fused red-black sweep
 //
 // One full red-black sweep in one pass, from u_in to u_out (two buffers;
