@@ -178,3 +178,25 @@ def test_long_polycrystal_growth_section_6_2():
     kpeak = np.argmax(power[1:]) * dk + dk
     print("spectrum peak at |k| =", kpeak)
     assert 0.85 <= kpeak <= 1.15
+
+
+def test_run_reports_nonfinite():
+    """A NaN in the state makes the device stop test report NONFINITE after
+    the first norm, as the step loop does, and the loop stops there."""
+    from paper_1611_06288_amd import Solver
+    from paper_1611_06288_amd.solver import PFCError
+    n = 16
+    s = Solver(n, n * math.pi / 4, 0.25, 0.5)
+    phi0, mu0, om0 = start(s, n, 2500)
+    bad = phi0.clone()
+    bad[3, 4, 5] = float("nan")
+    prev, cur, mu, om = bad.clone(), bad.clone(), mu0.clone(), om0.clone()
+    infos = s.run(prev, cur, mu, om, 3, raise_on_error=False)
+    assert infos[0].status == 3 and infos[0].cycles == 0
+    assert infos[1].status == 0 and infos[1].cycles == 0  # not run
+    with pytest.raises(PFCError) as e:
+        s.run(bad.clone(), bad.clone(), mu0.clone(), om0.clone(), 1)
+    assert e.value.status == 3
+    # the handle is still usable afterwards
+    prev, cur, mu, om = phi0.clone(), phi0.clone(), mu0.clone(), om0.clone()
+    assert all(i.status == 0 for i in s.run(prev, cur, mu, om, 2))
