@@ -116,3 +116,36 @@ def test_mass_conserved_and_modified_energy_decays():
     phs = 1.5 * phis[-1] - 0.5 * phis[-2]
     M = D.mobility(phs, MOB)
     assert M.max() - M.min() > 0.1
+
+
+@pytest.mark.parametrize("mob", [MOB, MOB_LIN])
+def test_flux_operator_with_the_floor_reached(mob):
+    """phi* spread so that a good share of the faces sit on the floor mmin of
+    M: the flux operator still equals the independently assembled matrix."""
+    n, h, eps, tau = 6, 0.8, 0.2, 0.3
+    phkm1, phk, u = rand_fields(n, 16)
+    phs = inputs.rng(17).uniform(-1.3, 1.3, (n, n, n))
+    A = [D.face_average_matrix(n, ax) @ phs.ravel() for ax in range(3)]
+    floor = sum(int(np.sum(D.mobility(a, mob) == mob[3])) for a in A)
+    assert floor > 10, floor
+    got = cfas.apply_N_m(u, phk, phs, h, eps, tau, mob)
+    want = D.apply_N_mob(u, phk, phs, h, eps, tau, mob)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("n", [3, 4])
+def test_coarsest_newton_is_quadratic(n):
+    """Newton with the exact Jacobian of the flux form: a handful of iterations
+    to 1e-14 (a wrong Jacobian still converges, but linearly)."""
+    L, eps, tau = n * 2.0, 0.25, 0.5
+    h = L / n
+    g = inputs.rng(18 + n)
+    phk = 0.285 + 0.1 * g.uniform(-1, 1, (n, n, n))
+    phs = 0.2 + g.uniform(-1, 1, (n, n, n))
+    u0 = np.stack([phk + 0.2 * g.uniform(-1, 1, (n, n, n)), g.uniform(-1, 1, (n, n, n)),
+                   g.uniform(-1, 1, (n, n, n))])
+    f = cfas.apply_N_m(u0, phk, phs, h, eps, tau, MOB)
+    start = np.stack([phk, np.zeros_like(phk), np.zeros_like(phk)])
+    u, it = cfas.coarse_solve_m(start, f, phk, phs, h, eps, tau, MOB)
+    assert 1 <= it <= 7, it
+    assert np.max(np.abs(u - u0)) < 1e-11
