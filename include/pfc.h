@@ -298,7 +298,9 @@ const char *pfc_batch_last_error(const pfc_batch *b);
 #define PFC_KERNEL_PROLONG0 2    /* finest-level interpolation + correction     */
 #define PFC_KERNEL_NORM0 3       /* finest-level residual max-norm              */
 #define PFC_KERNEL_COARSE 4      /* coarsest-level solve                        */
-#define PFC_KERNEL_COUNT 5
+#define PFC_KERNEL_SWEEP_NORM0 5 /* finest-level first pre-sweep that also forms
+                                    half of the stop-test norm of its input     */
+#define PFC_KERNEL_COUNT 6
 /* When enabled, HIP events bracket each launch of the listed kernels on the
  * handle's stream and their durations are accumulated at every host
  * synchronisation point of the handle. */

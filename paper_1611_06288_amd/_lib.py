@@ -29,8 +29,9 @@ PFC_KERNEL_RESIDUAL0 = 1
 PFC_KERNEL_PROLONG0 = 2
 PFC_KERNEL_NORM0 = 3
 PFC_KERNEL_COARSE = 4
-PFC_KERNEL_COUNT = 5
-KERNEL_NAMES = ["smooth0", "residual0", "prolong0", "norm0", "coarse"]
+PFC_KERNEL_SWEEP_NORM0 = 5
+PFC_KERNEL_COUNT = 6
+KERNEL_NAMES = ["smooth0", "residual0", "prolong0", "norm0", "coarse", "sweep_norm0"]
 
 
 class HipLibraryMissing(RuntimeError):

@@ -196,6 +196,39 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
     return red[0];
 }
 
+// Block max of non-negative IEEE bit patterns through wave shuffles and one
+// word per wave of LDS (wm: blockDim.x / 64 entries); for kernels whose LDS
+// budget leaves no room for a per-thread array.  Every thread calls it.
+__device__ __forceinline__ unsigned long long block_max_u64_waves(unsigned long long v,
+                                                                  unsigned long long *wm) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = (unsigned long long)__double_as_longlong(
+            __shfl_xor(__longlong_as_double((long long)v), off, 64));
+        v = umax(v, o);
+    }
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long r = wm[0];
+    for (unsigned w = 1; w < blockDim.x / 64; ++w) r = umax(r, wm[w]);
+    return r;
+}
+
+// r = S - N(u) at one point (M = 1) from the discrete Laplacians ls of phi, mu
+// and omega there: the three equations of the scheme's operator (the cubic
+// term as g, or its correction form with base bb when DELTA).  Every kernel
+// that forms a point residual from Laplacians calls this, so their results
+// agree bit for bit.
+template <bool DELTA>
+__device__ __forceinline__ void resid_from_lap(const OpParams &op, const double (&ls)[3],
+                                               double phi, double mu, double om, double f0,
+                                               double f1, double f2, double ak, double bb,
+                                               double (&r)[3]) {
+    const double tau = op.tau, lin_c = lin_of(op), w3 = w3_of(op);
+    r[0] = f0 - (phi - tau * ls[1]);
+    r[1] = f1 - (mu - g_of<DELTA>(op.fo, phi, ak, bb) - lin_c * phi - ls[2]);
+    r[2] = f2 - (om - w3 * ls[0]);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     return v;

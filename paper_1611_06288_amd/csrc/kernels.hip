@@ -149,6 +149,22 @@ void launch_max_final(hipStream_t s, const unsigned long long *partial, int coun
     hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, partial, count, out, gate);
 }
 
+// The max of partial[0 .. count) into dst[0] and zeros into dst[1 .. dcount):
+// seeds one half of a split stop-test norm with a whole-level norm (max is
+// exact and idempotent, so the other half's partials then change nothing).
+__global__ __launch_bounds__(kBlock) void k_norm_seed(const unsigned long long *partial, int count,
+                                                      unsigned long long *dst, int dcount) {
+    unsigned long long m = 0;
+    for (int b = threadIdx.x; b < count; b += kBlock) m = umax(m, partial[b]);
+    m = block_max_u64(m);
+    for (int b = threadIdx.x; b < dcount; b += kBlock) dst[b] = b == 0 ? m : 0ull;
+}
+
+void launch_norm_seed(hipStream_t s, const unsigned long long *partial, int count,
+                      unsigned long long *dst, int dcount) {
+    hipLaunchKernelGGL(k_norm_seed, dim3(1), dim3(kBlock), 0, s, partial, count, dst, dcount);
+}
+
 // ------------------------------------------------ stop test of the time loop
 
 __global__ void k_run_reset(RunState st) {

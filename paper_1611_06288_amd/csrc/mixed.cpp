@@ -245,6 +245,8 @@ double algorithmic_bytes(const pfc_handle *H, int kernel) {
         case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0 + mob) * P;
         case PFC_KERNEL_PROLONG0: return (mixed ? 27.0 : 54.0) * P;
         case PFC_KERNEL_NORM0: return (mixed ? (H->lev[0].rt ? 108.0 : 72.0) : 56.0 + mob) * P;
+        // the fused sweep's 72 plus old mu and omega of the colour-0 points
+        case PFC_KERNEL_SWEEP_NORM0: return H->split_norm ? 80.0 * P : 0.0;
         default: return 0.0;
     }
 }

@@ -90,10 +90,14 @@ void launch_sweep_small(hipStream_t s, const OpParams &op, int picard, Tri<T> u,
 // One full red-black sweep (colour 0 then colour 1) from uin into uout
 // (distinct buffers, colour-split storage), bitwise equal to two launch_smooth
 // calls; the level is cut into nz plane ranges (see fused_nz).  Instantiated
-// for double only.
+// for double only.  nrm (M = 1 only) adds half of the stop-test norm as
+// per-workgroup maxima of |S - N(u)| bits in part[0 .. fused_blocks(n, nz)):
+// 1 over the colour-0 points of uin, 2 over the colour-1 points of uout.
 template <typename T, bool DELTA>
 void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
-                        Tri<T> uout, Tri<const T> f, const T *phk, const T *base);
+                        Tri<T> uout, Tri<const T> f, const T *phk, const T *base, int nrm = 0,
+                        unsigned long long *part = nullptr);
+int fused_blocks(int n, int nz);  // workgroups of one fused-sweep launch
 bool fused_fits(int n);           // n admits the fused sweep's column tiling
 int fused_slots(int device, bool mob = false);      // resident fused-sweep workgroups on the device (0 on error)
 int fused_nz(int n, int slots);   // plane ranges per column for a level of size n
@@ -153,6 +157,9 @@ int launch_resid_max(hipStream_t s, const OpParams &op, Tri<const T> u, Tri<cons
 
 void launch_max_final(hipStream_t s, const unsigned long long *partial, int count, double *out,
                       const int *gate = nullptr);
+// dst[0] = max of partial[0 .. count), dst[1 .. dcount) = 0 (bit patterns).
+void launch_norm_seed(hipStream_t s, const unsigned long long *partial, int count,
+                      unsigned long long *dst, int dcount);
 
 // Device-side stop test of the time loop: the cycle loop's decision on the
 // norm *rho (the residual max-norm before a cycle), made on the GPU so that a

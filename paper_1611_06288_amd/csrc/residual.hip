@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
 
     unsigned long long m = 0;
     double sr[3] = {0.0, 0.0, 0.0}, su[3] = {0.0, 0.0, 0.0};
-    const double h2inv = op.h2inv, tau = op.tau, lin_c = lin_of(op), w3 = w3_of(op);
+    const double h2inv = op.h2inv;
     for (int p = z0; p < z1; ++p) {
         T nxt[2][NO];
         if (p + 1 < z1) {
@@ -189,10 +189,8 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
                 face(sm, row, col);
                 ls[1] = sm6 * h2inv;
             }
-            r[e][0] = (double)cur[e][0] - (phi - tau * ls[1]);
-            r[e][1] = (double)cur[e][1] -
-                      (mu - g_of<DELTA>(op.fo, phi, ak, bb) - lin_c * phi - ls[2]);
-            r[e][2] = (double)cur[e][2] - (om - w3 * ls[0]);
+            resid_from_lap<DELTA>(op, ls, phi, mu, om, (double)cur[e][0], (double)cur[e][1],
+                                  (double)cur[e][2], ak, bb, r[e]);
         }
         if constexpr (RESTRICT) {
             // children in the order (x, y, z) = 000, 100, 010, 110, 001, ...: this

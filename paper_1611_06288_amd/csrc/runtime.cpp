@@ -212,13 +212,16 @@ pfc_handle::~pfc_handle() {
 
 namespace pfc {
 
-static void sweep64(pfc_handle *H, int l) {
+void sweep64(pfc_handle *H, int l, int nrm) {
     Level &A = H->lev[l];
     const OpParams op = op_of(H, l);
     if (A.fused) {  // one pass, then the two iterate buffers trade places
-        H->begin_timed(PFC_KERNEL_SMOOTH0, l);
+        if (!H->split_norm || l != 0) nrm = 0;
+        unsigned long long *part =
+            nrm == 1 ? H->partial : (nrm == 2 ? H->partial + H->split_blocks : nullptr);
+        H->begin_timed(nrm == 1 ? PFC_KERNEL_SWEEP_NORM0 : PFC_KERNEL_SMOOTH0, l);
         launch_sweep_fused<double, false>(H->stream, op, H->cfg.lin == PFC_LIN_PICARD, A.nz,
-                                          cst(A.u), A.u2, cst(A.f), A.phk, nullptr);
+                                          cst(A.u), A.u2, cst(A.f), A.phk, nullptr, nrm, part);
         H->end_timed();
         std::swap(A.u, A.u2);
         return;
@@ -238,7 +241,7 @@ static void sweep64(pfc_handle *H, int l) {
     }
 }
 
-void cycle64(pfc_handle *H, int l, bool fcycle) {
+void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
     Level &A = H->lev[l];
     if (l == H->nlev - 1) {
         H->begin_timed(PFC_KERNEL_COARSE, l);
@@ -249,7 +252,7 @@ void cycle64(pfc_handle *H, int l, bool fcycle) {
         return;
     }
     Level &B = H->lev[l + 1];
-    for (int s = 0; s < H->cfg.nu1; ++s) sweep64(H, l);
+    for (int s = (flags & kCyclePreDone) ? 1 : 0; s < H->cfg.nu1; ++s) sweep64(H, l);
     H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
     if (A.rt) {
         ResidTileArgs ra;
@@ -271,7 +274,8 @@ void cycle64(pfc_handle *H, int l, bool fcycle) {
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
     launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u, H->gate);
     H->end_timed();
-    for (int s = 0; s < H->cfg.nu2; ++s) sweep64(H, l);
+    for (int s = 0; s < H->cfg.nu2; ++s)
+        sweep64(H, l, (flags & kCyclePostNorm) && s == H->cfg.nu2 - 1 ? 2 : 0);
 }
 
 void restrict_phk(pfc_handle *H) {
@@ -301,9 +305,10 @@ pfc_status read_norm(pfc_handle *H, int partials, double *out) {
     return PFC_OK;
 }
 
-// Per-workgroup maxima of |S - N(u)| at the finest level into H->partial
-// (written to r too if r.a is set); returns their count.
-static int enqueue_norm(pfc_handle *H, Tri<double> r) {
+// Per-workgroup maxima of |S - N(u)| at the finest level into dst (default
+// H->partial; written to r too if r.a is set); returns their count.
+static int enqueue_norm(pfc_handle *H, Tri<double> r, unsigned long long *dst = nullptr) {
+    if (!dst) dst = H->partial;
     Level &A = H->lev[0];
     H->begin_timed(PFC_KERNEL_NORM0, 0);
     int cnt;
@@ -312,17 +317,19 @@ static int enqueue_norm(pfc_handle *H, Tri<double> r) {
         ra.u = cst(A.u);
         ra.f = cst(A.f);
         ra.phk = A.phk;
-        ra.partial = H->partial;
+        ra.partial = dst;
         cnt = launch_resid_tile(H->stream, RT_NORM, op_of(H, 0), A.rt_nz[RT_NORM], ra);
     } else {
         cnt = launch_resid_max<double, false>(H->stream, op_of(H, 0), cst(A.u), cst(A.f), A.phk,
-                                              nullptr, r, H->partial);
+                                              nullptr, r, dst);
     }
     H->end_timed();
     return cnt;
 }
 
-int enqueue_norm64(pfc_handle *H) { return enqueue_norm(H, Tri<double>{nullptr, nullptr, nullptr}); }
+int enqueue_norm64(pfc_handle *H, unsigned long long *dst) {
+    return enqueue_norm(H, Tri<double>{nullptr, nullptr, nullptr}, dst);
+}
 
 // Residual max-norm at the finest level (r.a may be null).  Synchronises.
 pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out) {
@@ -434,7 +441,14 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
             A.u2 = Tri<double>{u2, u2 + A.P, u2 + 2 * A.P};
         }
     }
-    ok = ok && dalloc(H, &H->partial, (size_t)kMaxReduceBlocks + 16);
+    ok = ok && dalloc(H, &H->partial, (size_t)3 * kMaxReduceBlocks + 16);
+    if (ok) {  // the split stop test (the graph loop seeds it behind both halves)
+        const Level &A = H->lev[0];
+        H->split_blocks = A.fused ? fused_blocks(A.n, A.nz) : 0;
+        H->split_norm = A.fused && cfg->nu1 >= 1 && cfg->nu2 >= 1 &&
+                        cfg->precision == PFC_FP64 && !mob &&
+                        H->split_blocks <= kMaxReduceBlocks;
+    }
     ok = ok && dalloc(H, &H->d_scal, 16) && dalloc(H, &H->d_iters, 4);
     ok = ok && dalloc(H, &H->energy_part, (size_t)6 * kMaxReduceBlocks + 16);
     ok = ok && dalloc(H, &H->minv64, 64 * 64) && dalloc(H, &H->minv32, 64 * 64) &&
@@ -532,9 +546,15 @@ pfc_status step64(pfc_handle *h, const double *phi_prev, const double *phi_cur, 
     int c = 0;
     double rho = 0, rho0 = 0;
     pfc_status status = PFC_OK;
-    for (;;) {
+    // With the split stop test, the norm after a cycle is completed by the next
+    // cycle's first pre-sweep, launched before the decision; when the loop then
+    // stops, that sweep's output is dropped (its input buffer is untouched).
+    bool ahead = false;
+    {
         const pfc_status st = resid_norm64(h, Tri<double>{nullptr, nullptr, nullptr}, &rho);
         if (st != PFC_OK) return st;
+    }
+    for (;;) {
         if (c == 0) rho0 = rho;
         if (!std::isfinite(rho)) {
             status = PFC_ERR_NONFINITE;
@@ -545,9 +565,22 @@ pfc_status step64(pfc_handle *h, const double *phi_prev, const double *phi_cur, 
             status = PFC_ERR_NOT_CONVERGED;
             break;
         }
-        cycle64(h, 0, h->cfg.cycle == PFC_CYCLE_F);
+        const bool split = h->split_norm && c + 1 < h->cfg.max_cycles;
+        cycle64(h, 0, h->cfg.cycle == PFC_CYCLE_F,
+                (ahead ? kCyclePreDone : 0u) | (split ? kCyclePostNorm : 0u));
         ++c;
+        pfc_status st;
+        if (split) {
+            sweep64(h, 0, 1);
+            ahead = true;
+            st = read_norm(h, 2 * h->split_blocks, &rho);
+        } else {
+            ahead = false;
+            st = resid_norm64(h, Tri<double>{nullptr, nullptr, nullptr}, &rho);
+        }
+        if (st != PFC_OK) return st;
     }
+    if (ahead) std::swap(h->lev[0].u, h->lev[0].u2);
     step_end(h, phi_next, mu, omega);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipStreamSynchronize(h->stream));

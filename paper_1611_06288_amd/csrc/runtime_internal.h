@@ -72,6 +72,13 @@ struct pfc_handle {
     double *minv_adj = nullptr;  // cached coarsest inverse of the adjoint solve
     int *valid_adj = nullptr;
     double *energy_part = nullptr;
+    // stop test split over the finest level's fused sweeps (FP64, M = 1): the
+    // last post-sweep of a cycle leaves the colour-1 half of the norm in
+    // partial[split_blocks .. 2 split_blocks), the next cycle's first
+    // pre-sweep, run ahead of the decision, the colour-0 half in
+    // partial[0 .. split_blocks)
+    bool split_norm = false;
+    int split_blocks = 0;
     // graph-driven time loop (pfc_run)
     const int *gate = nullptr;            // cycle gate, set only while its graph is recorded
     hipStream_t run_stream = nullptr;     // the loop's own stream (capturable)
@@ -91,8 +98,8 @@ struct pfc_handle {
     int cur_event = -1;
     std::vector<pfc::TimedLaunch> pending;
     std::vector<hipEvent_t> pool;
-    int64_t t_count[PFC_KERNEL_COUNT] = {0, 0, 0, 0, 0};
-    double t_ms[PFC_KERNEL_COUNT] = {0, 0, 0, 0, 0};
+    int64_t t_count[PFC_KERNEL_COUNT] = {};
+    double t_ms[PFC_KERNEL_COUNT] = {};
 
     void begin_timed(int kind, int level);
     void end_timed();
@@ -102,10 +109,15 @@ struct pfc_handle {
 
 namespace pfc {
 OpParams op_of(const pfc_handle *H, int l);
-void cycle64(pfc_handle *H, int l, bool fcycle);
+// flags of cycle64 at the finest level
+constexpr unsigned kCyclePreDone = 1;   // its first pre-sweep has already run (sweep64 nrm 1)
+constexpr unsigned kCyclePostNorm = 2;  // its last post-sweep leaves the colour-1 norm half
+void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags = 0);
+// One smoothing sweep of level l; nrm as in launch_sweep_fused (split_norm only).
+void sweep64(pfc_handle *H, int l, int nrm = 0);
 void restrict_phk(pfc_handle *H);
 pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out);
-int enqueue_norm64(pfc_handle *H);
+int enqueue_norm64(pfc_handle *H, unsigned long long *dst = nullptr);
 pfc_status read_norm(pfc_handle *H, int partials, double *out);
 pfc_status mixed_init(pfc_handle *H);
 pfc_status step64(pfc_handle *h, const double *phi_prev, const double *phi_cur, double *phi_next,

@@ -99,6 +99,16 @@ template void launch_sweep_small<float, true>(hipStream_t, const OpParams &, int
 // MOB (variable mobility): phi* rides along as a fourth field of both rings
 // (read-only), and the mu-sum becomes the face-mobility sum of the flux form
 // in the half-sweep's neighbour order.
+// NRM (M = 1, FP64) carries half of the cycle loop's stop test, max |S - N(u)|
+// over the level, as per-workgroup maxima in part[blockIdx.x]:
+//   NRM = 1: over the colour-0 points of the sweep's INPUT (their neighbour sums
+//            are the colour-0 phase's own; old mu and omega of the box's
+//            colour-0 points are read in addition, 8 B per point),
+//   NRM = 2: over the colour-1 points of the sweep's OUTPUT (neighbour sums of
+//            the colour-1 phase, the point's new values).
+// The neighbour sums are taken in the residual kernels' order and the
+// residual is formed by the same function, so the two halves together give
+// bitwise the norm of the residual kernels.
 constexpr int kFX = 64, kFY = 8, kFT = 256;  // column extents, threads per workgroup
 constexpr int kFSl = kFX / 2 + 1;            // colour-0 ring: points per row
 constexpr int kFRw = kFY + 2;                //                rows
@@ -108,15 +118,17 @@ constexpr int kFNr = kFSl * kFRw, kFNb = (kFX / 2) * kFY, kFNc = kFCs * kFCr;
 constexpr int kFIr = (kFNr + kFT - 1) / kFT, kFIb = (kFNb + kFT - 1) / kFT,
               kFIc = (kFNc + kFT - 1) / kFT;  // items per thread in each phase
 
-template <typename T, bool DELTA, bool MOB>
+template <typename T, bool DELTA, bool MOB, int NRM>
 __global__ __launch_bounds__(kFT) void k_sweep_fused(
     OpParams op, int picard, int nz, const T *__restrict__ ua, const T *__restrict__ ub,
     const T *__restrict__ uc, T *__restrict__ oa, T *__restrict__ ob, T *__restrict__ oc,
     const T *__restrict__ fa, const T *__restrict__ fb, const T *__restrict__ fc,
-    const T *__restrict__ phk, const T *__restrict__ base) {
+    const T *__restrict__ phk, const T *__restrict__ base, unsigned long long *__restrict__ part) {
+    static_assert(NRM == 0 || (!DELTA && !MOB), "stop-test halves: FP64 sweeps with M = 1");
     constexpr int NF = MOB ? 4 : 3;         // ring fields: phi, mu, omega (, phi*)
     __shared__ T c1[NF][3][kFCr][kFCs];   // [field][plane slot][row][point] old colour 1
     __shared__ T red[NF][3][kFRw][kFSl];  // [field][plane slot][row][point] new colour 0
+    __shared__ unsigned long long wmax[kFT / 64];  // NRM: per-wave maxima
     if (gate_closed(op.gate)) return;
     const double *__restrict__ ps = op.mob.phs;
     const int n = op.lay.n, hn = n >> 1;
@@ -168,6 +180,10 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
     // own inputs of the colour-0 points of plane k (box plus ring)
     T ro[kFIr][MOB ? 7 : 6];
     unsigned rg[kFIr];
+    T rmo[kFIr][2];  // NRM = 1: old mu, omega of the box's colour-0 points
+    auto in_box = [&](int x, int y, int k) {
+        return x >= x0 && x < x0 + kFX && y >= y0 && y < y0 + kFY && k >= z0 && k < z1;
+    };
     auto load_red = [&](int k) {
         const unsigned kw = (unsigned)wn(k);
 #pragma unroll
@@ -186,6 +202,12 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                 ro[i][4] = fb[g];
                 ro[i][5] = fc[g];
                 if constexpr (MOB) ro[i][6] = ps[g];
+                if constexpr (NRM == 1) {
+                    if (in_box(x, y, k)) {
+                        rmo[i][0] = ub[g];
+                        rmo[i][1] = uc[g];
+                    }
+                }
             }
         }
     };
@@ -211,6 +233,8 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
         }
     };
 
+    unsigned long long nrm = 0;  // NRM: this thread's max |r| bits
+    const double h2inv = op.h2inv;
     load_c1(z0 - 2);
     store_c1(z0 - 2);
     load_c1(z0 - 1);
@@ -267,10 +291,22 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                 red[0][rq][r][sl] = tphi;
                 red[1][rq][r][sl] = tmu;
                 red[2][rq][r][sl] = tom;
-                if (x >= x0 && x < x0 + kFX && y >= y0 && y < y0 + kFY && k >= z0 && k < z1) {
+                if (in_box(x, y, k)) {
                     oa[rg[i]] = tphi;
                     ob[rg[i]] = tmu;
                     oc[rg[i]] = tom;
+                    if constexpr (NRM == 1) {  // residual of the input at this point
+                        const double p0 = (double)ro[i][0], m0 = (double)rmo[i][0],
+                                     w0 = (double)rmo[i][1];
+                        const double ls[3] = {(s3[0] - 6.0 * p0) * h2inv,
+                                              (s3[1] - 6.0 * m0) * h2inv,
+                                              (s3[2] - 6.0 * w0) * h2inv};
+                        double rr[3];
+                        resid_from_lap<false>(op, ls, p0, m0, w0, (double)ro[i][3],
+                                              (double)ro[i][4], (double)ro[i][5],
+                                              (double)ro[i][1], 0.0, rr);
+                        nrm = umax(nrm, umax(abs_bits(rr[0]), umax(abs_bits(rr[1]), abs_bits(rr[2]))));
+                    }
                 }
             }
         }
@@ -337,9 +373,23 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                     oa[g] = (T)phi;
                     ob[g] = (T)mu;
                     oc[g] = (T)om;
+                    if constexpr (NRM == 2) {  // residual of the output at this point
+                        const double ls[3] = {(s3[0] - 6.0 * phi) * h2inv,
+                                              (s3[1] - 6.0 * mu) * h2inv,
+                                              (s3[2] - 6.0 * om) * h2inv};
+                        double rr[3];
+                        resid_from_lap<false>(op, ls, phi, mu, om, (double)bo[i][2],
+                                              (double)bo[i][3], (double)bo[i][4],
+                                              (double)bo[i][0], 0.0, rr);
+                        nrm = umax(nrm, umax(abs_bits(rr[0]), umax(abs_bits(rr[1]), abs_bits(rr[2]))));
+                    }
                 }
             }
         }
+    }
+    if constexpr (NRM != 0) {
+        nrm = block_max_u64_waves(nrm, wmax);
+        if (threadIdx.x == 0) part[blockIdx.x] = nrm;
     }
 }
 
@@ -347,8 +397,8 @@ bool fused_fits(int n) { return n % kFX == 0 && n % kFY == 0 && n >= kFusedMinN;
 
 int fused_slots(int device, bool mob) {
     int occ = 0, cus = 0;
-    const void *fn = mob ? (const void *)k_sweep_fused<double, false, true>
-                         : (const void *)k_sweep_fused<double, false, false>;
+    const void *fn = mob ? (const void *)k_sweep_fused<double, false, true, 0>
+                         : (const void *)k_sweep_fused<double, false, false, 0>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kFT, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
@@ -366,21 +416,37 @@ int fused_nz(int n, int slots) {
     return nz;
 }
 
+int fused_blocks(int n, int nz) { return (n / kFX) * (n / kFY) * nz; }
+
 template <typename T, bool DELTA>
 void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
-                        Tri<T> uout, Tri<const T> f, const T *phk, const T *base) {
+                        Tri<T> uout, Tri<const T> f, const T *phk, const T *base, int nrm,
+                        unsigned long long *part) {
     const int n = op.lay.n;
-    const unsigned blocks = (unsigned)((n / kFX) * (n / kFY) * nz);
+    const unsigned blocks = (unsigned)fused_blocks(n, nz);
     if constexpr (!DELTA) {
         if (op.mob.phs) {  // variable mobility
-            hipLaunchKernelGGL((k_sweep_fused<T, false, true>), dim3(blocks), dim3(kFT), 0, s, op,
-                               picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b,
-                               f.c, phk, base);
+            hipLaunchKernelGGL((k_sweep_fused<T, false, true, 0>), dim3(blocks), dim3(kFT), 0, s,
+                               op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
+                               f.b, f.c, phk, base, nullptr);
+            return;
+        }
+        if (nrm == 1) {
+            hipLaunchKernelGGL((k_sweep_fused<T, false, false, 1>), dim3(blocks), dim3(kFT), 0, s,
+                               op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
+                               f.b, f.c, phk, base, part);
+            return;
+        }
+        if (nrm == 2) {
+            hipLaunchKernelGGL((k_sweep_fused<T, false, false, 2>), dim3(blocks), dim3(kFT), 0, s,
+                               op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
+                               f.b, f.c, phk, base, part);
             return;
         }
     }
-    hipLaunchKernelGGL((k_sweep_fused<T, DELTA, false>), dim3(blocks), dim3(kFT), 0, s, op, picard,
-                       nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b, f.c, phk, base);
+    hipLaunchKernelGGL((k_sweep_fused<T, DELTA, false, 0>), dim3(blocks), dim3(kFT), 0, s, op,
+                       picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b, f.c, phk,
+                       base, nullptr);
 }
 
 template void launch_smooth<double, false>(hipStream_t, const OpParams &, int, int, Tri<double>,
@@ -389,6 +455,7 @@ template void launch_smooth<float, true>(hipStream_t, const OpParams &, int, int
                                          Tri<const float>, const float *, const float *);
 template void launch_sweep_fused<double, false>(hipStream_t, const OpParams &, int, int,
                                                 Tri<const double>, Tri<double>, Tri<const double>,
-                                                const double *, const double *);
+                                                const double *, const double *, int,
+                                                unsigned long long *);
 
 }  // namespace pfc

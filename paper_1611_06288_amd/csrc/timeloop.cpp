@@ -13,6 +13,14 @@
 // kernels, same order, same decisions), so results agree bit for bit, while
 // the host round trips drop from one per cycle to one or two per step and the
 // launches of a cycle go out as one graph.
+//
+// With the split stop test (FP64, M = 1, fused finest level) the recorded
+// unit is instead: the next cycle's first finest-level pre-sweep, which also
+// yields the colour-0 half of the norm of its input, then the decision on
+// both halves, then the rest of the cycle, whose last post-sweep leaves the
+// colour-1 half for the next replay.  A replay that stops leaves the iterate
+// in the pre-sweep's input buffer, which the sweep does not write.  Before a
+// step's first replay the colour-1 half is seeded with the whole-level norm.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -64,10 +72,18 @@ pfc_status record_graph(pfc_handle *H) {
         return hip_fail(H, e, "hipStreamBeginCapture");
     }
     H->gate = H->d_run;  // every launch below reads the active flag
-    const int cnt = enqueue_norm64(H);
-    launch_max_final(H->stream, H->partial, cnt, H->d_scal, H->gate);
-    launch_stop_test(H->stream, H->d_scal, H->cfg.tol, H->cfg.max_cycles, run_state(H));
-    cycle64(H, 0, H->cfg.cycle == PFC_CYCLE_F);
+    const bool fcycle = H->cfg.cycle == PFC_CYCLE_F;
+    if (H->split_norm) {
+        sweep64(H, 0, 1);
+        launch_max_final(H->stream, H->partial, 2 * H->split_blocks, H->d_scal, H->gate);
+        launch_stop_test(H->stream, H->d_scal, H->cfg.tol, H->cfg.max_cycles, run_state(H));
+        cycle64(H, 0, fcycle, kCyclePreDone | kCyclePostNorm);
+    } else {
+        const int cnt = enqueue_norm64(H);
+        launch_max_final(H->stream, H->partial, cnt, H->d_scal, H->gate);
+        launch_stop_test(H->stream, H->d_scal, H->cfg.tol, H->cfg.max_cycles, run_state(H));
+        cycle64(H, 0, fcycle);
+    }
     H->gate = nullptr;
     H->timing = timing;
     e = hipStreamEndCapture(H->stream, &H->run_graph);
@@ -83,6 +99,11 @@ pfc_status graph_step(pfc_handle *H, const double *prev, const double *cur, doub
                       double *mu, double *om, pfc_step_info *info) {
     step_begin(H, prev, cur, mu, om);
     launch_run_reset(H->stream, run_state(H));
+    if (H->split_norm) {
+        unsigned long long *whole = H->partial + 2 * H->split_blocks;
+        const int cnt = enqueue_norm64(H, whole);
+        launch_norm_seed(H->stream, whole, cnt, H->partial + H->split_blocks, H->split_blocks);
+    }
     HIP_TRY(H, hipGetLastError());
     if (!graph_current(H)) {
         const pfc_status st = record_graph(H);
