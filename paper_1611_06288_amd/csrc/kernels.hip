@@ -428,7 +428,9 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
             for (int z = 0; z < 2; ++z)
 #pragma unroll
                 for (int y = 0; y < 2; ++y)
-                    e[z][y] = (double)vv[o[z][y][x]] - (uu ? (double)uu[o[z][y][x]] : 0.0);
+                    // v - ubar rounded to T: the value the coarse-error pass stores
+                    e[z][y] = uu ? (double)(T)((double)vv[o[z][y][x]] - (double)uu[o[z][y][x]])
+                                 : (double)vv[o[z][y][x]];
             w[x] = 0.75 * (0.75 * e[0][0] + 0.25 * e[0][1]) + 0.25 * (0.75 * e[1][0] + 0.25 * e[1][1]);
         }
         ff[f0] = (T)((double)ff[f0] + (0.75 * w[1] + 0.25 * w[0]));
@@ -531,8 +533,8 @@ void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const
                     Tri<const T> ubar, Tri<T> fine_u, const int *gate) {
     const size_t pairs = (size_t)coarse.n * fine.n * fine.n;
     const bool tile = fine.split && fine.n % kPX == 0 && fine.n % kPY == 0;
-    if (std::is_same<T, double>::value && ubar.a && fine_u.b && !tile) {
-        // small FP64 levels: one launch that forms v - ubar where it reads it
+    if (ubar.a && fine_u.b && !tile) {
+        // small levels: one launch that forms v - ubar where it reads it
         // (the same value the separate coarse-error pass would store)
         hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine,
                            v, ubar, fine_u, gate);

@@ -9,9 +9,9 @@
 //          = 1/4 [e (b^2 + (phi^k)^2) + (b + e + phi^k)(2 b e + e^2)],
 // b = phi of the current FP64 iterate rounded to FP32 (restricted to the
 // coarse levels), written without cancellation.  Then u += e in FP64 (on
-// levels with column tiles, inside the next defect pass).  While the residual
-// is far above tol up to twelve FP32 cycles run per defect (one cycle is
-// recorded as a hipGraph and replayed).  The smoother's pointwise
+// levels with column tiles, inside the next defect pass).  Up to twenty FP32
+// cycles run per defect, as many as the observed contraction predicts are
+// needed to reach tol (one cycle is recorded as a hipGraph and replayed).  The smoother's pointwise
 // 3x3 solve, the residual and all reductions run in FP64 arithmetic; only
 // stored fields of the correction cycle are FP32.
 #include <cmath>
@@ -21,10 +21,17 @@
 
 namespace pfc {
 
-// Up to kMaxInnerCycles FP32 cycles per FP64 defect, each extra one only
-// while the predicted residual after it still exceeds this multiple of tol.
-constexpr int kMaxInnerCycles = 12;
-constexpr double kInnerCycleMargin = 3.0;
+// Up to kMaxInnerCycles FP32 cycles per FP64 defect: as many as the observed
+// contraction predicts are needed to bring the residual within kTolMargin of
+// tol, while the predicted reduction of this defect stays above
+// kMinDefectFactor: the FP32 correction cannot reduce an FP64 defect by much
+// more than that (the stored correction's rounding, amplified by the
+// operator), so cycles past it would be spent at that floor.  The margin
+// keeps an optimistic prediction from running cycles the FP64 loop would
+// not; a pessimistic one costs one more defect pass.
+constexpr int kMaxInnerCycles = 20;
+constexpr double kMinDefectFactor = 1e-5;
+constexpr double kTolMargin = 1.5;
 
 pfc_status mixed_init(pfc_handle *H) {
     for (int l = 0; l < H->nlev; ++l) {
@@ -183,14 +190,15 @@ static pfc_status mixed_step_on(pfc_handle *H, const double *phi_prev, const dou
         }
         // FP32 cycles on this defect: as many (up to kMaxInnerCycles) as the
         // observed contraction per cycle predicts the FP64 loop would run
-        // anyway before reaching tol (with a margin), at least one.  Each
-        // FP64 defect pass saved is a full-level FP64 read of u, f and phi^k.
+        // anyway before reaching tol, at least one.  Each FP64 defect pass
+        // saved is a full-level FP64 read of u, f and phi^k.
         int inner = 1;
         if (rho_prev > 0 && rho < rho_prev) {
             const double q = std::pow(rho / rho_prev, 1.0 / inner_prev);
             double pred = rho * q;
             while (inner < kMaxInnerCycles && c + inner + 1 <= H->cfg.max_cycles &&
-                   pred * q > kInnerCycleMargin * H->cfg.tol) {
+                   pred > kTolMargin * H->cfg.tol &&
+                   pred * q > kMinDefectFactor * rho) {
                 ++inner;
                 pred *= q;
             }
