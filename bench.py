@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the smoother sources
 # it was measured on (first 16 hex digits of the sha256 of smooth.hip, smooth.h
 # and device_common.h, concatenated); otherwise reported null.
-SMOOTHER_TRAFFIC = {"sources_sha256_16": "76d506f49d4cfd91", "n": 256,
-                    "fetch_KiB": 465494, "write_KiB": 395512,
+SMOOTHER_TRAFFIC = {"sources_sha256_16": "a1a9808ce48067c0", "n": 256,
+                    "fetch_KiB": 466280, "write_KiB": 395528,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 SMOOTHER_SOURCES = ("smooth.hip", "smooth.h", "device_common.h")
 METRIC = "time-steps/s & V-cycles/s at 256^3 (FP64 vs mixed); smoother HBM GB/s %peak"
