@@ -14,6 +14,7 @@
 // needed to reach tol (one cycle is recorded as a hipGraph and replayed).  The smoother's pointwise
 // 3x3 solve, the residual and all reductions run in FP64 arithmetic; only
 // stored fields of the correction cycle are FP32.
+#include <algorithm>
 #include <cmath>
 #include <utility>
 
@@ -28,10 +29,14 @@ namespace pfc {
 // more than that (the stored correction's rounding, amplified by the
 // operator), so cycles past it would be spent at that floor.  The margin
 // keeps an optimistic prediction from running cycles the FP64 loop would
-// not; a pessimistic one costs one more defect pass.
+// not; a pessimistic one costs one more defect pass.  The floor test takes
+// the contraction as at least kFloorQ: the first cycles of a step remove the
+// rough part of the error at rates the later ones never reach, and a floor
+// predicted from them would cut the next defect's cycles short.
 constexpr int kMaxInnerCycles = 20;
 constexpr double kMinDefectFactor = 1e-5;
 constexpr double kTolMargin = 1.5;
+constexpr double kFloorQ = 0.5;
 
 pfc_status mixed_init(pfc_handle *H) {
     for (int l = 0; l < H->nlev; ++l) {
@@ -195,12 +200,13 @@ static pfc_status mixed_step_on(pfc_handle *H, const double *phi_prev, const dou
         int inner = 1;
         if (rho_prev > 0 && rho < rho_prev) {
             const double q = std::pow(rho / rho_prev, 1.0 / inner_prev);
-            double pred = rho * q;
+            const double qf = std::max(q, kFloorQ);
+            double pred = rho * q, predf = rho * qf;
             while (inner < kMaxInnerCycles && c + inner + 1 <= H->cfg.max_cycles &&
-                   pred > kTolMargin * H->cfg.tol &&
-                   pred * q > kMinDefectFactor * rho) {
+                   pred > kTolMargin * H->cfg.tol && predf * qf > kMinDefectFactor * rho) {
                 ++inner;
                 pred *= q;
+                predf *= qf;
             }
         }
         for (int l = 0; l + 1 < H->nlev; ++l)
