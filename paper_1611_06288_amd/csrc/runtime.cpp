@@ -358,7 +358,10 @@ namespace pfc {
 void step_begin(pfc_handle *H, const double *phi_prev, const double *phi_cur, const double *mu,
                 const double *omega) {
     Level &A = H->lev[0];
-    invalidate_coarse(H);
+    // The coarsest level's cached Newton inverse carries over from the
+    // previous step: the chord iteration rebuilds it wherever an update
+    // contracts by less than 4x, so a stale inverse costs iterations, never
+    // accuracy (each solve still runs to its 1e-14 update bound).
     launch_source(H->stream, op_of(H, 0), phi_cur, phi_prev, A.f);
     to_level0(H, phi_cur, mu, omega);
     launch_to_lay<double, double>(H->stream, A.lay, phi_cur, A.phk, 1);

@@ -63,10 +63,16 @@ def workload(n, seed):
 def check_step(n, seed, tol, max_cycles, **kw):
     p, phi = workload(n, seed)
     s = make(n, p.L, p.eps, p.dt, tol=tol, max_cycles=max_cycles, **kw)
+    ref = make(n, p.L, p.eps, p.dt, tol=tol, max_cycles=max_cycles, **kw)
     mu, om = s.init_guess(phi)
-    # the state one step in, so that phi_prev != phi_cur
+    mu_r, om_r = mu.clone(), om.clone()
+    # the state one step in, so that phi_prev != phi_cur; the reference handle
+    # takes the same step, so both carry the same coarsest-level inverse
     cur, info = s.step(phi, phi, mu, om, raise_on_error=False)
     assert info.status in (0, 2)
+    cur_r, _ = ref.step(phi, phi, mu_r, om_r, raise_on_error=False)
+    torch.cuda.synchronize()
+    assert torch.equal(cur, cur_r)
     prev = phi
     mu_h, om_h = mu.clone(), om.clone()
     s.timing(True)
@@ -75,7 +81,6 @@ def check_step(n, seed, tol, max_cycles, **kw):
     counts = {k: s.timing_get(k)[0] for k in (PFC_KERNEL_SMOOTH0, PFC_KERNEL_SWEEP_NORM0,
                                                PFC_KERNEL_NORM0)}
     s.timing(False)
-    ref = make(n, p.L, p.eps, p.dt, tol=tol, max_cycles=max_cycles, **kw)
     u, c, status, res0, res = host_loop(ref, prev, cur, mu_h, om_h, tol, max_cycles)
     torch.cuda.synchronize()
     assert (info.cycles, info.status) == (c, status)
