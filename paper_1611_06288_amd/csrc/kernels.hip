@@ -184,9 +184,15 @@ void launch_run_reset(hipStream_t s, RunState st) {
 // The decision the host loop of a time step takes before each cycle: stop on
 // a non-finite norm, on norm <= tol, or when max_cycles cycles have run;
 // otherwise count the cycle that follows.
-__global__ void k_stop_test(const double *rho, double tol, int max_cycles, RunState st) {
-    if (threadIdx.x != 0 || *st.active == 0) return;
-    const double r = *rho;
+__global__ __launch_bounds__(kBlock) void k_stop_test(const unsigned long long *partial,
+                                                      int count, double tol, int max_cycles,
+                                                      RunState st) {
+    if (*st.active == 0) return;  // the same for every thread of the block
+    unsigned long long m = 0;
+    for (int b = threadIdx.x; b < count; b += kBlock) m = umax(m, partial[b]);
+    m = block_max_u64(m);
+    if (threadIdx.x != 0) return;
+    const double r = __longlong_as_double((long long)m);
     const int c = *st.cycles;
     if (c == 0) *st.res0 = r;
     *st.res = r;
@@ -203,8 +209,10 @@ __global__ void k_stop_test(const double *rho, double tol, int max_cycles, RunSt
     }
 }
 
-void launch_stop_test(hipStream_t s, const double *rho, double tol, int max_cycles, RunState st) {
-    hipLaunchKernelGGL(k_stop_test, dim3(1), dim3(64), 0, s, rho, tol, max_cycles, st);
+void launch_stop_test(hipStream_t s, const unsigned long long *partial, int count, double tol,
+                      int max_cycles, RunState st) {
+    hipLaunchKernelGGL(k_stop_test, dim3(1), dim3(kBlock), 0, s, partial, count, tol, max_cycles,
+                       st);
 }
 
 // ------------------------------------------------ residual + coarsening

@@ -162,7 +162,9 @@ void launch_norm_seed(hipStream_t s, const unsigned long long *partial, int coun
                       unsigned long long *dst, int dcount);
 
 // Device-side stop test of the time loop: the cycle loop's decision on the
-// norm *rho (the residual max-norm before a cycle), made on the GPU so that a
+// residual max-norm before a cycle, reduced from the per-workgroup maxima
+// partial[0 .. count) (IEEE bit patterns) by the same one-block launch, made
+// on the GPU so that a
 // replayed graph of cycles needs no host round trip.  active: cycles still
 // wanted (the gate of the cycle kernels); cycles: cycles started; status: a
 // pfc_status; res0/res: first and latest norm.
@@ -174,7 +176,8 @@ struct RunState {
     double *res;
 };
 void launch_run_reset(hipStream_t s, RunState st);
-void launch_stop_test(hipStream_t s, const double *rho, double tol, int max_cycles, RunState st);
+void launch_stop_test(hipStream_t s, const unsigned long long *partial, int count, double tol,
+                      int max_cycles, RunState st);
 
 // Coarsest level (natural layout, n = 3 or 4).  lu/piv: cached factorisation
 // of the Newton matrix (device scratch of 64*64 doubles and 64 ints), reused

@@ -75,13 +75,13 @@ pfc_status record_graph(pfc_handle *H) {
     const bool fcycle = H->cfg.cycle == PFC_CYCLE_F;
     if (H->split_norm) {
         sweep64(H, 0, 1);
-        launch_max_final(H->stream, H->partial, 2 * H->split_blocks, H->d_scal, H->gate);
-        launch_stop_test(H->stream, H->d_scal, H->cfg.tol, H->cfg.max_cycles, run_state(H));
+        launch_stop_test(H->stream, H->partial, 2 * H->split_blocks, H->cfg.tol,
+                         H->cfg.max_cycles, run_state(H));
         cycle64(H, 0, fcycle, kCyclePreDone | kCyclePostNorm);
     } else {
         const int cnt = enqueue_norm64(H);
-        launch_max_final(H->stream, H->partial, cnt, H->d_scal, H->gate);
-        launch_stop_test(H->stream, H->d_scal, H->cfg.tol, H->cfg.max_cycles, run_state(H));
+        launch_stop_test(H->stream, H->partial, cnt, H->cfg.tol, H->cfg.max_cycles,
+                         run_state(H));
         cycle64(H, 0, fcycle);
     }
     H->gate = nullptr;
