@@ -328,8 +328,19 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
             *d = nullptr;
             return true;
         }
-        return balloc(B, d, v.size()) &&
-               hipMemcpy(*d, v.data(), v.size() * sizeof(BSeg), hipMemcpyHostToDevice) == hipSuccess;
+        std::vector<BSeg> w = v;  // with this list's first blocks
+        for (int kind = 0; kind < 6; ++kind)
+            for (int ti = 0; ti < 4; ++ti) {
+                const unsigned tile = 64u << ti;
+                const int ck = kind == BK_ERR ? BK_RR : kind;
+                unsigned acc = 0;
+                for (auto &g : w) {
+                    g.first[kind][ti] = acc;
+                    acc += (seg_count(g, ck) + tile - 1) / tile;
+                }
+            }
+        return balloc(B, d, w.size()) &&
+               hipMemcpy(*d, w.data(), w.size() * sizeof(BSeg), hipMemcpyHostToDevice) == hipSuccess;
     };
     B->d_all.resize(B->maxdepth);
     B->d_mid.resize(B->maxdepth);

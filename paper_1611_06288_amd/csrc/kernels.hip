@@ -1047,8 +1047,9 @@ void launch_zero(hipStream_t s, float *p, size_t count) {
 //
 // One launch serves every instance that takes part in a multigrid phase: the
 // grid is the concatenation of each instance's blocks (its "segment"), a
-// workgroup finds its segment by a scan over the per-instance block counts,
-// and instances whose convergence flag is cleared return at once.
+// workgroup finds its segment by a binary search over the segments' first
+// blocks (precomputed per launch kind and workgroup size), and instances
+// whose convergence flag is cleared return at once.
 
 __device__ __forceinline__ unsigned bseg_count(const BSeg &g, int kind) {
     const unsigned n = (unsigned)g.op.lay.n, P = n * n * n;
@@ -1060,19 +1061,22 @@ __device__ __forceinline__ unsigned bseg_count(const BSeg &g, int kind) {
     }
 }
 
-// Segment of workgroup blockIdx.x for a launch of `kind`; -1 past the end.
+// Segment of workgroup blockIdx.x for a launch of `kind` with workgroups of
+// 64, 128, 256 or 512 threads; -1 past the end.
 __device__ __forceinline__ int bseg_find(const BSeg *segs, int nseg, int kind, unsigned &local) {
-    unsigned acc = 0;
     const unsigned b = blockIdx.x, bd = blockDim.x;
-    for (int s = 0; s < nseg; ++s) {
-        const unsigned nb = (bseg_count(segs[s], kind) + bd - 1) / bd;
-        if (b < acc + nb) {
-            local = b - acc;
-            return s;
-        }
-        acc += nb;
+    const int ti = bd == 64 ? 0 : (bd == 128 ? 1 : (bd == 256 ? 2 : 3));
+    int lo = 0, hi = nseg - 1;  // the last segment whose first block is <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].first[kind][ti] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
-    return -1;
+    local = b - segs[lo].first[kind][ti];
+    const unsigned nb = (bseg_count(segs[lo], kind) + bd - 1) / bd;
+    return local < nb ? lo : -1;
 }
 
 __global__ __launch_bounds__(512) void kb_smooth(const BSeg *segs, int nseg, int colour, int picard) {

@@ -236,6 +236,10 @@ struct BSeg {
     int *valid, *iters;
     const int *active;           // the instance's convergence flag
     int inst;
+    // first workgroup of this segment in a launch over its list, per launch
+    // kind and workgroup size (64, 128, 256, 512): segments are padded to
+    // whole workgroups, so a workgroup finds its segment by binary search
+    unsigned first[6][4];
 };
 
 // Per-instance state of the batched stop test (device arrays).
