@@ -37,7 +37,7 @@ struct pfc_batch {
     unsigned long long *partial = nullptr;
     BState st{};
     int **d_valid = nullptr;
-    int *h_num = nullptr;   // pinned
+    int *h_num = nullptr;   // pinned: the instances' active flags
     int *h_stats = nullptr; // pinned: cycles, status per instance
     double *h_res = nullptr;  // pinned: res0, res per instance
     int tile[4] = {256, 256, 256, 256};
@@ -190,10 +190,11 @@ pfc_status run_step(pfc_batch *B, pfc_step_info *infos_step) {
     }
     for (int guard = 0; guard <= B->cfg.max_cycles + 2; ++guard) {
         e = hipGraphLaunch(B->exec, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(B->h_num, B->st.num_active, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(B->h_num, B->st.active, B->count * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return bfail(B, PFC_ERR_HIP, std::string("batched cycle: ") + hipGetErrorString(e));
-        if (*B->h_num == 0) break;
+        if (std::none_of(B->h_num, B->h_num + B->count, [](int a) { return a != 0; })) break;
     }
     for (int i = 0; i < B->count; ++i) step_end(B->inst[i], B->nxt[i], B->mu[i], B->om[i]);
     const size_t n = (size_t)B->count;
@@ -303,7 +304,7 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
     }
     const size_t n = (size_t)count;
     ok = ok && balloc(B, &B->st.active, n) && balloc(B, &B->st.cycles, n) && balloc(B, &B->st.status, n) &&
-         balloc(B, &B->st.res0, n) && balloc(B, &B->st.res, n) && balloc(B, &B->st.num_active, 1) &&
+         balloc(B, &B->st.res0, n) && balloc(B, &B->st.res, n) &&
          balloc(B, &B->d_valid, n);
     unsigned *nf = nullptr, *nbk = nullptr;
     ok = ok && balloc(B, &nf, n) && balloc(B, &nbk, n);
@@ -365,7 +366,7 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
          hipMemcpy(nf, first.data(), n * sizeof(unsigned), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(nbk, nblk.data(), n * sizeof(unsigned), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(B->d_valid, valids.data(), n * sizeof(int *), hipMemcpyHostToDevice) == hipSuccess &&
-         hipHostMalloc((void **)&B->h_num, sizeof(int), 0) == hipSuccess &&
+         hipHostMalloc((void **)&B->h_num, n * sizeof(int), 0) == hipSuccess &&
          hipHostMalloc((void **)&B->h_stats, 2 * n * sizeof(int), 0) == hipSuccess &&
          hipHostMalloc((void **)&B->h_res, 2 * n * sizeof(double), 0) == hipSuccess;
     if (!ok) {

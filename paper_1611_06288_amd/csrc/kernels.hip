@@ -1147,49 +1147,34 @@ __global__ __launch_bounds__(kBlock) void kb_norm(const BSeg *segs, int nseg,
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
-// Stop test of every instance (one wavefront per instance in turn): residual
+// Stop test of every instance (one workgroup per instance): residual
 // max-norm from its partials, then the rule of the single-instance driver:
 // finished if the norm is at most tol (or not finite, or max_cycles cycles
-// were done), otherwise one more cycle is counted.  Also counts the
-// instances still active.
-__global__ __launch_bounds__(1024) void kb_update(const BSeg *segs, int nseg, const unsigned long long *partial,
-                                                  BState st, double tol, int max_cycles) {
-    __shared__ int live[1024 / 64];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    int mine = 0;
-    for (int s = w; s < nseg; s += nw) {
-        const int i = segs[s].inst;
-        unsigned long long m = 0;
-        for (unsigned b = st.norm_first[s] + lane; b < st.norm_first[s] + st.norm_blocks[s]; b += 64)
-            m = umax(m, partial[b]);
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long o = __shfl_xor(m, off, 64);
-            m = umax(m, o);
-        }
-        if (lane == 0 && st.active[i]) {
-            const double r = __longlong_as_double((long long)m);
-            if (st.cycles[i] == 0) st.res0[i] = r;
-            st.res[i] = r;
-            if (!(r <= 1.7976931348623157e308)) {  // NaN or Inf
-                st.status[i] = PFC_ERR_NONFINITE;
-                st.active[i] = 0;
-            } else if (r <= tol) {
-                st.active[i] = 0;
-            } else if (st.cycles[i] == max_cycles) {
-                st.status[i] = PFC_ERR_NOT_CONVERGED;
-                st.active[i] = 0;
-            } else {
-                st.cycles[i] += 1;
-            }
-        }
-        if (lane == 0 && st.active[i]) ++mine;
-    }
-    if (lane == 0) live[w] = mine;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int tot = 0;
-        for (int q = 0; q < nw; ++q) tot += live[q];
-        *st.num_active = tot;
+// were done), otherwise one more cycle is counted.
+__global__ __launch_bounds__(kBlock) void kb_update(const BSeg *segs, int nseg,
+                                                    const unsigned long long *partial, BState st,
+                                                    double tol, int max_cycles) {
+    const int s = blockIdx.x;
+    if (s >= nseg) return;
+    const int i = segs[s].inst;
+    const unsigned b0 = st.norm_first[s], b1 = b0 + st.norm_blocks[s];
+    unsigned long long m = 0;
+    for (unsigned b = b0 + threadIdx.x; b < b1; b += kBlock) m = umax(m, partial[b]);
+    m = block_max_u64(m);
+    if (threadIdx.x != 0 || !st.active[i]) return;
+    const double r = __longlong_as_double((long long)m);
+    if (st.cycles[i] == 0) st.res0[i] = r;
+    st.res[i] = r;
+    if (!(r <= 1.7976931348623157e308)) {  // NaN or Inf
+        st.status[i] = PFC_ERR_NONFINITE;
+        st.active[i] = 0;
+    } else if (r <= tol) {
+        st.active[i] = 0;
+    } else if (st.cycles[i] == max_cycles) {
+        st.status[i] = PFC_ERR_NOT_CONVERGED;
+        st.active[i] = 0;
+    } else {
+        st.cycles[i] += 1;
     }
 }
 
@@ -1235,7 +1220,7 @@ void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg) {
 void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned blocks,
                        unsigned long long *partial, BState st, double tol, int max_cycles) {
     hipLaunchKernelGGL(kb_norm, dim3(blocks), dim3(kBlock), 0, s, segs, nseg, partial);
-    hipLaunchKernelGGL(kb_update, dim3(1), dim3(1024), 0, s, segs, nseg,
+    hipLaunchKernelGGL(kb_update, dim3(nseg), dim3(kBlock), 0, s, segs, nseg,
                        (const unsigned long long *)partial, st, tol, max_cycles);
 }
 

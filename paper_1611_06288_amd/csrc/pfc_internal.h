@@ -247,7 +247,6 @@ struct BState {
     int *active, *cycles, *status;
     double *res0, *res;
     const unsigned *norm_first, *norm_blocks;  // per finest-level segment
-    int *num_active;
 };
 
 void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned blocks, int block,
