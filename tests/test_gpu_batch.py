@@ -99,3 +99,40 @@ def test_batch_64_instances_uneven():
         assert [x.cycles for x in infos[i]] == [x.cycles for x in sinfos]
         assert float((b.get_state(i)[1] - cur).abs().max()) <= 1e-13 * float(cur.abs().max())
     assert seen == {32, 48, 64, 96}
+
+
+def test_batch_statuses_per_instance():
+    """Per-instance stop tests: with max_cycles = 2 and an unreachable tol
+    every instance ends NOT_CONVERGED after exactly 2 cycles with the
+    single-instance solver's residuals; an instance whose state holds a NaN
+    ends NONFINITE while the others converge as they do alone."""
+    from paper_1611_06288_amd.solver import Batch, Solver
+    ens = small_ensemble()[:4]
+    b = Batch(ens, tol=1e-14, max_cycles=2)
+    for i, p in enumerate(ens):
+        b.init_state(i, dev(p["phi0"]))
+    infos = b.run(1, raise_on_error=False)
+    for i, p in enumerate(ens):
+        x = infos[i][0]
+        assert (x.status, x.cycles) == (2, 2), (i, x)
+        s = Solver(p["n"], p["L"], p["eps"], p["dt"], tol=1e-14, max_cycles=2)
+        phi = dev(p["phi0"])
+        mu, om = s.init_guess(phi)
+        _, y = s.step(phi, phi, mu, om, raise_on_error=False)
+        assert y.status == 2 and y.cycles == 2
+        assert x.res0 == pytest.approx(y.res0, rel=1e-12)
+        assert x.res_final == pytest.approx(y.res_final, rel=1e-9)
+    b2 = Batch(ens, tol=1e-10)
+    for i, p in enumerate(ens):
+        phi = dev(p["phi0"])
+        if i == 1:
+            phi[1, 2, 3] = float("nan")
+        b2.init_state(i, phi)
+    infos = b2.run(1, raise_on_error=False)
+    assert infos[1][0].status == 3
+    for i, p in enumerate(ens):
+        if i == 1:
+            continue
+        s = Solver(p["n"], p["L"], p["eps"], p["dt"], tol=1e-10)
+        _, _, _, _, sinfos = s.simulate(dev(p["phi0"]), 1)
+        assert infos[i][0].status == 0 and infos[i][0].cycles == sinfos[0].cycles, i
