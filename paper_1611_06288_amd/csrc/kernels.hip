@@ -480,12 +480,15 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T>
 // interpolates from in LDS, so each coarse value is fetched a few times per
 // workgroup rather than once per use through the caches.  A thread updates an
 // x-pair in both fine planes.  Same weights and operation order as
-// prolong_body.
+// prolong_body.  phi0 (the cycle's interpolation, followed by a smoothing
+// sweep): at colour-0 points only phi is corrected, since the sweep's colour-0
+// half reads nothing else of a colour-0 point before overwriting it; mu and
+// omega there are neither read nor written.
 constexpr int kPX = 64, kPY = 8;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_tile(Lay LC, Lay LF, Tri<const T> e,
-                                                         Tri<T> fine, const int *gate) {
+                                                         Tri<T> fine, const int *gate, int phi0) {
     __shared__ double ce[3][3][kPY / 2 + 2][kPX / 2 + 2];  // [field][K-1..K+1][Y][X]
     if (gate_closed(gate)) return;
     const int nc = LC.n, nf = LF.n;
@@ -505,8 +508,10 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tile(Lay LC, Lay LF, Tri<con
             const unsigned g = sidx32(LF, x0 + 2 * qx + dx, y, 2 * K + dz);
             fo[dz][dx] = g;
             fv[dz][dx][0] = (double)fine.a[g];
-            fv[dz][dx][1] = (double)fine.b[g];
-            fv[dz][dx][2] = (double)fine.c[g];
+            if (!phi0 || ((dx + y + dz) & 1)) {  // x0, 2 qx and 2 K are even
+                fv[dz][dx][1] = (double)fine.b[g];
+                fv[dz][dx][2] = (double)fine.c[g];
+            }
         }
     constexpr int CW = kPX / 2 + 2, CH = kPY / 2 + 2;
     auto wc = [nc](int v) { return v < 0 ? v + nc : (v >= nc ? v - nc : v); };
@@ -530,15 +535,18 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tile(Lay LC, Lay LF, Tri<con
                 w[xx] = 0.75 * (0.75 * ce[fl][1][cy][cx - 1 + xx] + 0.25 * ce[fl][1][cy1][cx - 1 + xx]) +
                         0.25 * (0.75 * ce[fl][z1][cy][cx - 1 + xx] + 0.25 * ce[fl][z1][cy1][cx - 1 + xx]);
             T *ff = fl == 0 ? fine.a : (fl == 1 ? fine.b : fine.c);
-            ff[fo[dz][0]] = (T)(fv[dz][0][fl] + (0.75 * w[1] + 0.25 * w[0]));
-            ff[fo[dz][1]] = (T)(fv[dz][1][fl] + (0.75 * w[1] + 0.25 * w[2]));
+            const bool c1x0 = ((y + dz) & 1) != 0;  // the pair's even-x point is colour 1
+            if (fl == 0 || !phi0 || c1x0)
+                ff[fo[dz][0]] = (T)(fv[dz][0][fl] + (0.75 * w[1] + 0.25 * w[0]));
+            if (fl == 0 || !phi0 || !c1x0)
+                ff[fo[dz][1]] = (T)(fv[dz][1][fl] + (0.75 * w[1] + 0.25 * w[2]));
         }
     }
 }
 
 template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
-                    Tri<const T> ubar, Tri<T> fine_u, const int *gate) {
+                    Tri<const T> ubar, Tri<T> fine_u, const int *gate, bool phi0) {
     const size_t pairs = (size_t)coarse.n * fine.n * fine.n;
     const bool tile = fine.split && fine.n % kPX == 0 && fine.n % kPY == 0;
     if (ubar.a && fine_u.b && !tile) {
@@ -557,7 +565,7 @@ void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const
         if (tile) {
             const unsigned blocks = (unsigned)((fine.n / kPX) * (fine.n / kPY) * coarse.n);
             hipLaunchKernelGGL((k_prolong_tile<T>), dim3(blocks), dim3(kBlock), 0, s, coarse, fine,
-                               cst(e), fine_u, gate);
+                               cst(e), fine_u, gate, phi0 ? 1 : 0);
         } else {
             hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse,
                                fine, cst(e), Tri<const T>{nullptr, nullptr, nullptr}, fine_u, gate);
@@ -1249,9 +1257,9 @@ PFC_INST(float, true)
 template void launch_restrict<double>(hipStream_t, const Lay &, const Lay &, const double *, double *);
 template void launch_restrict<float>(hipStream_t, const Lay &, const Lay &, const float *, float *);
 template void launch_prolong<double>(hipStream_t, const Lay &, const Lay &, Tri<const double>,
-                                     Tri<const double>, Tri<double>, const int *);
+                                     Tri<const double>, Tri<double>, const int *, bool);
 template void launch_prolong<float>(hipStream_t, const Lay &, const Lay &, Tri<const float>,
-                                    Tri<const float>, Tri<float>, const int *);
+                                    Tri<const float>, Tri<float>, const int *, bool);
 template void launch_to_lay<double, double>(hipStream_t, const Lay &, const double *, double *, int);
 template void launch_from_lay<double, double>(hipStream_t, const Lay &, const double *, double *, int);
 template void launch_to_lay<double, float>(hipStream_t, const Lay &, const double *, float *, int);

@@ -99,7 +99,8 @@ static void cycle32(pfc_handle *H, int l, bool fcycle) {
     cycle32(H, l + 1, fcycle);
     if (fcycle) cycle32(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
-    launch_prolong<float>(H->stream, LB, H->lev[l].lay, cst(B.e), cst(B.ebar), A.e);
+    launch_prolong<float>(H->stream, LB, H->lev[l].lay, cst(B.e), cst(B.ebar), A.e, nullptr,
+                          H->cfg.nu2 >= 1);
     H->end_timed();
     for (int s = 0; s < H->cfg.nu2; ++s) sweep32(H, l);
 }
@@ -257,7 +258,13 @@ double algorithmic_bytes(const pfc_handle *H, int kernel) {
     switch (kernel) {
         case PFC_KERNEL_SMOOTH0: return smooth * P;
         case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0 + mob) * P;
-        case PFC_KERNEL_PROLONG0: return (mixed ? 27.0 : 54.0) * P;
+        // interpolation: u read and written where it is live after it (all
+        // phi, colour-1 mu and omega: 2 x 2 fields' worth when a post-sweep
+        // follows, else all three), plus the coarse error and its computation
+        case PFC_KERNEL_PROLONG0: {
+            const double fine = H->cfg.nu2 >= 1 ? 2.0 : 3.0;
+            return (mixed ? 2 * 4.0 * fine + 3.0 : 2 * 8.0 * fine + 6.0) * P;
+        }
         case PFC_KERNEL_NORM0: return (mixed ? (H->lev[0].rt ? 108.0 : 72.0) : 56.0 + mob) * P;
         // the fused sweep's 72 plus old mu and omega of the colour-0 points
         case PFC_KERNEL_SWEEP_NORM0: return H->split_norm ? 80.0 * P : 0.0;

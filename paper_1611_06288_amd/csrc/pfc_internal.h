@@ -145,9 +145,13 @@ void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f,
                 const T *phk, const T *base);
 
 // fine += P (v - ubar); ubar.a may be null; fine.b null: one field only.
+// phi0: a smoothing sweep follows, so mu and omega at colour-0 points may be
+// left uncorrected (they are dead until the sweep overwrites them); the tiled
+// levels skip them, the others correct everything.
 template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
-                    Tri<const T> ubar, Tri<T> fine_u, const int *gate = nullptr);
+                    Tri<const T> ubar, Tri<T> fine_u, const int *gate = nullptr,
+                    bool phi0 = false);
 
 // Residual r = f - N(u) (r.a may be null) and per-block maxima of |r| as
 // IEEE bit patterns; returns the number of partials written.

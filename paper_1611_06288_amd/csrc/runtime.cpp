@@ -272,7 +272,8 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
     cycle64(H, l + 1, fcycle);
     if (fcycle) cycle64(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
-    launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u, H->gate);
+    launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u, H->gate,
+                           H->cfg.nu2 >= 1);
     H->end_timed();
     for (int s = 0; s < H->cfg.nu2; ++s)
         sweep64(H, l, (flags & kCyclePostNorm) && s == H->cfg.nu2 - 1 ? 2 : 0);
