@@ -336,7 +336,8 @@ void launch_restrict(hipStream_t s, const Lay &fine, const Lay &coarse, const T 
 // ------------------------------------------------------- tau correction
 //
 // Coarse right-hand side of the FAS: f_c = N_c(I u) + I r (f holds I r on
-// entry); also starts the coarse iterate at I u.
+// entry); also starts the coarse iterate at I u, unless u.a is null (a fused
+// coarse level whose first sweep reads I u directly).
 template <typename T, bool DELTA, bool MOB = false>
 __device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                                          const T *__restrict__ phk, const T *__restrict__ base,
@@ -370,9 +371,11 @@ __device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, 
     f.a[t] = (T)((double)f.a[t] + n1);
     f.b[t] = (T)((double)f.b[t] + n2);
     f.c[t] = (T)((double)f.c[t] + n3);
-    u.a[t] = ubar.a[t];
-    u.b[t] = ubar.b[t];
-    u.c[t] = ubar.c[t];
+    if (u.a) {
+        u.a[t] = ubar.a[t];
+        u.b[t] = ubar.b[t];
+        u.c[t] = ubar.c[t];
+    }
 }
 
 template <typename T, bool DELTA, bool MOB>

@@ -212,7 +212,7 @@ pfc_handle::~pfc_handle() {
 
 namespace pfc {
 
-void sweep64(pfc_handle *H, int l, int nrm) {
+void sweep64(pfc_handle *H, int l, int nrm, bool from_ubar) {
     Level &A = H->lev[l];
     const OpParams op = op_of(H, l);
     if (A.fused) {  // one pass, then the two iterate buffers trade places
@@ -221,7 +221,8 @@ void sweep64(pfc_handle *H, int l, int nrm) {
             nrm == 1 ? H->partial : (nrm == 2 ? H->partial + H->split_blocks : nullptr);
         H->begin_timed(nrm == 1 ? PFC_KERNEL_SWEEP_NORM0 : PFC_KERNEL_SMOOTH0, l);
         launch_sweep_fused<double, false>(H->stream, op, H->cfg.lin == PFC_LIN_PICARD, A.nz,
-                                          cst(A.u), A.u2, cst(A.f), A.phk, nullptr, nrm, part);
+                                          from_ubar ? cst(A.ubar) : cst(A.u), A.u2, cst(A.f), A.phk,
+                                          nullptr, nrm, part);
         H->end_timed();
         std::swap(A.u, A.u2);
         return;
@@ -252,7 +253,8 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
         return;
     }
     Level &B = H->lev[l + 1];
-    for (int s = (flags & kCyclePreDone) ? 1 : 0; s < H->cfg.nu1; ++s) sweep64(H, l);
+    for (int s = (flags & kCyclePreDone) ? 1 : 0; s < H->cfg.nu1; ++s)
+        sweep64(H, l, 0, s == 0 && (flags & kCycleFromUbar));
     H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
     if (A.rt) {
         ResidTileArgs ra;
@@ -268,8 +270,13 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
                                              A.phk, nullptr, B.ubar, B.f);
     }
     H->end_timed();
-    launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f, B.u, B.phk, nullptr);
-    cycle64(H, l + 1, fcycle);
+    // a fused coarse level with pre-sweeps starts from I u where the
+    // restriction left it, so tau writes no copy into B.u
+    const bool from_ubar = B.fused && H->cfg.nu1 >= 1;
+    launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f,
+                              from_ubar ? Tri<double>{nullptr, nullptr, nullptr} : B.u, B.phk,
+                              nullptr);
+    cycle64(H, l + 1, fcycle, from_ubar ? kCycleFromUbar : 0u);
     if (fcycle) cycle64(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
     launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u, H->gate,

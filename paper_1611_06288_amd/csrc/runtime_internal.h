@@ -112,9 +112,12 @@ OpParams op_of(const pfc_handle *H, int l);
 // flags of cycle64 at the finest level
 constexpr unsigned kCyclePreDone = 1;   // its first pre-sweep has already run (sweep64 nrm 1)
 constexpr unsigned kCyclePostNorm = 2;  // its last post-sweep leaves the colour-1 norm half
+constexpr unsigned kCycleFromUbar = 4;  // (fused level) the iterate is still in ubar: the
+                                        // first pre-sweep reads it there
 void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags = 0);
-// One smoothing sweep of level l; nrm as in launch_sweep_fused (split_norm only).
-void sweep64(pfc_handle *H, int l, int nrm = 0);
+// One smoothing sweep of level l; nrm as in launch_sweep_fused (split_norm
+// only); from_ubar: a fused sweep reading its input from the level's ubar.
+void sweep64(pfc_handle *H, int l, int nrm = 0, bool from_ubar = false);
 void restrict_phk(pfc_handle *H);
 pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out);
 int enqueue_norm64(pfc_handle *H, unsigned long long *dst = nullptr);
