@@ -33,12 +33,14 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic of one finest-level FP64 smoother launch at 256^3, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, averaged over
-# the step's 256^3 launches) scaled by what the same counters read for a 1 GiB
-# device copy (FETCH x 2.0, WRITE x 1.0).  Valid only for the smoother sources
+# the step's 256^3 launches of the sweeps the smoother timing covers: plain,
+# plain without the dead colour-0 writes, and norm-carrying post-sweeps) scaled
+# by what the same counters read for a 1 GiB device copy (FETCH x 2.0,
+# WRITE x 1.0).  Valid only for the smoother sources
 # it was measured on (first 16 hex digits of the sha256 of smooth.hip, smooth.h
 # and device_common.h, concatenated); otherwise reported null.
-SMOOTHER_TRAFFIC = {"sources_sha256_16": "a1a9808ce48067c0", "n": 256,
-                    "fetch_KiB": 466280, "write_KiB": 395528,
+SMOOTHER_TRAFFIC = {"sources_sha256_16": "25fb4c7b1c55abd5", "n": 256,
+                    "fetch_KiB": 455015, "write_KiB": 350799,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 SMOOTHER_SOURCES = ("smooth.hip", "smooth.h", "device_common.h")
 METRIC = "time-steps/s & V-cycles/s at 256^3 (FP64 vs mixed); smoother HBM GB/s %peak"
@@ -441,7 +443,8 @@ def main():
     sm = fp64["kernels"].get("smooth0", {})
     achieved = sm.get("achieved_GBps")
     roofline = {
-        "kernel": "finest-level fused red-black sweep (one full sweep per launch, 72 B/pt)",
+        "kernel": ("finest-level fused red-black sweep (one full sweep per launch; 72 B/pt, 64 "
+                   "where the next sweep makes colour-0 mu, omega dead; mean over launches)"),
         "bound": "hbm",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,

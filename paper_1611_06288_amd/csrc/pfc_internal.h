@@ -93,10 +93,12 @@ void launch_sweep_small(hipStream_t s, const OpParams &op, int picard, Tri<T> u,
 // for double only.  nrm (M = 1 only) adds half of the stop-test norm as
 // per-workgroup maxima of |S - N(u)| bits in part[0 .. fused_blocks(n, nz)):
 // 1 over the colour-0 points of uin, 2 over the colour-1 points of uout.
+// skip0: mu and omega of colour-0 points are not written to uout (only when
+// the next operation on uout is another fused sweep, which does not read them).
 template <typename T, bool DELTA>
 void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
                         Tri<T> uout, Tri<const T> f, const T *phk, const T *base, int nrm = 0,
-                        unsigned long long *part = nullptr);
+                        unsigned long long *part = nullptr, bool skip0 = false);
 int fused_blocks(int n, int nz);  // workgroups of one fused-sweep launch
 bool fused_fits(int n);           // n admits the fused sweep's column tiling
 int fused_slots(int device, bool mob = false);      // resident fused-sweep workgroups on the device (0 on error)

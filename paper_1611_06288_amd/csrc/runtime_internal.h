@@ -45,6 +45,7 @@ struct Level32 {
 struct TimedLaunch {
     int kind;
     hipEvent_t a, b;
+    double bytes;  // the launch's algorithmic HBM bytes
 };
 
 bool level_sizes(int n, std::vector<int> &out);
@@ -100,8 +101,10 @@ struct pfc_handle {
     std::vector<hipEvent_t> pool;
     int64_t t_count[PFC_KERNEL_COUNT] = {};
     double t_ms[PFC_KERNEL_COUNT] = {};
+    double t_bytes[PFC_KERNEL_COUNT] = {};
 
-    void begin_timed(int kind, int level);
+    // bytes < 0: the kind's algorithmic bytes per finest-level launch
+    void begin_timed(int kind, int level, double bytes = -1.0);
     void end_timed();
     void collect_timings();
     ~pfc_handle();
@@ -116,8 +119,10 @@ constexpr unsigned kCycleFromUbar = 4;  // (fused level) the iterate is still in
                                         // first pre-sweep reads it there
 void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags = 0);
 // One smoothing sweep of level l; nrm as in launch_sweep_fused (split_norm
-// only); from_ubar: a fused sweep reading its input from the level's ubar.
-void sweep64(pfc_handle *H, int l, int nrm = 0, bool from_ubar = false);
+// only); from_ubar: a fused sweep reading its input from the level's ubar;
+// then_sweep: the next operation on the iterate is another sweep of this
+// level (a fused sweep then leaves the dead colour-0 mu, omega unwritten).
+void sweep64(pfc_handle *H, int l, int nrm = 0, bool from_ubar = false, bool then_sweep = false);
 void restrict_phk(pfc_handle *H);
 pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out);
 int enqueue_norm64(pfc_handle *H, unsigned long long *dst = nullptr);

@@ -109,6 +109,9 @@ template void launch_sweep_small<float, true>(hipStream_t, const OpParams &, int
 // The neighbour sums are taken in the residual kernels' order and the
 // residual is formed by the same function, so the two halves together give
 // bitwise the norm of the residual kernels.
+// skip0: the new mu and omega of colour-0 points are not written (the next
+// operation on this iterate is another fused sweep, which reads only phi of
+// a colour-0 point; the colour-1 phase takes them from LDS).
 constexpr int kFX = 64, kFY = 8, kFT = 256;  // column extents, threads per workgroup
 constexpr int kFSl = kFX / 2 + 1;            // colour-0 ring: points per row
 constexpr int kFRw = kFY + 2;                //                rows
@@ -123,7 +126,8 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
     OpParams op, int picard, int nz, const T *__restrict__ ua, const T *__restrict__ ub,
     const T *__restrict__ uc, T *__restrict__ oa, T *__restrict__ ob, T *__restrict__ oc,
     const T *__restrict__ fa, const T *__restrict__ fb, const T *__restrict__ fc,
-    const T *__restrict__ phk, const T *__restrict__ base, unsigned long long *__restrict__ part) {
+    const T *__restrict__ phk, const T *__restrict__ base, unsigned long long *__restrict__ part,
+    int skip0) {
     static_assert(NRM == 0 || (!DELTA && !MOB), "stop-test halves: FP64 sweeps with M = 1");
     constexpr int NF = MOB ? 4 : 3;         // ring fields: phi, mu, omega (, phi*)
     __shared__ T c1[NF][3][kFCr][kFCs];   // [field][plane slot][row][point] old colour 1
@@ -293,8 +297,10 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                 red[2][rq][r][sl] = tom;
                 if (in_box(x, y, k)) {
                     oa[rg[i]] = tphi;
-                    ob[rg[i]] = tmu;
-                    oc[rg[i]] = tom;
+                    if (!skip0) {
+                        ob[rg[i]] = tmu;
+                        oc[rg[i]] = tom;
+                    }
                     if constexpr (NRM == 1) {  // residual of the input at this point
                         const double p0 = (double)ro[i][0], m0 = (double)rmo[i][0],
                                      w0 = (double)rmo[i][1];
@@ -421,32 +427,33 @@ int fused_blocks(int n, int nz) { return (n / kFX) * (n / kFY) * nz; }
 template <typename T, bool DELTA>
 void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
                         Tri<T> uout, Tri<const T> f, const T *phk, const T *base, int nrm,
-                        unsigned long long *part) {
+                        unsigned long long *part, bool skip0) {
+    const int sk = skip0 ? 1 : 0;
     const int n = op.lay.n;
     const unsigned blocks = (unsigned)fused_blocks(n, nz);
     if constexpr (!DELTA) {
         if (op.mob.phs) {  // variable mobility
             hipLaunchKernelGGL((k_sweep_fused<T, false, true, 0>), dim3(blocks), dim3(kFT), 0, s,
                                op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
-                               f.b, f.c, phk, base, nullptr);
+                               f.b, f.c, phk, base, nullptr, sk);
             return;
         }
         if (nrm == 1) {
             hipLaunchKernelGGL((k_sweep_fused<T, false, false, 1>), dim3(blocks), dim3(kFT), 0, s,
                                op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
-                               f.b, f.c, phk, base, part);
+                               f.b, f.c, phk, base, part, sk);
             return;
         }
         if (nrm == 2) {
             hipLaunchKernelGGL((k_sweep_fused<T, false, false, 2>), dim3(blocks), dim3(kFT), 0, s,
                                op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
-                               f.b, f.c, phk, base, part);
+                               f.b, f.c, phk, base, part, sk);
             return;
         }
     }
     hipLaunchKernelGGL((k_sweep_fused<T, DELTA, false, 0>), dim3(blocks), dim3(kFT), 0, s, op,
                        picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b, f.c, phk,
-                       base, nullptr);
+                       base, nullptr, sk);
 }
 
 template void launch_smooth<double, false>(hipStream_t, const OpParams &, int, int, Tri<double>,
@@ -456,6 +463,6 @@ template void launch_smooth<float, true>(hipStream_t, const OpParams &, int, int
 template void launch_sweep_fused<double, false>(hipStream_t, const OpParams &, int, int,
                                                 Tri<const double>, Tri<double>, Tri<const double>,
                                                 const double *, const double *, int,
-                                                unsigned long long *);
+                                                unsigned long long *, bool);
 
 }  // namespace pfc
