@@ -464,117 +464,173 @@ __device__ __forceinline__ void coarse_err_body(size_t P, Tri<const T> v, Tri<T>
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarse_err(size_t P, Tri<const T> v, Tri<T> ubar,
-                                                       const int *gate) {
-    if (gate_closed(gate)) return;
-    coarse_err_body<T>(P, v, ubar, xcd_block() * kBlock + threadIdx.x);
-}
-
-template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T> v, Tri<const T> ubar,
                                                     Tri<T> fine, const int *gate) {
     if (gate_closed(gate)) return;
     prolong_body<T>(LC, LF, v, ubar, fine, xcd_block() * kBlock + threadIdx.x);
 }
 
-// Tiled form for colour-split fine levels with n a multiple of 64, on the
-// precomputed coarse error e: a workgroup owns a 64 x 8 x 2 block of fine
-// cells (coarse plane K) and stages the (32+2) x (4+2) x 3 coarse cells it
-// interpolates from in LDS, so each coarse value is fetched a few times per
-// workgroup rather than once per use through the caches.  A thread updates an
-// x-pair in both fine planes.  Same weights and operation order as
-// prolong_body.  phi0 (the cycle's interpolation, followed by a smoothing
-// sweep): at colour-0 points only phi is corrected, since the sweep's colour-0
-// half reads nothing else of a colour-0 point before overwriting it; mu and
-// omega there are neither read nor written.
+// Tiled form for colour-split fine levels with n a multiple of 64: a
+// workgroup owns a 64 x 8 fine column and a range of coarse planes, and walks
+// it in z.  The coarse error e = v - ubar (rounded to T, the value
+// coarse_err_body stores) of three coarse planes, (32+2) x (4+2) cells each,
+// sits in an LDS ring; the next coarse plane and the next plane pair's fine
+// values are loaded into registers while the current pair is computed, so
+// each coarse value is fetched about once per column and the load latency
+// overlaps the arithmetic.  A thread updates an x-pair in both fine planes of
+// a coarse plane K.  Same weights and operation order as prolong_body.  phi0
+// (the cycle's interpolation, followed by a smoothing sweep): at colour-0
+// points only phi is corrected, since the sweep's colour-0 half reads nothing
+// else of a colour-0 point before overwriting it; mu and omega there are
+// neither read nor written.
 constexpr int kPX = 64, kPY = 8;
+constexpr int kPCW = kPX / 2 + 2, kPCH = kPY / 2 + 2, kPCN = kPCW * kPCH;  // coarse ring plane
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong_tile(Lay LC, Lay LF, Tri<const T> e,
-                                                         Tri<T> fine, const int *gate, int phi0) {
-    __shared__ double ce[3][3][kPY / 2 + 2][kPX / 2 + 2];  // [field][K-1..K+1][Y][X]
+__global__ __launch_bounds__(kBlock) void k_prolong_tile(Lay LC, Lay LF, Tri<const T> v,
+                                                         Tri<const T> ubar, Tri<T> fine,
+                                                         const int *gate, int phi0, int nzr) {
+    static_assert(kPCN <= kBlock, "one coarse ring cell per thread");
+    __shared__ double ce[3][3][kPCH][kPCW];  // [field][plane slot][Y][X]
     if (gate_closed(gate)) return;
     const int nc = LC.n, nf = LF.n;
     const int nbx = nf / kPX, nby = nf / kPY;
     const int b = (int)xcd_block();
-    const int bx = b % nbx, by = (b / nbx) % nby, K = b / (nbx * nby);
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int x0 = bx * kPX, y0 = by * kPY, X0 = x0 / 2, Y0 = y0 / 2;
+    const int K0 = bz * nc / nzr, K1 = (bz + 1) * nc / nzr;
     const int tid = threadIdx.x, qx = tid & 31, qy = tid >> 5;
     const int y = y0 + qy;
-    // the thread's fine values first (independent of the coarse block)
-    double fv[2][2][3];  // [dz][dx][field]
-    unsigned fo[2][2];
-#pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-            const unsigned g = sidx32(LF, x0 + 2 * qx + dx, y, 2 * K + dz);
-            fo[dz][dx] = g;
-            fv[dz][dx][0] = (double)fine.a[g];
-            if (!phi0 || ((dx + y + dz) & 1)) {  // x0, 2 qx and 2 K are even
-                fv[dz][dx][1] = (double)fine.b[g];
-                fv[dz][dx][2] = (double)fine.c[g];
+    auto wc = [nc](int q) { return q < 0 ? q + nc : (q >= nc ? q - nc : q); };
+    auto slot = [K0](int P) { return (P - K0 + 4) % 3; };  // P >= K0 - 1
+    // this thread's coarse ring cell and its error on plane P
+    const int cpy = tid / kPCW, cpx = tid - cpy * kPCW;
+    T cn[3];
+    auto load_coarse = [&](int P) {
+        if (tid < kPCN) {
+            const unsigned g = sidx32(LC, wc(X0 - 1 + cpx), wc(Y0 - 1 + cpy), wc(P));
+            if (ubar.a) {
+                cn[0] = (T)((double)v.a[g] - (double)ubar.a[g]);
+                cn[1] = (T)((double)v.b[g] - (double)ubar.b[g]);
+                cn[2] = (T)((double)v.c[g] - (double)ubar.c[g]);
+            } else {
+                cn[0] = v.a[g];
+                cn[1] = v.b[g];
+                cn[2] = v.c[g];
             }
         }
-    constexpr int CW = kPX / 2 + 2, CH = kPY / 2 + 2;
-    auto wc = [nc](int v) { return v < 0 ? v + nc : (v >= nc ? v - nc : v); };
-    for (int c = tid; c < 3 * CH * CW; c += kBlock) {
-        const int pz = c / (CH * CW), rem = c - pz * (CH * CW), py = rem / CW, px = rem - py * CW;
-        const unsigned g = sidx32(LC, wc(X0 - 1 + px), wc(Y0 - 1 + py), wc(K - 1 + pz));
-        ce[0][pz][py][px] = (double)e.a[g];
-        ce[1][pz][py][px] = (double)e.b[g];
-        ce[2][pz][py][px] = (double)e.c[g];
-    }
+    };
+    auto store_coarse = [&](int P) {
+        if (tid < kPCN) {
+            const int s = slot(P);
+            ce[0][s][cpy][cpx] = (double)cn[0];
+            ce[1][s][cpy][cpx] = (double)cn[1];
+            ce[2][s][cpy][cpx] = (double)cn[2];
+        }
+    };
+    // the thread's fine values of the plane pair 2K, 2K + 1
+    T fv[2][2][3];  // [dz][dx][field]
+    auto load_fine = [&](int K, T (&o)[2][2][3]) {
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const unsigned g = sidx32(LF, x0 + 2 * qx + dx, y, 2 * K + dz);
+                o[dz][dx][0] = fine.a[g];
+                if (!phi0 || ((dx + y + dz) & 1)) {  // x0, 2 qx and 2 K are even
+                    o[dz][dx][1] = fine.b[g];
+                    o[dz][dx][2] = fine.c[g];
+                }
+            }
+    };
+    load_coarse(K0 - 1);
+    store_coarse(K0 - 1);
+    load_coarse(K0);
+    store_coarse(K0);
+    load_coarse(K0 + 1);
+    load_fine(K0, fv);
+    store_coarse(K0 + 1);
     __syncthreads();
     const int cy = (y >> 1) - Y0 + 1, cy1 = (y & 1) ? cy + 1 : cy - 1, cx = qx + 1;
+    for (int K = K0; K < K1; ++K) {
+        T fn[2][2][3];
+        if (K + 1 < K1) {
+            load_coarse(K + 2);
+            load_fine(K + 1, fn);
+        }
+        const int s1 = slot(K);
 #pragma unroll
-    for (int dz = 0; dz < 2; ++dz) {
-        const int z1 = dz ? 2 : 0;  // plane K-1 for fine plane 2K, K+1 for 2K+1
+        for (int dz = 0; dz < 2; ++dz) {
+            const int sz = slot(dz ? K + 1 : K - 1);  // plane K-1 for fine plane 2K, K+1 for 2K+1
 #pragma unroll
-        for (int fl = 0; fl < 3; ++fl) {
-            double w[3];  // y/z-interpolated values at X-1, X, X+1
+            for (int fl = 0; fl < 3; ++fl) {
+                double w[3];  // y/z-interpolated values at X-1, X, X+1
 #pragma unroll
-            for (int xx = 0; xx < 3; ++xx)
-                w[xx] = 0.75 * (0.75 * ce[fl][1][cy][cx - 1 + xx] + 0.25 * ce[fl][1][cy1][cx - 1 + xx]) +
-                        0.25 * (0.75 * ce[fl][z1][cy][cx - 1 + xx] + 0.25 * ce[fl][z1][cy1][cx - 1 + xx]);
-            T *ff = fl == 0 ? fine.a : (fl == 1 ? fine.b : fine.c);
-            const bool c1x0 = ((y + dz) & 1) != 0;  // the pair's even-x point is colour 1
-            if (fl == 0 || !phi0 || c1x0)
-                ff[fo[dz][0]] = (T)(fv[dz][0][fl] + (0.75 * w[1] + 0.25 * w[0]));
-            if (fl == 0 || !phi0 || !c1x0)
-                ff[fo[dz][1]] = (T)(fv[dz][1][fl] + (0.75 * w[1] + 0.25 * w[2]));
+                for (int xx = 0; xx < 3; ++xx)
+                    w[xx] = 0.75 * (0.75 * ce[fl][s1][cy][cx - 1 + xx] +
+                                    0.25 * ce[fl][s1][cy1][cx - 1 + xx]) +
+                            0.25 * (0.75 * ce[fl][sz][cy][cx - 1 + xx] +
+                                    0.25 * ce[fl][sz][cy1][cx - 1 + xx]);
+                T *ff = fl == 0 ? fine.a : (fl == 1 ? fine.b : fine.c);
+                const bool c1x0 = ((y + dz) & 1) != 0;  // the pair's even-x point is colour 1
+                const unsigned g0 = sidx32(LF, x0 + 2 * qx, y, 2 * K + dz);
+                const unsigned g1 = sidx32(LF, x0 + 2 * qx + 1, y, 2 * K + dz);
+                if (fl == 0 || !phi0 || c1x0)
+                    ff[g0] = (T)((double)fv[dz][0][fl] + (0.75 * w[1] + 0.25 * w[0]));
+                if (fl == 0 || !phi0 || !c1x0)
+                    ff[g1] = (T)((double)fv[dz][1][fl] + (0.75 * w[1] + 0.25 * w[2]));
+            }
+        }
+        if (K + 1 < K1) {
+            __syncthreads();  // plane K-1's slot is free
+            store_coarse(K + 2);
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx)
+#pragma unroll
+                    for (int fl = 0; fl < 3; ++fl) fv[dz][dx][fl] = fn[dz][dx][fl];
+            __syncthreads();
         }
     }
 }
 
+// Resident workgroups of the tiled interpolation on `device` (0 if the query
+// fails), for T = double and float.
+int prolong_tile_slots(int device, bool fp32) {
+    int occ = 0, cus = 0;
+    const void *fn = fp32 ? (const void *)k_prolong_tile<float> : (const void *)k_prolong_tile<double>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kBlock, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    return occ * cus;
+}
+
+// Coarse-plane ranges per column of the tiled interpolation: one resident
+// wave of workgroups (a partly filled second wave costs as much as a full
+// one), at most one workgroup per coarse plane of a column.
+int prolong_tile_nzr(int slots, int nc, int nf) {
+    if (nf % kPX != 0 || nf % kPY != 0) return 1;  // no tiled interpolation onto this level
+    const int cols = (nf / kPX) * (nf / kPY);
+    const int want = slots > 0 ? std::max(1, slots / cols) : 8;
+    return std::max(1, std::min(want, nc));
+}
+
 template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
-                    Tri<const T> ubar, Tri<T> fine_u, const int *gate, bool phi0) {
+                    Tri<const T> ubar, Tri<T> fine_u, const int *gate, bool phi0, int nzr) {
     const size_t pairs = (size_t)coarse.n * fine.n * fine.n;
     const bool tile = fine.split && fine.n % kPX == 0 && fine.n % kPY == 0;
-    if (ubar.a && fine_u.b && !tile) {
-        // small levels: one launch that forms v - ubar where it reads it
-        // (the same value the separate coarse-error pass would store)
-        hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine,
-                           v, ubar, fine_u, gate);
+    if (fine_u.b && tile) {
+        // coarse error formed while its planes are staged (the value the
+        // separate coarse-error pass would store); ubar is left as it is
+        if (nzr <= 0) nzr = prolong_tile_nzr(0, coarse.n, fine.n);
+        const unsigned blocks = (unsigned)((fine.n / kPX) * (fine.n / kPY) * nzr);
+        hipLaunchKernelGGL((k_prolong_tile<T>), dim3(blocks), dim3(kBlock), 0, s, coarse, fine, v,
+                           ubar, fine_u, gate, phi0 ? 1 : 0, nzr);
         return;
     }
-    if (ubar.a && fine_u.b) {
-        // e = v - ubar once on the coarse level (in place of ubar), so the
-        // fine-level pass loads one coarse array instead of two
-        Tri<T> e{const_cast<T *>(ubar.a), const_cast<T *>(ubar.b), const_cast<T *>(ubar.c)};
-        hipLaunchKernelGGL((k_coarse_err<T>), dim3(blocks_for(npts_host(coarse))), dim3(kBlock), 0, s,
-                           npts_host(coarse), v, e, gate);
-        if (tile) {
-            const unsigned blocks = (unsigned)((fine.n / kPX) * (fine.n / kPY) * coarse.n);
-            hipLaunchKernelGGL((k_prolong_tile<T>), dim3(blocks), dim3(kBlock), 0, s, coarse, fine,
-                               cst(e), fine_u, gate, phi0 ? 1 : 0);
-        } else {
-            hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse,
-                               fine, cst(e), Tri<const T>{nullptr, nullptr, nullptr}, fine_u, gate);
-        }
-        return;
-    }
+    // thread per fine pair; with ubar it forms v - ubar where it reads it
     hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine, v,
                        ubar, fine_u, gate);
 }
@@ -1260,9 +1316,9 @@ PFC_INST(float, true)
 template void launch_restrict<double>(hipStream_t, const Lay &, const Lay &, const double *, double *);
 template void launch_restrict<float>(hipStream_t, const Lay &, const Lay &, const float *, float *);
 template void launch_prolong<double>(hipStream_t, const Lay &, const Lay &, Tri<const double>,
-                                     Tri<const double>, Tri<double>, const int *, bool);
+                                     Tri<const double>, Tri<double>, const int *, bool, int);
 template void launch_prolong<float>(hipStream_t, const Lay &, const Lay &, Tri<const float>,
-                                    Tri<const float>, Tri<float>, const int *, bool);
+                                    Tri<const float>, Tri<float>, const int *, bool, int);
 template void launch_to_lay<double, double>(hipStream_t, const Lay &, const double *, double *, int);
 template void launch_from_lay<double, double>(hipStream_t, const Lay &, const double *, double *, int);
 template void launch_to_lay<double, float>(hipStream_t, const Lay &, const double *, float *, int);

@@ -100,7 +100,7 @@ static void cycle32(pfc_handle *H, int l, bool fcycle) {
     if (fcycle) cycle32(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
     launch_prolong<float>(H->stream, LB, H->lev[l].lay, cst(B.e), cst(B.ebar), A.e, nullptr,
-                          H->cfg.nu2 >= 1);
+                          H->cfg.nu2 >= 1, H->lev[l].pz[1]);
     H->end_timed();
     for (int s = 0; s < H->cfg.nu2; ++s) sweep32(H, l);
 }
@@ -260,7 +260,8 @@ double algorithmic_bytes(const pfc_handle *H, int kernel) {
         case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0 + mob) * P;
         // interpolation: u read and written where it is live after it (all
         // phi, colour-1 mu and omega: 2 x 2 fields' worth when a post-sweep
-        // follows, else all three), plus the coarse error and its computation
+        // follows, else all three), plus the coarse v and ubar it forms the
+        // error from (3 fields each, an eighth of the points)
         case PFC_KERNEL_PROLONG0: {
             const double fine = H->cfg.nu2 >= 1 ? 2.0 : 3.0;
             return (mixed ? 2 * 4.0 * fine + 3.0 : 2 * 8.0 * fine + 6.0) * P;

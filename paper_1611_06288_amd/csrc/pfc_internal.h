@@ -153,7 +153,9 @@ void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f,
 template <typename T>
 void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const T> v,
                     Tri<const T> ubar, Tri<T> fine_u, const int *gate = nullptr,
-                    bool phi0 = false);
+                    bool phi0 = false, int nzr = 0);
+int prolong_tile_slots(int device, bool fp32);  // resident workgroups (0 on error)
+int prolong_tile_nzr(int slots, int nc, int nf);  // coarse-plane ranges per column
 
 // Residual r = f - N(u) (r.a may be null) and per-block maxima of |r| as
 // IEEE bit patterns; returns the number of partials written.

@@ -284,7 +284,7 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
     if (fcycle) cycle64(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
     launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u, H->gate,
-                           H->cfg.nu2 >= 1);
+                           H->cfg.nu2 >= 1, A.pz[0]);
     H->end_timed();
     for (int s = 0; s < H->cfg.nu2; ++s)
         sweep64(H, l, (flags & kCyclePostNorm) && s == H->cfg.nu2 - 1 ? 2 : 0, false,
@@ -430,6 +430,7 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
     const int slots = fused_slots(device, mob);
     int rt_slots[RT_MODES];
     for (int m = 0; m < RT_MODES; ++m) rt_slots[m] = resid_tile_slots(device, m, mob);
+    const int pt_slots[2] = {prolong_tile_slots(device, false), prolong_tile_slots(device, true)};
     bool ok = true;
     for (int l = 0; l < H->nlev && ok; ++l) {
         Level &A = H->lev[l];
@@ -448,6 +449,8 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
         A.ubar = Tri<double>{ub, ub + A.P, ub + 2 * A.P};
         A.rt = resid_tile_fits(A.lay);
         for (int m = 0; m < RT_MODES; ++m) A.rt_nz[m] = resid_tile_nz(A.n, rt_slots[m], m);
+        if (l + 1 < H->nlev)
+            for (int t = 0; t < 2; ++t) A.pz[t] = prolong_tile_nzr(pt_slots[t], A.n / 2, A.n);
         A.fused = l < H->nlev - 1 && fused_fits(A.n);
         if (A.fused || (l == 0 && A.rt)) {
             A.nz = fused_nz(A.n, slots);
@@ -752,7 +755,7 @@ pfc_status pfc_prolong_add(pfc_handle *h, int32_t level, const double *coarse_v,
     const Tri<const double> none{nullptr, nullptr, nullptr};
     if (ncomp == 3) {
         launch_prolong<double>(h->stream, B.lay, A.lay, cst(B.u), coarse_ubar ? cst(B.ubar) : none,
-                               A.u);
+                               A.u, nullptr, false, A.pz[0]);
     } else {
         launch_prolong<double>(h->stream, B.lay, A.lay, Tri<const double>{B.u.a, nullptr, nullptr},
                                Tri<const double>{coarse_ubar ? B.ubar.a : nullptr, nullptr, nullptr},

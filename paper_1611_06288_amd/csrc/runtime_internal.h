@@ -31,6 +31,7 @@ struct Level {
     int nz = 1;                                   // its plane ranges per column
     bool rt = false;                              // residuals by column tiles
     int rt_nz[RT_MODES] = {1, 1, 1, 1, 1};        // their plane ranges, per epilogue
+    int pz[2] = {0, 0};  // plane ranges of the tiled interpolation onto this level (FP64, FP32)
 };
 
 // One level of the FP32 correction cycle of the mixed-precision form.

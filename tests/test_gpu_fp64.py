@@ -155,10 +155,12 @@ def test_transfers(n, level):
     assert rel(host(od), cfas.prolong_add(v[0], one)) < KERNEL_RTOL
 
 
-# Interpolation of a coarse error onto fine levels with n % 64 == 0 runs the
-# LDS-tiled kernel; with the error passed directly (no ubar) the
-# thread-per-pair kernel runs.  The two must agree bitwise, and with the oracle.
-@pytest.mark.parametrize("n,level", [(128, 0), (192, 0), (256, 0), (256, 1)])
+# Interpolation of all three components onto fine levels with n % 64 == 0
+# runs the z-marching LDS-tiled kernel (forming v - ubar as it stages the
+# coarse planes, or taking v as the error when no ubar is given); one
+# component at a time runs the thread-per-pair kernel.  They must agree
+# bitwise, and with the oracle.
+@pytest.mark.parametrize("n,level", [(64, 0), (128, 0), (192, 0), (256, 0), (256, 1)])
 def test_prolong_tiles(n, level):
     s = make(n)
     nf, nc = s.levels[level], s.levels[level + 1]
@@ -166,11 +168,15 @@ def test_prolong_tiles(n, level):
     fine = g.uniform(-1, 1, (3, nf, nf, nf))
     v = g.uniform(-1, 1, (3, nc, nc, nc))
     ub = g.uniform(-1, 1, (3, nc, nc, nc))
-    tiled, direct = dev(fine), dev(fine)
+    tiled, tiled_e = dev(fine), dev(fine)
     s.prolong_add(level, dev(v), dev(ub), tiled, 3)
-    s.prolong_add(level, dev(v - ub), None, direct, 3)
+    s.prolong_add(level, dev(v - ub), None, tiled_e, 3)
+    direct = [dev(fine[c]) for c in range(3)]
+    for c in range(3):
+        s.prolong_add(level, dev(v[c]), dev(ub[c]), direct[c], 1)
     torch.cuda.synchronize()
-    assert torch.equal(tiled, direct)
+    assert torch.equal(tiled, tiled_e)
+    assert torch.equal(tiled, torch.stack(direct))
     assert rel(host(tiled), cfas.prolong_add(v - ub, fine)) < KERNEL_RTOL
 
 
