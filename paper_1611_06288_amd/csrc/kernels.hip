@@ -439,7 +439,7 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
             for (int z = 0; z < 2; ++z)
 #pragma unroll
                 for (int y = 0; y < 2; ++y)
-                    // v - ubar rounded to T: the value the coarse-error pass stores
+                    // v - ubar rounded to T: the value coarse_err_body stores
                     e[z][y] = uu ? (double)(T)((double)vv[o[z][y][x]] - (double)uu[o[z][y][x]])
                                  : (double)vv[o[z][y][x]];
             w[x] = 0.75 * (0.75 * e[0][0] + 0.25 * e[0][1]) + 0.25 * (0.75 * e[1][0] + 0.25 * e[1][1]);
@@ -622,8 +622,8 @@ void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const
     const size_t pairs = (size_t)coarse.n * fine.n * fine.n;
     const bool tile = fine.split && fine.n % kPX == 0 && fine.n % kPY == 0;
     if (fine_u.b && tile) {
-        // coarse error formed while its planes are staged (the value the
-        // separate coarse-error pass would store); ubar is left as it is
+        // coarse error formed while its planes are staged (the value
+        // coarse_err_body stores); ubar is left as it is
         if (nzr <= 0) nzr = prolong_tile_nzr(0, coarse.n, fine.n);
         const unsigned blocks = (unsigned)((fine.n / kPX) * (fine.n / kPY) * nzr);
         hipLaunchKernelGGL((k_prolong_tile<T>), dim3(blocks), dim3(kBlock), 0, s, coarse, fine, v,
