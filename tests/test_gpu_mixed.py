@@ -97,3 +97,22 @@ def test_mixed_cycle_graph_replays_are_consistent():
         assert outs[0][3] == outs[1][3]
         for a, b in zip(outs[0][:3], outs[1][:3]):
             assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n", [192, 256])
+def test_mixed_matches_fp64_at_tile_sizes(n):
+    """Column-tile sizes (192^3: uneven plane ranges in the z-marching
+    interpolation; 256^3: the benchmark's size and its 8-crystallite start):
+    the mixed form against the FP64 HIP path (itself held to the oracle at the
+    sizes the oracle finishes), two steps, same bar as above."""
+    p = inputs.polycrystal_params(n)
+    phi0 = inputs.polycrystal_256() if n == 256 else inputs.polycrystal_phi0(n, p.L, 8, seed=3)
+    mp, mi = run("mixed", n, p.L, p.eps, p.dt, phi0, 2, p.tol)
+    fp, fi = run("fp64", n, p.L, p.eps, p.dt, phi0, 2, p.tol)
+    for k in range(2):
+        assert mi[k].status == 0 and mi[k].res_final <= p.tol
+        err = float(np.max(np.abs(mp[k] - fp[k])))
+        print(f"n={n} step {k}: cycles mixed {mi[k].cycles} fp64 {fi[k].cycles}; "
+              f"max|phi_mixed - phi_fp64| = {err:.3e}")
+        assert err <= 100 * p.tol
+        assert abs(mi[k].cycles - fi[k].cycles) <= 2
