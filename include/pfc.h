@@ -131,8 +131,9 @@ pfc_status pfc_init_guess(pfc_handle *h, const double *phi0, double *mu, double 
  * phi^{k+1} = phi_next, mu^{k+1/2} and omega^{k+1/2}.  mu and omega are read
  * as the initial guess and overwritten with the result; the phi guess is
  * phi_cur.  The FAS cycle of Algorithm algorithm:FAS (V or F per the config)
- * repeats until max|S - N(u)| <= tol, tested before each cycle.  In FP64 with
- * M = 1 on a finest level of at least 128^3 with n a multiple of 64 the test
+ * repeats until max|S - N(u)| <= tol, tested before each cycle.  In FP64 (M = 1
+ * or variable mobility) on a finest level of at least 128^3 with n a multiple
+ * of 64 the test
  * after a cycle is formed inside the finest sweeps (the cycle's last
  * post-sweep and the next cycle's first pre-sweep, launched before the
  * decision and dropped when the loop stops); the norm is bitwise that of

@@ -267,8 +267,8 @@ double algorithmic_bytes(const pfc_handle *H, int kernel) {
             return (mixed ? 2 * 4.0 * fine + 3.0 : 2 * 8.0 * fine + 6.0) * P;
         }
         case PFC_KERNEL_NORM0: return (mixed ? (H->lev[0].rt ? 108.0 : 72.0) : 56.0 + mob) * P;
-        // the fused sweep's 72 plus old mu and omega of the colour-0 points
-        case PFC_KERNEL_SWEEP_NORM0: return H->split_norm ? 80.0 * P : 0.0;
+        // the fused sweep's 72 (80 with phi*) plus old mu and omega of the colour-0 points
+        case PFC_KERNEL_SWEEP_NORM0: return H->split_norm ? (80.0 + mob) * P : 0.0;
         default: return 0.0;
     }
 }

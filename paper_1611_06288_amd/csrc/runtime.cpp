@@ -465,8 +465,7 @@ pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out) {
         const Level &A = H->lev[0];
         H->split_blocks = A.fused ? fused_blocks(A.n, A.nz) : 0;
         H->split_norm = A.fused && cfg->nu1 >= 1 && cfg->nu2 >= 1 &&
-                        cfg->precision == PFC_FP64 && !mob &&
-                        H->split_blocks <= kMaxReduceBlocks;
+                        cfg->precision == PFC_FP64 && H->split_blocks <= kMaxReduceBlocks;
     }
     ok = ok && dalloc(H, &H->d_scal, 16) && dalloc(H, &H->d_iters, 4);
     ok = ok && dalloc(H, &H->energy_part, (size_t)6 * kMaxReduceBlocks + 16);

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
     const T *__restrict__ fa, const T *__restrict__ fb, const T *__restrict__ fc,
     const T *__restrict__ phk, const T *__restrict__ base, unsigned long long *__restrict__ part,
     int skip0) {
-    static_assert(NRM == 0 || (!DELTA && !MOB), "stop-test halves: FP64 sweeps with M = 1");
+    static_assert(NRM == 0 || !DELTA, "stop-test halves: FP64 sweeps");
     constexpr int NF = MOB ? 4 : 3;         // ring fields: phi, mu, omega (, phi*)
     __shared__ T c1[NF][3][kFCr][kFCs];   // [field][plane slot][row][point] old colour 1
     __shared__ T red[NF][3][kFRw][kFSl];  // [field][plane slot][row][point] new colour 0
@@ -304,9 +304,23 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                     if constexpr (NRM == 1) {  // residual of the input at this point
                         const double p0 = (double)ro[i][0], m0 = (double)rmo[i][0],
                                      w0 = (double)rmo[i][1];
-                        const double ls[3] = {(s3[0] - 6.0 * p0) * h2inv,
-                                              (s3[1] - 6.0 * m0) * h2inv,
-                                              (s3[2] - 6.0 * w0) * h2inv};
+                        double ls[3] = {(s3[0] - 6.0 * p0) * h2inv, (s3[1] - 6.0 * m0) * h2inv,
+                                        (s3[2] - 6.0 * w0) * h2inv};
+                        if constexpr (MOB) {  // flux form, faces xp, xm, yp, ym, zp, zm
+                            const double pc = (double)ro[i][6];
+                            double sm6 = 0.0;
+                            auto rface = [&](int sl3, int rr3, int cc3) {
+                                sm6 += face_mob(op.mob, pc, (double)c1[3][sl3][rr3][cc3]) *
+                                       ((double)c1[1][sl3][rr3][cc3] - m0);
+                            };
+                            rface(sk, r + 1, cxp);
+                            rface(sk, r + 1, cxm);
+                            rface(sk, r + 2, cx);
+                            rface(sk, r, cx);
+                            rface(skp, r + 1, cx);
+                            rface(skm, r + 1, cx);
+                            ls[1] = sm6 * h2inv;
+                        }
                         double rr[3];
                         resid_from_lap<false>(op, ls, p0, m0, w0, (double)ro[i][3],
                                               (double)ro[i][4], (double)ro[i][5],
@@ -380,9 +394,23 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                     ob[g] = (T)mu;
                     oc[g] = (T)om;
                     if constexpr (NRM == 2) {  // residual of the output at this point
-                        const double ls[3] = {(s3[0] - 6.0 * phi) * h2inv,
-                                              (s3[1] - 6.0 * mu) * h2inv,
-                                              (s3[2] - 6.0 * om) * h2inv};
+                        double ls[3] = {(s3[0] - 6.0 * phi) * h2inv, (s3[1] - 6.0 * mu) * h2inv,
+                                        (s3[2] - 6.0 * om) * h2inv};
+                        if constexpr (MOB) {  // flux form, faces xp, xm, yp, ym, zp, zm
+                            const double pc = (double)bphs[i];
+                            double sm6 = 0.0;
+                            auto rface = [&](int sl3, int rr3, int cc3) {
+                                sm6 += face_mob(op.mob, pc, (double)red[3][sl3][rr3][cc3]) *
+                                       ((double)red[1][sl3][rr3][cc3] - mu);
+                            };
+                            rface(q0, rr, sp);
+                            rface(q0, rr, sm);
+                            rface(q0, rr + 1, s0);
+                            rface(q0, rr - 1, s0);
+                            rface(qp, rr, s0);
+                            rface(qm, rr, s0);
+                            ls[1] = sm6 * h2inv;
+                        }
                         double rr[3];
                         resid_from_lap<false>(op, ls, phi, mu, om, (double)bo[i][2],
                                               (double)bo[i][3], (double)bo[i][4],
@@ -433,9 +461,18 @@ void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, T
     const unsigned blocks = (unsigned)fused_blocks(n, nz);
     if constexpr (!DELTA) {
         if (op.mob.phs) {  // variable mobility
-            hipLaunchKernelGGL((k_sweep_fused<T, false, true, 0>), dim3(blocks), dim3(kFT), 0, s,
-                               op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
-                               f.b, f.c, phk, base, nullptr, sk);
+            if (nrm == 1)
+                hipLaunchKernelGGL((k_sweep_fused<T, false, true, 1>), dim3(blocks), dim3(kFT), 0,
+                                   s, op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c,
+                                   f.a, f.b, f.c, phk, base, part, sk);
+            else if (nrm == 2)
+                hipLaunchKernelGGL((k_sweep_fused<T, false, true, 2>), dim3(blocks), dim3(kFT), 0,
+                                   s, op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c,
+                                   f.a, f.b, f.c, phk, base, part, sk);
+            else
+                hipLaunchKernelGGL((k_sweep_fused<T, false, true, 0>), dim3(blocks), dim3(kFT), 0,
+                                   s, op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c,
+                                   f.a, f.b, f.c, phk, base, nullptr, sk);
             return;
         }
         if (nrm == 1) {

@@ -1,5 +1,6 @@
 """The cycle loop's stop test split over the finest level's fused sweeps
-(FP64, M = 1, finest level of at least 128^3 with n % 64 == 0).
+(FP64, M = 1 or variable mobility, finest level of at least 128^3 with
+n % 64 == 0).
 
 The residual max-norm after a cycle is assembled from two halves: the
 colour-1 points, whose residual the cycle's last post-sweep forms from the
@@ -34,8 +35,13 @@ def make(n, L, eps, dt, **kw):
     return Solver(n, L, eps, dt, **kw)
 
 
-def host_loop(s, phi_prev, phi_cur, mu, om, tol, max_cycles):
+MOB = (1.0, 0.0, -1.0, 0.05)  # M(v) = max(0.05, 1 - v^2)
+
+
+def host_loop(s, phi_prev, phi_cur, mu, om, tol, max_cycles, mobility=None):
     """The cycle loop of one step with a whole-level norm before each cycle."""
+    if mobility is not None:  # phi* of this step, as the step computes it
+        s.set_phistar(0, 1.5 * phi_cur - 0.5 * phi_prev)
     f = s.source(phi_prev, phi_cur)
     u = torch.stack([phi_cur, mu, om]).contiguous()
     _, r = s.residual(0, u, f, phi_cur, want_r=False)
@@ -81,7 +87,8 @@ def check_step(n, seed, tol, max_cycles, **kw):
     counts = {k: s.timing_get(k)[0] for k in (PFC_KERNEL_SMOOTH0, PFC_KERNEL_SWEEP_NORM0,
                                                PFC_KERNEL_NORM0)}
     s.timing(False)
-    u, c, status, res0, res = host_loop(ref, prev, cur, mu_h, om_h, tol, max_cycles)
+    u, c, status, res0, res = host_loop(ref, prev, cur, mu_h, om_h, tol, max_cycles,
+                                        kw.get("mobility"))
     torch.cuda.synchronize()
     assert (info.cycles, info.status) == (c, status)
     assert info.res0 == res0 and info.res_final == res
@@ -97,6 +104,19 @@ def test_step_equals_host_loop(n, cycle, nu):
     assert info.status == 0 and c >= 3
     # the split path ran: one whole-level norm (before the first cycle), one
     # pre-sweep ahead per cycle, and every later cycle skips its first pre-sweep
+    assert counts[PFC_KERNEL_NORM0] == 1
+    assert counts[PFC_KERNEL_SWEEP_NORM0] == c
+    assert counts[PFC_KERNEL_SMOOTH0] == c * (nu[0] + nu[1]) - (c - 1)
+
+
+@pytest.mark.parametrize("n,cycle,nu", [(128, "V", (2, 2)), (128, "F", (2, 2)), (192, "V", (2, 1))])
+def test_step_equals_host_loop_mobility(n, cycle, nu):
+    """Variable mobility: both halves take the flux form of the first
+    equation with the face mobilities of phi*."""
+    s, info, counts = check_step(n, 60 + n, 1e-10, 400, cycle=cycle, nu1=nu[0], nu2=nu[1],
+                                 mobility=MOB)
+    c = info.cycles
+    assert info.status == 0 and c >= 3
     assert counts[PFC_KERNEL_NORM0] == 1
     assert counts[PFC_KERNEL_SWEEP_NORM0] == c
     assert counts[PFC_KERNEL_SMOOTH0] == c * (nu[0] + nu[1]) - (c - 1)
@@ -121,21 +141,21 @@ def test_step_256_equals_host_loop():
     assert info.status == 0 and counts[PFC_KERNEL_SWEEP_NORM0] == info.cycles
 
 
-@pytest.mark.parametrize("cycle", ["V", "F"])
-def test_graph_loop_equals_host_loop(cycle):
+@pytest.mark.parametrize("cycle,mobility", [("V", None), ("F", None), ("V", MOB)])
+def test_graph_loop_equals_host_loop(cycle, mobility):
     """pfc_run (graph replays, the colour-1 half seeded with the whole-level
     norm before a step's first replay) against the host loop, three steps."""
     n = 128
     p, phi = workload(n, 123)
-    s = make(n, p.L, p.eps, p.dt, cycle=cycle)
-    ref = make(n, p.L, p.eps, p.dt, cycle=cycle)
+    s = make(n, p.L, p.eps, p.dt, cycle=cycle, mobility=mobility)
+    ref = make(n, p.L, p.eps, p.dt, cycle=cycle, mobility=mobility)
     mu, om = s.init_guess(phi)
     mu_h, om_h = mu.clone(), om.clone()
     prev, cur = phi.clone(), phi.clone()
     infos = s.run(prev, cur, mu, om, 3)
     hp, hc = phi.clone(), phi.clone()
     for k in range(3):
-        u, c, status, res0, res = host_loop(ref, hp, hc, mu_h, om_h, 1e-10, 400)
+        u, c, status, res0, res = host_loop(ref, hp, hc, mu_h, om_h, 1e-10, 400, mobility)
         assert (infos[k].cycles, infos[k].status) == (c, status)
         assert infos[k].res0 == res0 and infos[k].res_final == res
         hp, hc = hc, u[0].clone()
