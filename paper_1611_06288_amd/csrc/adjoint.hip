@@ -300,7 +300,8 @@ static void adj_cycle(pfc_handle *H, int l, bool fcycle) {
     adj_cycle(H, l + 1, fcycle);
     if (fcycle) adj_cycle(H, l + 1, false);
     launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u),
-                           Tri<const double>{nullptr, nullptr, nullptr}, A.u);
+                           Tri<const double>{nullptr, nullptr, nullptr}, A.u, nullptr, false,
+                           A.pz[0]);
     for (int s = 0; s < H->cfg.nu2; ++s) adj_sweep(H, l);
 }
 
