@@ -540,6 +540,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tile(Lay LC, Lay LF, Tri<con
                 if (!phi0 || ((dx + y + dz) & 1)) {  // x0, 2 qx and 2 K are even
                     o[dz][dx][1] = fine.b[g];
                     o[dz][dx][2] = fine.c[g];
+                } else {  // not read nor written back; defined for the copy below
+                    o[dz][dx][1] = (T)0;
+                    o[dz][dx][2] = (T)0;
                 }
             }
     };
