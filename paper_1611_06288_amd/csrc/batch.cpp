@@ -148,7 +148,7 @@ void bcycle(pfc_batch *B, int d, bool fcycle) {
     if (fcycle) bcycle(B, d + 1, false);
     launch_batch(s, BK_ERR, B->d_mid[d], nm, blocks_of(mid, BK_RR, B->tile[BK_RR]), B->tile[BK_RR], 0, 0);
     launch_batch(s, BK_PROLONG, B->d_mid[d], nm, blocks_of(mid, BK_PROLONG, B->tile[BK_PROLONG]),
-                 B->tile[BK_PROLONG], 0, 0);
+                 B->tile[BK_PROLONG], B->cfg.nu2 >= 1 ? 1 : 0, 0);
     for (int q = 0; q < B->cfg.nu2; ++q) sweep();
 }
 
@@ -471,11 +471,17 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
         BSeg *dsegs = kind == BK_TAU ? b->d_all[1] : b->d_mid[0];
         float best = 1e30f;
         int best_tile = 256;
+        // the interpolation is timed in the form the cycle runs (see launch_batch)
+        const int pflag = b->cfg.nu2 >= 1 ? 1 : 0;
         for (int tile : {64, 128, 256, 512}) {
             const unsigned nb = blocks_of(segs, kind, tile);
-            for (int rep = 0; rep < 2; ++rep) launch_batch(b->stream, kind, dsegs, (int)segs.size(), nb, tile, rep & 1, 0);
+            for (int rep = 0; rep < 2; ++rep)
+                launch_batch(b->stream, kind, dsegs, (int)segs.size(), nb, tile,
+                             kind == BK_PROLONG ? pflag : rep & 1, 0);
             (void)hipEventRecord(t0, b->stream);
-            for (int rep = 0; rep < 6; ++rep) launch_batch(b->stream, kind, dsegs, (int)segs.size(), nb, tile, rep & 1, 0);
+            for (int rep = 0; rep < 6; ++rep)
+                launch_batch(b->stream, kind, dsegs, (int)segs.size(), nb, tile,
+                             kind == BK_PROLONG ? pflag : rep & 1, 0);
             (void)hipEventRecord(t1, b->stream);
             if (hipEventSynchronize(t1) != hipSuccess) break;
             float ms = 0.f;

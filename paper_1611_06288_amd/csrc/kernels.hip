@@ -407,10 +407,13 @@ void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f,
 // (d = 1), periodic; 3D weights are products.  One thread per pair of fine
 // cells (2I, j, k), (2I+1, j, k): they share the 12 coarse cells
 // {I-1, I, I+1} x {J0, J1} x {K0, K1}.  Consecutive threads take consecutive
-// I, so the fine accesses are unit-stride in each colour block.
+// I, so the fine accesses are unit-stride in each colour block.  phi0 (a
+// smoothing sweep follows): mu and omega are corrected at the pair's colour-1
+// point only, the colour-0 ones being dead until that sweep overwrites them.
 template <typename T>
 __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<const T> v,
-                                             Tri<const T> ubar, Tri<T> fine, unsigned t) {
+                                             Tri<const T> ubar, Tri<T> fine, unsigned t,
+                                             bool phi0 = false) {
     const int nc = LC.n, nf = LF.n;
     if (t >= (unsigned)nc * (unsigned)nf * (unsigned)nf) return;
     const unsigned row = LC.dn.q(t);           // (k, j) fine row
@@ -430,7 +433,7 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
             for (int x = 0; x < 3; ++x) o[z][y][x] = sidx32(LC, Ix[x], y ? J1 : J0, z ? K1 : K0);
     const unsigned f0 = sidx32(LF, 2 * I, j, k), f1 = sidx32(LF, 2 * I + 1, j, k);
     // one component; all three are issued together when there are three
-    auto comp_add = [&](const T *vv, const T *uu, T *ff) {
+    auto comp_add = [&](const T *vv, const T *uu, T *ff, bool w0, bool w1) {
         double w[3];  // y/z-interpolated values at x = I-1, I, I+1
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
@@ -444,13 +447,14 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
                                  : (double)vv[o[z][y][x]];
             w[x] = 0.75 * (0.75 * e[0][0] + 0.25 * e[0][1]) + 0.25 * (0.75 * e[1][0] + 0.25 * e[1][1]);
         }
-        ff[f0] = (T)((double)ff[f0] + (0.75 * w[1] + 0.25 * w[0]));
-        ff[f1] = (T)((double)ff[f1] + (0.75 * w[1] + 0.25 * w[2]));
+        if (w0) ff[f0] = (T)((double)ff[f0] + (0.75 * w[1] + 0.25 * w[0]));
+        if (w1) ff[f1] = (T)((double)ff[f1] + (0.75 * w[1] + 0.25 * w[2]));
     };
-    comp_add(v.a, ubar.a, fine.a);
+    comp_add(v.a, ubar.a, fine.a, true, true);
     if (fine.b) {
-        comp_add(v.b, ubar.b, fine.b);
-        comp_add(v.c, ubar.c, fine.c);
+        const bool c1 = ((j + k) & 1) != 0;  // (2I, j, k) is colour 1
+        comp_add(v.b, ubar.b, fine.b, !phi0 || c1, !phi0 || !c1);
+        comp_add(v.c, ubar.c, fine.c, !phi0 || c1, !phi0 || !c1);
     }
 }
 
@@ -465,9 +469,9 @@ __device__ __forceinline__ void coarse_err_body(size_t P, Tri<const T> v, Tri<T>
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(Lay LC, Lay LF, Tri<const T> v, Tri<const T> ubar,
-                                                    Tri<T> fine, const int *gate) {
+                                                    Tri<T> fine, const int *gate, int phi0) {
     if (gate_closed(gate)) return;
-    prolong_body<T>(LC, LF, v, ubar, fine, xcd_block() * kBlock + threadIdx.x);
+    prolong_body<T>(LC, LF, v, ubar, fine, xcd_block() * kBlock + threadIdx.x, phi0 != 0);
 }
 
 // Tiled form for colour-split fine levels with n a multiple of 64: a
@@ -635,7 +639,7 @@ void launch_prolong(hipStream_t s, const Lay &coarse, const Lay &fine, Tri<const
     }
     // thread per fine pair; with ubar it forms v - ubar where it reads it
     hipLaunchKernelGGL((k_prolong<T>), dim3(blocks_for(pairs)), dim3(kBlock), 0, s, coarse, fine, v,
-                       ubar, fine_u, gate);
+                       ubar, fine_u, gate, phi0 ? 1 : 0);
 }
 
 // ------------------------------------------------------ coarsest solve
@@ -1183,13 +1187,13 @@ __global__ __launch_bounds__(512) void kb_coarse_err(const BSeg *segs, int nseg)
     coarse_err_body<double>(npts(g.lay_c), cst(g.uc), g.ubarc, lb * blockDim.x + threadIdx.x);
 }
 
-__global__ __launch_bounds__(512) void kb_prolong(const BSeg *segs, int nseg) {
+__global__ __launch_bounds__(512) void kb_prolong(const BSeg *segs, int nseg, int phi0) {
     unsigned lb;
     const int s = bseg_find(segs, nseg, BK_PROLONG, lb);
     if (s < 0 || !*segs[s].active) return;
     const BSeg &g = segs[s];
     prolong_body<double>(g.lay_c, g.op.lay, cst(g.ubarc), Tri<const double>{nullptr, nullptr, nullptr},
-                         g.u, lb * blockDim.x + threadIdx.x);
+                         g.u, lb * blockDim.x + threadIdx.x, phi0 != 0);
 }
 
 __global__ __launch_bounds__(64) void kb_coarse(const BSeg *segs, int nseg) {
@@ -1274,7 +1278,8 @@ void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned 
             hipLaunchKernelGGL(kb_tau, dim3(blocks), dim3(block), 0, s, segs, nseg);
             break;
         case BK_PROLONG:
-            hipLaunchKernelGGL(kb_prolong, dim3(blocks), dim3(block), 0, s, segs, nseg);
+            // colour: 1 when a smoothing sweep follows (colour-0 mu, omega dead)
+            hipLaunchKernelGGL(kb_prolong, dim3(blocks), dim3(block), 0, s, segs, nseg, colour);
             break;
         case BK_ERR:
             hipLaunchKernelGGL(kb_coarse_err, dim3(blocks), dim3(block), 0, s, segs, nseg);

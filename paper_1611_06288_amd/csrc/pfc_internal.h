@@ -257,6 +257,8 @@ struct BState {
     const unsigned *norm_first, *norm_blocks;  // per finest-level segment
 };
 
+// colour: the half-sweep's colour (BK_SMOOTH); for BK_PROLONG 1 when a
+// smoothing sweep follows, so colour-0 mu, omega are left unwritten
 void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned blocks, int block,
                   int colour, int picard);
 void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg);
