@@ -39,8 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE x 1.0).  Valid only for the smoother sources
 # it was measured on (first 16 hex digits of the sha256 of smooth.hip, smooth.h
 # and device_common.h, concatenated); otherwise reported null.
-SMOOTHER_TRAFFIC = {"sources_sha256_16": "25fb4c7b1c55abd5", "n": 256,
-                    "fetch_KiB": 455015, "write_KiB": 350799,
+SMOOTHER_TRAFFIC = {"sources_sha256_16": "c5d3a19dcacf4126", "n": 256,
+                    "fetch_KiB": 466213, "write_KiB": 351504,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 SMOOTHER_SOURCES = ("smooth.hip", "smooth.h", "device_common.h")
 METRIC = "time-steps/s & V-cycles/s at 256^3 (FP64 vs mixed); smoother HBM GB/s %peak"
