@@ -177,6 +177,51 @@ def test_constant_state_is_exact_fixed_point(n):
     assert np.array_equal(out, phi)
 
 
+@pytest.mark.parametrize("n", [6, 7, 8])
+def test_initial_guess_is_the_gradient_of_the_discrete_energy(n):
+    """The first-step guess mu = phi^3 + (1-eps) phi + 2 Delta_h phi +
+    Delta_h^2 phi is the discrete chemical potential of (equation-PFC): the
+    gradient of F_h (PFC energy-discrete-1) in the h^3-weighted inner
+    product.  So along any direction v the central difference of F_h must
+    equal h^3 sum(mu v).  F_h is a quartic polynomial in phi, so the
+    five-point difference used here is exact up to rounding.  The last
+    direction is the constant one (d/dc F_h(phi + c) = h^3 sum(mu))."""
+    L, eps = 1.3 * n, 0.25
+    h = L / n
+    g = inputs.rng(100 + n)
+    phi = 0.2 + 0.3 * g.uniform(-1.0, 1.0, size=(n, n, n))
+    mu, om = cfas.initial_guess(phi, h, eps)
+
+    def slope(v, d=1e-3):
+        def F(t):
+            return D.energy(phi + t * v, h, eps)
+        return (8.0 * (F(d) - F(-d)) - (F(2 * d) - F(-2 * d))) / (12.0 * d)
+
+    dirs = [g.standard_normal((n, n, n)) for _ in range(3)] + [np.ones_like(phi)]
+    for trial, v in enumerate(dirs):
+        v = v / np.linalg.norm(v)
+        fd = slope(v)
+        got = h ** 3 * float(np.sum(mu * v))
+        assert abs(fd - got) <= 1e-9 * max(1.0, abs(got)), (trial, fd, got)
+
+
+@pytest.mark.parametrize("mode", [(1, 0, 0), (1, 2, 0), (2, 1, 3)])
+def test_initial_guess_omega_and_mu_on_a_fourier_mode(mode):
+    """On phi = a cos(2 pi (r i + s j + t k)/n) the guess must give
+    omega = lambda phi and mu = phi^3 + (1 - eps) phi + (2 lambda + lambda^2) phi
+    with the brute-force symbol lambda = -(4/h^2) sum sin^2(pi r/n) of
+    Section 4.1 (a sign or factor slip on either Laplacian term changes the
+    lambda polynomial)."""
+    n, L, eps, a = 8, 10.4, 0.3, 0.4
+    h = L / n
+    phi = np.ascontiguousarray(a * _mode(n, *mode).real)
+    lam = -(4.0 / h ** 2) * sum(math.sin(math.pi * r / n) ** 2 for r in mode)
+    mu, om = cfas.initial_guess(phi, h, eps)
+    assert np.max(np.abs(om - lam * phi)) < 1e-12 * max(1.0, abs(lam))
+    want = phi ** 3 + (1.0 - eps) * phi + (2.0 * lam + lam * lam) * phi
+    assert np.max(np.abs(mu - want)) < 1e-12 * max(1.0, lam * lam)
+
+
 def test_transfers_preserve_constants_and_linear_fields():
     """Restriction (8-child mean) and cell-centred trilinear interpolation:
     constants are preserved; a field linear in x is reproduced exactly away
