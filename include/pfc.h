@@ -148,6 +148,18 @@ pfc_status pfc_init_guess(pfc_handle *h, const double *phi0, double *mu, double 
 pfc_status pfc_step(pfc_handle *h, const double *phi_prev, const double *phi_cur,
                     double *phi_next, double *mu, double *omega, pfc_step_info *info);
 
+/* Forgets the coarsest level's cached Newton inverse (FP64 and FP32
+ * copies), so that the next coarsest solve rebuilds it.  Between calls of
+ * pfc_step the cache makes a step's last bits depend on the steps before it
+ * (the chord iteration starts from whichever inverse the previous solve
+ * left).  After this call a step's result depends on its arguments alone:
+ * checkpoint-and-recompute differentiation calls it at the start of every
+ * segment, in the forward pass and again in the recompute, and so
+ * reproduces the forward trajectory bit for bit.  Stream-ordered (one
+ * one-block kernel, no memset, so it may be recorded into a graph); does
+ * not synchronise.  INVALID_ARG for a NULL handle. */
+pfc_status pfc_reset_coarse_cache(pfc_handle *h);
+
 /* Time loop: advances (phi_prev, phi_cur) = (phi^{k-1}, phi^k) by `steps`
  * steps of pfc_step, in place: on return phi_prev and phi_cur hold the last
  * two states and mu, omega the last step's chemical potential and omega (the

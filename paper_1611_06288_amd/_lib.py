@@ -76,6 +76,7 @@ SIGNATURES = {
     "pfc_prolong_add": (_i32, [_vp, _i32, _dp, _dp, _dp, _i32]),
     "pfc_coarse_solve": (_i32, [_vp, _dp, _dp, _dp, C.POINTER(_i32)]),
     "pfc_set_phistar": (_i32, [_vp, _i32, _dp]),
+    "pfc_reset_coarse_cache": (_i32, [_vp]),
     "pfc_batch_create": (_i32, [_i32, C.POINTER(PfcConfig), _vp, C.POINTER(_vp)]),
     "pfc_batch_destroy": (_i32, [_vp]),
     "pfc_batch_set_state": (_i32, [_vp, _i32, _dp, _dp, _dp, _dp]),

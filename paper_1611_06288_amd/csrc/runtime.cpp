@@ -141,9 +141,14 @@ OpParams op_of(const pfc_handle *H, int l) {
     return op;
 }
 
+// Clears the two cache flags with a kernel rather than hipMemsetAsync, so
+// that a caller may record the call into a graph.
+__global__ void k_clear_flags(int *a, int *b) {
+    if (threadIdx.x == 0) { *a = 0; *b = 0; }
+}
+
 void invalidate_coarse(pfc_handle *H) {
-    (void)hipMemsetAsync(H->valid64, 0, sizeof(int), H->stream);
-    (void)hipMemsetAsync(H->valid32, 0, sizeof(int), H->stream);
+    k_clear_flags<<<1, 64, 0, H->stream>>>(H->valid64, H->valid32);
 }
 
 }  // namespace pfc
@@ -784,6 +789,13 @@ pfc_status pfc_coarse_solve(pfc_handle *h, double *u3, const double *f3, const d
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         std::memcpy(iters, h->h_pin, sizeof(int));
     }
+    return PFC_OK;
+}
+
+pfc_status pfc_reset_coarse_cache(pfc_handle *h) {
+    if (!h) return PFC_ERR_INVALID_ARG;
+    invalidate_coarse(h);
+    HIP_TRY(h, hipGetLastError());
     return PFC_OK;
 }
 

@@ -238,6 +238,11 @@ class Solver:
                                              _ptr(coarse_ubar, ncomp * nc ** 3, "ubar"),
                                              _ptr(fine, ncomp * nf ** 3, "fine"), ncomp))
 
+    def reset_coarse_cache(self):
+        """Forgets the cached coarsest Newton inverse (``pfc_reset_coarse_cache``)."""
+        self._sync_stream()
+        self._check(self.lib.pfc_reset_coarse_cache(self._h))
+
     def set_phistar(self, level, phs):
         """Variable mobility: phi* at `level` (and its 8-child means below)."""
         self._sync_stream()

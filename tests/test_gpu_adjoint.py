@@ -122,3 +122,38 @@ def test_adjoint_workload_64_finite_differences():
     fde = loss_diff(final(phi0, p.eps + d), final(phi0, p.eps - d)) / (2 * d)
     print(f"d/deps: adjoint {float(e.grad):.12e} FD {fde:.12e} rel {abs(float(e.grad) - fde) / abs(fde):.2e}")
     assert abs(float(e.grad) - fde) <= 1e-6 * abs(fde)
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_recompute_reproduces_the_forward_segment_bitwise(n):
+    """Checkpoint-and-recompute: the backward pass recomputes each segment
+    from its checkpoint after other work has run on the handle (later
+    segments, adjoint steps, unrelated steps that leave another coarsest
+    inverse in the cache).  run_segment clears the cache first, so the
+    recomputed trajectory must equal the forward one bit for bit."""
+    from paper_1611_06288_amd import Solver
+    from paper_1611_06288_amd.autograd import run_segment
+    p = inputs.adjoint_params(n)
+    s = Solver(n, p.L, p.eps, p.dt, tol=1e-12, max_cycles=600)
+    phi0 = dev(inputs.adjoint_phi0(n, seed=5))
+    mu, om = s.init_guess(phi0)
+    state = (phi0.clone(), phi0.clone(), mu, om)
+    fwd, ckpts = [], []
+    for seg in range(2):
+        ckpts.append(tuple(t.clone() for t in state))
+        phis, mu, om = run_segment(s, state, 5)
+        fwd.append(([t.clone() for t in phis], mu.clone(), om.clone()))
+        state = (phis[-2], phis[-1], mu, om)
+    # disturb the cache: steps on another field, and an adjoint step
+    other = dev(inputs.adjoint_phi0(n, seed=9))
+    mu2, om2 = s.init_guess(other)
+    s.step(other, other, mu2, om2)
+    g = torch.zeros_like(phi0)
+    geps = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.adjoint_step(fwd[1][0][0], fwd[1][0][1], fwd[1][0][2], other, g, g, geps)
+    for seg in (1, 0):
+        phis, mu_r, om_r = run_segment(s, ckpts[seg], 5)
+        want, mu_w, om_w = fwd[seg]
+        for k, (a, b) in enumerate(zip(phis, want)):
+            assert torch.equal(a, b), (seg, k, float((a - b).abs().max()))
+        assert torch.equal(mu_r, mu_w) and torch.equal(om_r, om_w), seg
