@@ -1,4 +1,5 @@
-"""The graph-driven time loop (pfc_run) against the step-by-step driver.
+"""The graph-driven time loop (pfc_run) against the step-by-step driver and
+the CPU oracle.
 
 pfc_run replays one recorded cycle (residual test, then a gated cycle) per
 cycle and takes the loop's decisions on the device; it must reproduce the
@@ -66,6 +67,41 @@ def test_run_equals_step_loop_bitwise(n, cycle, nu, mob):
     assert all(i.status == 0 for i in ia)
     for x, y in ((prev_a, prev_b), (cur_a, cur_b), (mu_a, mu_b), (om_a, om_b)):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("n,cycle,mob", [
+    (32, "V", None),             # thread-per-point levels
+    (48, "F", None),             # F-cycles, hierarchy down to 3^3
+    (64, "V", None),             # the long run's size
+    (32, "V", MOB),              # variable mobility
+])
+def test_run_matches_oracle(n, cycle, mob):
+    """pfc_run (graph replays, device stop test and cycle gate) against the
+    CPU oracle's time loop directly: equal cycle counts at every step,
+    phi, mu and omega within 1e-11 relative (max norm), the reported final
+    residual below tol.  (128^3 with fused sweeps and column tiles is
+    compared with the oracle's 200-step trajectory of the 128^3 polycrystal
+    in test_gpu_configs.py.)"""
+    from oracle import cfas
+    from paper_1611_06288_amd import Solver
+    L, eps, dt, steps, tol = n * math.pi / 4, 0.25, 0.5, 6, 1e-10
+    phi0 = inputs.polycrystal_phi0(n, L, 2, seed=2600 + n, radius_cells=4)
+    s = Solver(n, L, eps, dt, tol=tol, cycle=cycle, mobility=mob)
+    p0 = torch.from_numpy(phi0).cuda()
+    mu, om = s.init_guess(p0)
+    prev, cur = p0.clone(), p0.clone()
+    infos = s.run(prev, cur, mu, om, steps)
+    torch.cuda.synchronize()
+    phis, oinfos, (omu, oom) = cfas.simulate(phi0, L, eps, dt, steps, tol=tol, cycle=cycle,
+                                             mobility=mob)
+    got_c, want_c = [i.cycles for i in infos], [i.cycles for i in oinfos]
+    print(f"n={n} {cycle} mob={mob is not None}: cycles {got_c} (oracle {want_c})")
+    assert got_c == want_c
+    assert all(i.status == 0 and i.res_final <= tol for i in infos)
+    for got, want in ((prev, phis[-2]), (cur, phis[-1]), (mu, omu), (om, oom)):
+        g = got.cpu().numpy()
+        err = float(np.max(np.abs(g - want)) / np.max(np.abs(want)))
+        assert err <= 1e-11, err
 
 
 @pytest.mark.parametrize("steps", [1, 2, 3, 4])
