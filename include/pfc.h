@@ -197,6 +197,27 @@ pfc_status pfc_fas_vcycle(pfc_handle *h, double *u3, const double *f3,
  * (bitwise reproducible).  Synchronises. */
 pfc_status pfc_energy(pfc_handle *h, const double *phi, const double *phi_prev, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * energies and mass as pfc_energy, for any n in [4, PFC_ENERGY_STATIC_MAX_N],
+ * with no handle and no allocation.  phi (and phi_prev, nullable) are DEVICE
+ * pointers to n^3 FP64 values in C order on the current device, L the box
+ * edge (h = L/n), eps as in the config; out3 is a DEVICE pointer to 3
+ * doubles receiving (F_h, modified energy, mass) as pfc_energy's out.
+ * The per-workgroup partial sums live in a 768 KiB device array of the
+ * library, one per GPU, held until the process ends; its address is looked
+ * up on the first call on each device (call with the stream's device
+ * current).  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams, other host threads) race and must be
+ * ordered by the caller.  Enqueued on `stream` (NULL: the null stream);
+ * does not synchronise, calls no hipMalloc/hipFree, and records only kernel
+ * launches (capturable).  Results are bitwise those of pfc_energy.
+ * INVALID_ARG (message in pfc_last_error(NULL)) for n outside the range,
+ * L <= 0, non-finite eps or NULL phi/out3. */
+#define PFC_ENERGY_STATIC_MAX_N 1024
+pfc_status pfc_energy_static(int32_t n, double L, double eps, const double *phi,
+                             const double *phi_prev, double *out3, void *stream);
+
 /* Adjoint of one time step (the implicit-function theorem applied to
  * G(u; phi^k, phi^{k-1}, eps) = N(u) - S = 0 of scheme-PFC-o/s).
  * Given phi_prev = phi^{k-1}, phi_cur = phi^k, phi_next = phi^{k+1} (the

@@ -23,6 +23,7 @@ PFC_LIN_NEWTON, PFC_LIN_PICARD = 0, 1
 PFC_SWEEP_FULL = 2
 PFC_MOBILITY_ONE, PFC_MOBILITY_QUADRATIC = 0, 1
 PFC_SCHEME_CS2, PFC_SCHEME_CS1 = 0, 1
+PFC_ENERGY_STATIC_MAX_N = 1024
 
 PFC_KERNEL_SMOOTH0 = 0
 PFC_KERNEL_RESIDUAL0 = 1
@@ -68,6 +69,7 @@ SIGNATURES = {
     "pfc_run": (_i32, [_vp, _dp, _dp, _dp, _dp, _i32, C.POINTER(PfcStepInfo)]),
     "pfc_fas_vcycle": (_i32, [_vp, _dp, _dp, _dp, C.POINTER(C.c_double)]),
     "pfc_energy": (_i32, [_vp, _dp, _dp, C.POINTER(C.c_double)]),
+    "pfc_energy_static": (_i32, [_i32, _d, _d, _dp, _dp, _dp, _vp]),
     "pfc_adjoint_step": (_i32, [_vp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _d, C.POINTER(_i32)]),
     "pfc_source": (_i32, [_vp, _dp, _dp, _dp]),
     "pfc_residual": (_i32, [_vp, _i32, _dp, _dp, _dp, _dp, C.POINTER(C.c_double)]),

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libpfc_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "smooth.hip", "residual.hip", "runtime.cpp", "mixed.cpp", "timeloop.cpp", "adjoint.hip", "batch.cpp"]
+SOURCES = ["kernels.hip", "smooth.hip", "residual.hip", "runtime.cpp", "mixed.cpp", "timeloop.cpp", "adjoint.hip", "batch.cpp", "noalloc.hip"]
 
 # Contraction off: every kernel evaluates a formula exactly as written, so
 # kernels that share a formula (the half-sweep and the fused sweep) agree
