@@ -22,6 +22,8 @@ import argparse
 import json
 import math
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -68,8 +70,12 @@ def parse():
                     help="steps of that leg's step-by-step comparison run")
     ap.add_argument("--no-fcycle", action="store_true",
                     help="skip the FP64 F(2,2) run of the same steps (reported beside V)")
-    ap.add_argument("--cpu-cycles", type=int, default=3,
-                    help="oracle cycles timed for the CPU baseline (0 disables it)")
+    ap.add_argument("--cpu-cycles", type=int, default=8,
+                    help="oracle cycles timed on all threads for the CPU baseline (0 disables it)")
+    ap.add_argument("--cpu-one-core-cycles", type=int, default=1,
+                    help="oracle cycles timed on one thread (child process; 0 skips)")
+    ap.add_argument("--cpu-full-step", action="store_true",
+                    help="also time the oracle's whole first step on all threads (~1-2 min at 256^3)")
     ap.add_argument("--batch-steps", type=int, default=6,
                     help="time steps of the 64-instance batched ensemble (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=20,
@@ -287,30 +293,111 @@ def run_adjoint(torch, inputs, steps):
             "loss": float(loss.detach()), "dloss_deps": float(e.grad)}
 
 
-def cpu_baseline(cfas, phi0, p, cycles, cycles_per_step):
-    """Times the CPU oracle for `cycles` V(2,2) cycles of the first step."""
-    n = phi0.shape[0]
-    f = cfas.source(phi0, phi0, p.h, p.eps)
-    mu, om = cfas.initial_guess(phi0, p.h, p.eps)
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+# Run by the one-core leg in a child process whose OpenMP runtime starts
+# with one thread: one untimed cycle (first touch of the hierarchy), then
+# `cycles` timed V(2,2) cycles of the first step of the workload.
+_ONE_CORE_CHILD = """
+import json, math, sys, time
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+from oracle import cfas
+from paper_1611_06288_amd import inputs
+n, cycles = int(sys.argv[2]), int(sys.argv[3])
+p = inputs.polycrystal_params(n)
+phi0 = inputs.polycrystal_256() if n == 256 else inputs.polycrystal_phi0(n, p.L, 8, seed=3)
+h = p.L / n
+f = cfas.source(phi0, phi0, h, p.eps)
+mu, om = cfas.initial_guess(phi0, h, p.eps)
+o = cfas.Solver(n, p.L, p.eps, p.dt, tol=p.tol)
+u, _ = o.cycle(np.stack([phi0, mu, om]), f, phi0)
+t0 = time.perf_counter()
+for _ in range(cycles):
+    u, _ = o.cycle(u, f, phi0)
+dt = time.perf_counter() - t0
+print(json.dumps({"threads": cfas.num_threads(), "seconds": dt, "cycles": cycles}))
+"""
+
+
+def cpu_oracle_legs(cfas, phi0, p, cycles, one_core_cycles, full_step):
+    """Times the CPU oracle on the workload's first step: `cycles` V(2,2)
+    cycles on every thread the oracle's OpenMP runtime uses, `one_core_cycles`
+    on one thread (child process), and, with `full_step`, the whole first
+    step on every thread.  Runs before the GPU is touched."""
     import numpy as np
-    u = np.stack([phi0, mu, om])
+    n = phi0.shape[0]
+    h = p.L / n
+    out = {"threads_all": cfas.num_threads(), "cpu_model": _cpu_model(),
+           "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+    f = cfas.source(phi0, phi0, h, p.eps)
+    mu, om = cfas.initial_guess(phi0, h, p.eps)
     o = cfas.Solver(n, p.L, p.eps, p.dt, tol=p.tol)
-    u, _ = o.cycle(u, f, phi0)          # first touch of the hierarchy, untimed
+    u, _ = o.cycle(np.stack([phi0, mu, om]), f, phi0)      # first touch, untimed
     t0 = time.perf_counter()
     for _ in range(cycles):
         u, _ = o.cycle(u, f, phi0)
-    dt = time.perf_counter() - t0
+    out["all_cycles"], out["all_seconds"] = cycles, time.perf_counter() - t0
     o.close()
-    cps = cycles / dt
-    return {
+    if one_core_cycles > 0:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", _ONE_CORE_CHILD, ROOT, str(n), str(one_core_cycles)],
+                           env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0:
+            one = json.loads(r.stdout.strip().splitlines()[-1])
+            out["one_threads"], out["one_cycles"], out["one_seconds"] = (
+                one["threads"], one["cycles"], one["seconds"])
+        else:
+            out["one_core_error"] = r.stderr.strip()[-300:]
+    if full_step:
+        t0 = time.perf_counter()
+        _, infos, _ = cfas.simulate(phi0, p.L, p.eps, p.dt, 1, tol=p.tol)
+        out["full_step_seconds"] = time.perf_counter() - t0
+        out["full_step_cycles"] = infos[0].cycles
+    return out
+
+
+def cpu_baseline(legs, cycles_per_step, n):
+    """The bench line's cpu_baseline object from the timed legs: V-cycles/s
+    on all threads, converted to steps/s with the GPU run's mean cycles per
+    step over its timed steps (the oracle and the GPU take the same number
+    of cycles per step: the parity tests require equal counts)."""
+    cps = legs["all_cycles"] / legs["all_seconds"]
+    res = {
         "value": cps / cycles_per_step,
         "unit": "time-steps/s",
         "v_cycles_per_s": cps,
-        "cores": cfas.num_threads(),
+        "cores": legs["threads_all"],
         "kind": "oracle",
-        "sample": (f"{cycles} V(2,2) cycles of the first step at {n}^3 ({dt:.1f} s), "
-                   f"converted with the GPU run's mean of {cycles_per_step:.1f} cycles/step"),
+        "cpu_model": legs["cpu_model"],
+        "nproc": legs["nproc"],
+        "affinity_cpus": legs["affinity_cpus"],
+        "sample": (f"{legs['all_cycles']} V(2,2) cycles of the first step at {n}^3 on "
+                   f"{legs['threads_all']} threads ({legs['all_seconds']:.1f} s), converted with "
+                   f"the GPU run's mean of {cycles_per_step:.1f} cycles per timed step"),
     }
+    if "one_seconds" in legs:
+        c1 = legs["one_cycles"] / legs["one_seconds"]
+        res["one_core"] = {"threads": legs["one_threads"], "v_cycles_per_s": c1,
+                           "value": c1 / cycles_per_step,
+                           "sample": f"{legs['one_cycles']} cycle(s) of the same step on one "
+                                     f"thread ({legs['one_seconds']:.1f} s)"}
+    elif "one_core_error" in legs:
+        res["one_core"] = {"error": legs["one_core_error"]}
+    if "full_step_seconds" in legs:
+        res["first_step_in_full"] = {
+            "seconds": legs["full_step_seconds"], "cycles": legs["full_step_cycles"],
+            "steps_per_s": 1.0 / legs["full_step_seconds"],
+            "v_cycles_per_s": legs["full_step_cycles"] / legs["full_step_seconds"]}
+    return res
 
 
 def main():
@@ -321,11 +408,23 @@ def main():
               "supported (the z-slab decomposition is a design note, not code)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    from paper_1611_06288_amd import inputs
+
+    n = args.n
+    p = inputs.polycrystal_params(n)
+    phi0 = inputs.polycrystal_256() if n == 256 else inputs.polycrystal_phi0(n, p.L, 8, seed=3)
+    # the CPU oracle legs run first, before anything touches the GPU (the
+    # one-core leg is a child process)
+    cpu_legs = None
+    if args.cpu_cycles > 0 and not args.copy_probe:
+        from oracle import cfas
+        cpu_legs = cpu_oracle_legs(cfas, phi0, p, args.cpu_cycles, args.cpu_one_core_cycles,
+                                   args.cpu_full_step)
+        print(f"cpu oracle: {cpu_legs}", file=sys.stderr, flush=True)
+
     import torch
 
     from paper_1611_06288_amd import _lib as abi
-    from paper_1611_06288_amd import inputs
     from paper_1611_06288_amd.solver import PFCError, Solver
 
     if not torch.cuda.is_available():
@@ -337,9 +436,6 @@ def main():
         return
     ceiling = copy_ceiling(torch)
 
-    n = args.n
-    p = inputs.polycrystal_params(n)
-    phi0 = inputs.polycrystal_256() if n == 256 else inputs.polycrystal_phi0(n, p.L, 8, seed=3)
     ph = torch.from_numpy(phi0).cuda()
     boot = Solver(n, p.L, p.eps, p.dt, tol=p.tol)
     mu, om = boot.init_guess(ph)
@@ -380,7 +476,7 @@ def main():
                 "ms_per_step": round(mres["ms_per_step"], 3),
                 "cycles_per_step": mres["cycles_per_step"],
                 "speedup_vs_fp64_per_step": round(mres["steps_per_s"] / fp64["steps_per_s"], 4),
-                "max_abs_err_vs_fp64_per_step": errs,
+                "max_abs_err_vs_fp64_gpu_per_step": errs,
                 "kernels": mres["kernels"],
             }
             print(f"mixed: {mres['steps_per_s']:.3f} steps/s", file=sys.stderr, flush=True)
@@ -463,10 +559,9 @@ def main():
     }
 
     cpu = None
-    if args.cpu_cycles > 0:
-        from oracle import cfas
+    if cpu_legs is not None:
         mean_cyc = sum(fp64["cycles_per_step"]) / len(fp64["cycles_per_step"])
-        cpu = cpu_baseline(cfas, phi0, p, args.cpu_cycles, mean_cyc)
+        cpu = cpu_baseline(cpu_legs, mean_cyc, n)
 
     line = {
         "metric": METRIC,
