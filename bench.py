@@ -76,7 +76,7 @@ def parse():
                     help="oracle cycles timed on one thread (child process; 0 skips)")
     ap.add_argument("--cpu-full-step", action="store_true",
                     help="also time the oracle's whole first step on all threads (~1-2 min at 256^3)")
-    ap.add_argument("--batch-steps", type=int, default=6,
+    ap.add_argument("--batch-steps", type=int, default=50,
                     help="time steps of the 64-instance batched ensemble (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=20,
                     help="time steps of the 64^3 differentiated rollout (0 skips it)")
@@ -230,7 +230,7 @@ def run_long(Solver, torch, inputs, steps, plain_steps=200):
 
 def run_batched(torch, inputs, steps, warmup=1):
     """64 instances, n in {32,48,64,96}, eps in [0.02,0.3], s = 0.1, V(2,2) to
-    1e-10, workgroup sizes from the autotuner.  Returns rates aggregated over
+    1e-10, tile shapes from the autotuner.  Returns rates aggregated over
     the instances."""
     from paper_1611_06288_amd.solver import Batch
     ens = inputs.batched_ensemble(64, steps=steps)
@@ -257,7 +257,9 @@ def run_batched(torch, inputs, steps, warmup=1):
         "v_cycles_per_s_summed": round(sum(cyc) / dt, 2),
         "mean_cycles_per_instance_step": round(sum(cyc) / (len(ens) * steps), 2),
         "max_cycles_per_step": max(max(x.cycles for x in row) for row in infos),
-        "autotuned_workgroup_sizes": dict(zip(["smooth", "resid_restrict", "tau", "prolong"], tiles)),
+        "autotuned_schedule_threads_items": dict(zip(
+            ["smooth", "resid_restrict", "tau", "prolong", "coarse_err"],
+            [["persistent" if p else "per-tile", th, it] for p, th, it in tiles])),
     }
 
 

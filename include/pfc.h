@@ -294,7 +294,7 @@ pfc_status pfc_coarse_solve(pfc_handle *h, double *u3, const double *f3, const d
 
 /* ---------------------------------------------------------------------------
  * Batched form: many independent simulations (own n, L, eps, dt) advanced
- * together, every kernel of a cycle launched once for all instances.
+ * together, every phase of a cycle one launch for all instances.
  * ------------------------------------------------------------------------- */
 typedef struct pfc_batch pfc_batch;
 
@@ -315,19 +315,27 @@ pfc_status pfc_batch_get_state(pfc_batch *b, int32_t i, double *phi_prev, double
 pfc_status pfc_batch_init_state(pfc_batch *b, int32_t i, const double *phi0);
 /* Advances every instance by `steps` time steps of scheme (1.10).  Each
  * phase of a cycle is one launch over all instances that take part in it
- * (levels aligned from the finest); an instance stops cycling when its own
+ * (levels aligned from the finest), over a work-list of fixed-size tiles of
+ * every instance's part of the phase, in the schedule the autotuner chose
+ * (one tile per workgroup by default); an instance stops cycling when its own
  * residual meets the tolerance, so it follows exactly the cycle sequence of
  * pfc_step.  One cycle plus the stop test is captured as a hipGraph on the
  * batch's own stream and replayed.  infos (host, nullable): count*steps
  * entries, instance-major.  Returns the first non-OK instance status (the
  * others still advance).  Synchronises. */
 pfc_status pfc_batch_run(pfc_batch *b, int32_t steps, pfc_step_info *infos);
-/* Chooses the workgroup size (64, 128, 256 or 512) of the batched smoothing,
- * residual+coarsening, tau and interpolation launches by timing each on
- * this batch; with cache_path (nullable) choices are read from / written to
- * a JSON file keyed by GPU architecture, instance sizes and kernel.
- * chosen (host, nullable): 4 ints in that kernel order.  Leaves the state
- * unchanged.  Synchronises. */
+/* Chooses, for each batched phase kind (smoothing, residual+coarsening, tau,
+ * interpolation, coarse error), its schedule and tile shape by timing every
+ * combination on this batch: one tile per workgroup or persistent (as many
+ * workgroups as are resident walk the work-list), 64, 128, 256 or 512
+ * threads per workgroup, and tiles of 64 .. 4096 consecutive work items
+ * (rows of half-sweep points, coarse cells, fine x-pairs or points: a slab
+ * of rows and planes of one instance).  With cache_path (nullable) choices
+ * are read from / written to a JSON file keyed by GPU architecture,
+ * instance sizes and phase.  chosen (host, nullable): 15 ints, (persistent,
+ * threads, tile items) per phase in that order.  Results do not depend on
+ * the choice (same per-point arithmetic).  Leaves the state unchanged.
+ * Synchronises. */
 pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *chosen);
 const char *pfc_batch_last_error(const pfc_batch *b);
 

@@ -1,11 +1,14 @@
 // Batched form: many independent PFC simulations (own n, L, eps, dt) advanced
-// together.  Every phase of a multigrid cycle is ONE launch over all instances
-// that take part in it (levels aligned from the finest); instances whose
-// residual met the tolerance are masked by a device flag, so each instance
-// runs exactly the cycle sequence of the single-instance driver.  One cycle
-// (stop test + V or F cycle) is captured once as a hipGraph and replayed
-// until no instance is active.  Workgroup sizes of the batched kernels are
-// chosen by a small autotuner whose choices can be cached in a JSON file.
+// together.  Every phase of a multigrid cycle is ONE launch over all
+// instances that take part in it (levels aligned from the finest), over a
+// work-list of tiles of every instance's part of the phase: one tile per
+// workgroup, or persistent (the resident workgroups walk the list).
+// Instances whose residual met the tolerance are masked by a device flag, so
+// each instance runs exactly the cycle sequence of the single-instance
+// driver.  One cycle (stop test + V or F cycle) is captured once as a
+// hipGraph and replayed until no instance is active.  Schedule, tile size
+// and workgroup size of every phase kind are chosen by an autotuner whose
+// choices can be cached in a JSON file.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,7 +43,14 @@ struct pfc_batch {
     int *h_num = nullptr;   // pinned: the instances' active flags
     int *h_stats = nullptr; // pinned: cycles, status per instance
     double *h_res = nullptr;  // pinned: res0, res per instance
-    int tile[4] = {256, 256, 256, 256};
+    // per phase kind (smooth, residual + coarsening, tau, interpolation,
+    // coarse error): threads per workgroup, tile size kTileMin << opt work
+    // items, schedule (persistent or one tile per workgroup) and, when
+    // persistent, the resident workgroups at that size
+    int threads[5] = {256, 256, 256, 256, 256};
+    int opt[5] = {2, 2, 2, 2, 2};
+    bool persist[5] = {false, false, false, false, false};
+    unsigned slots[5] = {0, 0, 0, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool graph_ready = false;
@@ -79,16 +89,24 @@ unsigned seg_count(const BSeg &g, int kind) {
     const unsigned n = (unsigned)g.op.lay.n, P = n * n * n;
     switch (kind) {
         case BK_SMOOTH: return P / 2;
-        case BK_RR: return (unsigned)(g.lay_c.n * g.lay_c.n * g.lay_c.n);
+        case BK_RR:
+        case BK_ERR: return (unsigned)(g.lay_c.n * g.lay_c.n * g.lay_c.n);
         case BK_PROLONG: return (unsigned)g.lay_c.n * n * n;
         default: return P;
     }
 }
 
-unsigned blocks_of(const std::vector<BSeg> &v, int kind, int tile) {
+// Tiles of kTileMin << opt work items in a launch of `kind` over the list v.
+unsigned tiles_of(const std::vector<BSeg> &v, int kind, int opt) {
+    const unsigned items = (unsigned)kTileMin << opt;
     unsigned b = 0;
-    for (const auto &g : v) b += (seg_count(g, kind) + tile - 1) / tile;
+    for (const auto &g : v) b += (seg_count(g, kind) + items - 1) / items;
     return b;
+}
+
+void phase(pfc_batch *B, int kind, const std::vector<BSeg> &h, BSeg *d, int arg0, int arg1) {
+    launch_batch(B->stream, kind, d, (int)h.size(), tiles_of(h, kind, B->opt[kind]), B->opt[kind],
+                 B->threads[kind], B->persist[kind] ? B->slots[kind] : 0u, arg0, arg1);
 }
 
 BSeg make_seg(pfc_handle *h, int l, int i, const int *active) {
@@ -132,23 +150,17 @@ void bcycle(pfc_batch *B, int d, bool fcycle) {
     if (!B->h_bot[d].empty()) launch_batch_coarse(s, B->d_bot[d], (int)B->h_bot[d].size());
     if (B->h_mid[d].empty()) return;
     const auto &mid = B->h_mid[d];
-    const int nm = (int)mid.size();
     const int picard = B->cfg.lin == PFC_LIN_PICARD;
     auto sweep = [&]() {
-        const unsigned nb = blocks_of(mid, BK_SMOOTH, B->tile[BK_SMOOTH]);
-        for (int c = 0; c < 2; ++c)
-            launch_batch(s, BK_SMOOTH, B->d_mid[d], nm, nb, B->tile[BK_SMOOTH], c, picard);
+        for (int c = 0; c < 2; ++c) phase(B, BK_SMOOTH, mid, B->d_mid[d], c, picard);
     };
     for (int q = 0; q < B->cfg.nu1; ++q) sweep();
-    launch_batch(s, BK_RR, B->d_mid[d], nm, blocks_of(mid, BK_RR, B->tile[BK_RR]), B->tile[BK_RR], 0, 0);
-    const auto &nxt = B->h_all[d + 1];
-    launch_batch(s, BK_TAU, B->d_all[d + 1], (int)nxt.size(), blocks_of(nxt, BK_TAU, B->tile[BK_TAU]),
-                 B->tile[BK_TAU], 0, 0);
+    phase(B, BK_RR, mid, B->d_mid[d], 0, 0);
+    phase(B, BK_TAU, B->h_all[d + 1], B->d_all[d + 1], 0, 0);
     bcycle(B, d + 1, fcycle);
     if (fcycle) bcycle(B, d + 1, false);
-    launch_batch(s, BK_ERR, B->d_mid[d], nm, blocks_of(mid, BK_RR, B->tile[BK_RR]), B->tile[BK_RR], 0, 0);
-    launch_batch(s, BK_PROLONG, B->d_mid[d], nm, blocks_of(mid, BK_PROLONG, B->tile[BK_PROLONG]),
-                 B->tile[BK_PROLONG], B->cfg.nu2 >= 1 ? 1 : 0, 0);
+    phase(B, BK_ERR, mid, B->d_mid[d], 0, 0);
+    phase(B, BK_PROLONG, mid, B->d_mid[d], B->cfg.nu2 >= 1 ? 1 : 0, 0);
     for (int q = 0; q < B->cfg.nu2; ++q) sweep();
 }
 
@@ -329,15 +341,14 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
             *d = nullptr;
             return true;
         }
-        std::vector<BSeg> w = v;  // with this list's first blocks
-        for (int kind = 0; kind < 6; ++kind)
-            for (int ti = 0; ti < 4; ++ti) {
-                const unsigned tile = 64u << ti;
-                const int ck = kind == BK_ERR ? BK_RR : kind;
+        std::vector<BSeg> w = v;  // with this list's first tiles
+        for (int kind = 0; kind < BK_KINDS; ++kind)
+            for (int opt = 0; opt < kTileOpts; ++opt) {
+                const unsigned items = (unsigned)kTileMin << opt;
                 unsigned acc = 0;
                 for (auto &g : w) {
-                    g.first[kind][ti] = acc;
-                    acc += (seg_count(g, ck) + tile - 1) / tile;
+                    g.first[kind][opt] = acc;
+                    acc += (seg_count(g, kind) + items - 1) / items;
                 }
             }
         return balloc(B, d, w.size()) &&
@@ -356,7 +367,7 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
     unsigned acc = 0;
     for (int s = 0; s < count; ++s) {
         first[s] = acc;
-        nblk[s] = (seg_count(B->h_all[0][s], BK_NORM) + kBlock - 1) / kBlock;
+        nblk[s] = (seg_count(B->h_all[0][s], BK_NORM) + kBlock - 1) / kBlock;  // norm tiles
         acc += nblk[s];
     }
     B->norm_blocks = acc;
@@ -448,21 +459,39 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
     std::ostringstream sig;
     sig << device_name() << "|" << sizes.size() << ":";
     for (size_t i = 0; i < sizes.size(); ++i) sig << (i ? "," : "") << sizes[i];
-    static const char *kind_name[4] = {"smooth", "resid_restrict", "tau", "prolong"};
+    static const char *kind_name[5] = {"smooth", "resid_restrict", "tau", "prolong", "coarse_err"};
     std::map<std::string, int> cache;
     if (cache_path) cache = read_cache(cache_path);
     bool changed = false;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
     // make the working buffers hold a sane state to time on
     for (int i = 0; i < b->count; ++i) step_begin(b->inst[i], b->prev[i], b->cur[i], b->mu[i], b->om[i]);
     launch_batch_reset(b->stream, b->st, b->count, b->d_valid);
     hipEvent_t t0, t1;
     (void)hipEventCreate(&t0);
     (void)hipEventCreate(&t1);
-    for (int kind = 0; kind < 4; ++kind) {
+    // a choice is stored as persistent * 100000 + threads * 10 + opt
+    auto decode = [](int code, bool &ps, int &th, int &o) {
+        ps = code / 100000 != 0;
+        th = (code % 100000) / 10;
+        o = code % 10;
+        return (th == 64 || th == 128 || th == 256 || th == 512) && o < kTileOpts &&
+               (kTileMin << o) >= th;
+    };
+    auto apply = [&](int kind, bool ps, int th, int o) {
+        b->persist[kind] = ps;
+        b->threads[kind] = th;
+        b->opt[kind] = o;
+        b->slots[kind] = ps ? (unsigned)batch_phase_slots(kind, th, dev) : 0u;
+    };
+    for (int kind = 0; kind < 5; ++kind) {
         const std::string key = sig.str() + "|" + kind_name[kind];
         auto it = cache.find(key);
-        if (it != cache.end() && (it->second == 64 || it->second == 128 || it->second == 256 || it->second == 512)) {
-            b->tile[kind] = it->second;
+        bool ps;
+        int th, o;
+        if (it != cache.end() && decode(it->second, ps, th, o)) {
+            apply(kind, ps, th, o);
             continue;
         }
         const int d = kind == BK_TAU ? 1 : 0;
@@ -470,29 +499,36 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
         const auto &segs = kind == BK_TAU ? b->h_all[1] : b->h_mid[0];
         BSeg *dsegs = kind == BK_TAU ? b->d_all[1] : b->d_mid[0];
         float best = 1e30f;
-        int best_tile = 256;
-        // the interpolation is timed in the form the cycle runs (see launch_batch)
+        int best_code = 256 * 10 + 2;
+        // the interpolation is timed in the form the cycle runs
         const int pflag = b->cfg.nu2 >= 1 ? 1 : 0;
-        for (int tile : {64, 128, 256, 512}) {
-            const unsigned nb = blocks_of(segs, kind, tile);
-            for (int rep = 0; rep < 2; ++rep)
-                launch_batch(b->stream, kind, dsegs, (int)segs.size(), nb, tile,
-                             kind == BK_PROLONG ? pflag : rep & 1, 0);
-            (void)hipEventRecord(t0, b->stream);
-            for (int rep = 0; rep < 6; ++rep)
-                launch_batch(b->stream, kind, dsegs, (int)segs.size(), nb, tile,
-                             kind == BK_PROLONG ? pflag : rep & 1, 0);
-            (void)hipEventRecord(t1, b->stream);
-            if (hipEventSynchronize(t1) != hipSuccess) break;
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, t0, t1);
-            if (ms < best) {
-                best = ms;
-                best_tile = tile;
+        for (int persistent = 0; persistent < 2; ++persistent)
+            for (int thr : {64, 128, 256, 512}) {
+                const unsigned sl = persistent ? (unsigned)batch_phase_slots(kind, thr, dev) : 0u;
+                if (persistent && sl == 0) continue;
+                for (int op = 0; op < kTileOpts; ++op) {
+                    if ((kTileMin << op) < thr) continue;
+                    const unsigned nt = tiles_of(segs, kind, op);
+                    auto run = [&](int rep) {
+                        launch_batch(b->stream, kind, dsegs, (int)segs.size(), nt, op, thr, sl,
+                                     kind == BK_PROLONG ? pflag : rep & 1, 0);
+                    };
+                    for (int rep = 0; rep < 2; ++rep) run(rep);
+                    (void)hipEventRecord(t0, b->stream);
+                    for (int rep = 0; rep < 6; ++rep) run(rep);
+                    (void)hipEventRecord(t1, b->stream);
+                    if (hipEventSynchronize(t1) != hipSuccess) break;
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, t0, t1);
+                    if (ms < best) {
+                        best = ms;
+                        best_code = persistent * 100000 + thr * 10 + op;
+                    }
+                }
             }
-        }
-        b->tile[kind] = best_tile;
-        cache[key] = best_tile;
+        decode(best_code, ps, th, o);
+        apply(kind, ps, th, o);
+        cache[key] = best_code;
         changed = true;
     }
     (void)hipEventDestroy(t0);
@@ -502,7 +538,11 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
     if (cache_path && changed) write_cache(cache_path, cache);
     b->graph_ready = false;  // recapture with the chosen tiles
     if (chosen)
-        for (int k = 0; k < 4; ++k) chosen[k] = b->tile[k];
+        for (int k = 0; k < 5; ++k) {
+            chosen[3 * k] = b->persist[k] ? 1 : 0;
+            chosen[3 * k + 1] = b->threads[k];
+            chosen[3 * k + 2] = kTileMin << b->opt[k];
+        }
     return PFC_OK;
 }
 

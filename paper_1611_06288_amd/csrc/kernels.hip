@@ -1119,81 +1119,80 @@ void launch_zero(hipStream_t s, float *p, size_t count) {
 
 // ----------------------------------------------------------- batched form
 //
-// One launch serves every instance that takes part in a multigrid phase: the
-// grid is the concatenation of each instance's blocks (its "segment"), a
-// workgroup finds its segment by a binary search over the segments' first
-// blocks (precomputed per launch kind and workgroup size), and instances
-// whose convergence flag is cleared return at once.
+// Every multigrid phase of the batched cycle is one launch over all
+// instances that take part in it.  Each instance's part of the phase (its
+// "segment") is cut into tiles of a fixed number of consecutive work items
+// (half-sweep points, coarse cells, fine x-pairs, points: a slab of rows and
+// planes of one instance); the tiles of all segments form one work-list, in
+// segment order.  Two schedules walk it:
+//   * one tile per workgroup, the hardware dispatcher handing out tiles
+//     (PERSIST = false: grid = tile count);
+//   * persistent: only as many workgroups as are resident at once, each
+//     taking every gridDim.x-th tile (PERSIST = true).
+// A workgroup finds a tile's segment by a binary search over the segments'
+// first tiles (precomputed for every tile size) and skips tiles of instances
+// whose convergence flag is cleared.  Schedule, tile size and workgroup size
+// are per phase kind, chosen by the batch's autotuner.  The per-item
+// arithmetic is that of the single-instance kernels, so the schedule does
+// not change any result.
 
 __device__ __forceinline__ unsigned bseg_count(const BSeg &g, int kind) {
     const unsigned n = (unsigned)g.op.lay.n, P = n * n * n;
     switch (kind) {
         case BK_SMOOTH: return P / 2;
-        case BK_RR: return (unsigned)(g.lay_c.n * g.lay_c.n * g.lay_c.n);
+        case BK_RR:
+        case BK_ERR: return (unsigned)(g.lay_c.n * g.lay_c.n * g.lay_c.n);
         case BK_PROLONG: return (unsigned)g.lay_c.n * n * n;
         default: return P;  // BK_TAU, BK_NORM
     }
 }
 
-// Segment of workgroup blockIdx.x for a launch of `kind` with workgroups of
-// 64, 128, 256 or 512 threads; -1 past the end.
-__device__ __forceinline__ int bseg_find(const BSeg *segs, int nseg, int kind, unsigned &local) {
-    const unsigned b = blockIdx.x, bd = blockDim.x;
-    const int ti = bd == 64 ? 0 : (bd == 128 ? 1 : (bd == 256 ? 2 : 3));
-    int lo = 0, hi = nseg - 1;  // the last segment whose first block is <= b
+// Segment holding work-list tile `tile` (tiles of kTileMin << opt items).
+__device__ __forceinline__ int bseg_of_tile(const BSeg *segs, int nseg, int kind, int opt,
+                                            unsigned tile, unsigned &local) {
+    int lo = 0, hi = nseg - 1;  // the last segment whose first tile is <= tile
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (segs[mid].first[kind][ti] <= b)
+        if (segs[mid].first[kind][opt] <= tile)
             lo = mid;
         else
             hi = mid - 1;
     }
-    local = b - segs[lo].first[kind][ti];
-    const unsigned nb = (bseg_count(segs[lo], kind) + bd - 1) / bd;
-    return local < nb ? lo : -1;
+    local = tile - segs[lo].first[kind][opt];
+    return lo;
 }
 
-__global__ __launch_bounds__(512) void kb_smooth(const BSeg *segs, int nseg, int colour, int picard) {
-    unsigned lb;
-    const int s = bseg_find(segs, nseg, BK_SMOOTH, lb);
-    if (s < 0 || !*segs[s].active) return;
-    const BSeg &g = segs[s];
-    smooth_body<double, false>(g.op, colour, picard, g.u, cst(g.f), g.phk, nullptr,
-                               lb * blockDim.x + threadIdx.x);
+template <int KIND>
+__device__ __forceinline__ void kb_item(const BSeg &g, unsigned i, int arg0, int arg1) {
+    if constexpr (KIND == BK_SMOOTH) {
+        smooth_body<double, false>(g.op, arg0, arg1, g.u, cst(g.f), g.phk, nullptr, i);
+    } else if constexpr (KIND == BK_RR) {
+        resid_restrict_body<double, false>(g.op, g.lay_c, cst(g.u), cst(g.f), g.phk, nullptr,
+                                           g.ubarc, g.fc, i);
+    } else if constexpr (KIND == BK_TAU) {
+        tau_body<double, false>(g.op, cst(g.ubar), g.f, g.u, g.phk, nullptr, i);
+    } else if constexpr (KIND == BK_ERR) {  // coarse error v - I u, stored over I u
+        coarse_err_body<double>(npts(g.lay_c), cst(g.uc), g.ubarc, i);
+    } else {  // BK_PROLONG: adds the interpolated coarse error
+        prolong_body<double>(g.lay_c, g.op.lay, cst(g.ubarc), Tri<const double>{nullptr, nullptr, nullptr},
+                             g.u, i, arg0 != 0);
+    }
 }
 
-__global__ __launch_bounds__(512) void kb_resid_restrict(const BSeg *segs, int nseg) {
-    unsigned lb;
-    const int s = bseg_find(segs, nseg, BK_RR, lb);
-    if (s < 0 || !*segs[s].active) return;
-    const BSeg &g = segs[s];
-    resid_restrict_body<double, false>(g.op, g.lay_c, cst(g.u), cst(g.f), g.phk, nullptr, g.ubarc,
-                                       g.fc, lb * blockDim.x + threadIdx.x);
-}
-
-__global__ __launch_bounds__(512) void kb_tau(const BSeg *segs, int nseg) {
-    unsigned lb;
-    const int s = bseg_find(segs, nseg, BK_TAU, lb);
-    if (s < 0 || !*segs[s].active) return;
-    const BSeg &g = segs[s];
-    tau_body<double, false>(g.op, cst(g.ubar), g.f, g.u, g.phk, nullptr, lb * blockDim.x + threadIdx.x);
-}
-
-__global__ __launch_bounds__(512) void kb_coarse_err(const BSeg *segs, int nseg) {
-    unsigned lb;
-    const int s = bseg_find(segs, nseg, BK_RR, lb);   // one thread per coarse point
-    if (s < 0 || !*segs[s].active) return;
-    const BSeg &g = segs[s];
-    coarse_err_body<double>(npts(g.lay_c), cst(g.uc), g.ubarc, lb * blockDim.x + threadIdx.x);
-}
-
-__global__ __launch_bounds__(512) void kb_prolong(const BSeg *segs, int nseg, int phi0) {
-    unsigned lb;
-    const int s = bseg_find(segs, nseg, BK_PROLONG, lb);
-    if (s < 0 || !*segs[s].active) return;
-    const BSeg &g = segs[s];
-    prolong_body<double>(g.lay_c, g.op.lay, cst(g.ubarc), Tri<const double>{nullptr, nullptr, nullptr},
-                         g.u, lb * blockDim.x + threadIdx.x, phi0 != 0);
+// arg0, arg1: colour and picard (BK_SMOOTH); 1 when a smoothing sweep
+// follows (BK_PROLONG: colour-0 mu, omega left unwritten).
+template <int KIND, bool PERSIST>
+__global__ __launch_bounds__(512) void kb_phase(const BSeg *segs, int nseg, unsigned ntiles, int opt,
+                                                int arg0, int arg1) {
+    const unsigned tile_items = (unsigned)kTileMin << opt;
+    for (unsigned t = blockIdx.x; t < ntiles; t += PERSIST ? gridDim.x : ntiles) {
+        unsigned local;
+        const BSeg &g = segs[bseg_of_tile(segs, nseg, KIND, opt, t, local)];
+        if (!*g.active) continue;
+        const unsigned base = local * tile_items;
+        for (unsigned r = threadIdx.x; r < tile_items; r += blockDim.x)
+            kb_item<KIND>(g, base + r, arg0, arg1);
+    }
 }
 
 __global__ __launch_bounds__(64) void kb_coarse(const BSeg *segs, int nseg) {
@@ -1204,15 +1203,15 @@ __global__ __launch_bounds__(64) void kb_coarse(const BSeg *segs, int nseg) {
                                g.iters);
 }
 
-// Per-block residual maxima of every instance's finest level (kBlock threads
-// per block, one point per thread); partial[] follows the segment order.
+// Residual maxima of every instance's finest level, one per workgroup of
+// kBlock points (norm tiles: opt kNormOpt, so that each instance owns a
+// known range of partial[]); workgroups of finished instances leave 0.
+static_assert(kBlock == (kTileMin << kNormOpt), "a norm tile is one workgroup of kBlock points");
 __global__ __launch_bounds__(kBlock) void kb_norm(const BSeg *segs, int nseg,
                                                   unsigned long long *partial) {
-    unsigned lb;
-    const int s = bseg_find(segs, nseg, BK_NORM, lb);
-    if (s < 0) return;
-    const BSeg &g = segs[s];
-    const unsigned t = lb * kBlock + threadIdx.x;
+    unsigned local;
+    const BSeg &g = segs[bseg_of_tile(segs, nseg, BK_NORM, kNormOpt, blockIdx.x, local)];
+    const unsigned t = local * kBlock + threadIdx.x;
     unsigned long long m = 0;
     if (*g.active && t < bseg_count(g, BK_NORM))
         m = resid_bits<double, false>(g.op, cst(g.u), cst(g.f), g.phk, nullptr,
@@ -1265,36 +1264,54 @@ __global__ __launch_bounds__(kBlock) void kb_reset(BState st, int count, int **v
     *valid[i] = 0;
 }
 
-void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned blocks, int block,
-                  int colour, int picard) {
+template <int KIND>
+static void launch_kind(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles, int opt,
+                        int threads, unsigned grid, int arg0, int arg1) {
+    if (grid)
+        hipLaunchKernelGGL((kb_phase<KIND, true>), dim3(grid), dim3(threads), 0, s, segs, nseg, ntiles,
+                           opt, arg0, arg1);
+    else
+        hipLaunchKernelGGL((kb_phase<KIND, false>), dim3(std::max(ntiles, 1u)), dim3(threads), 0, s,
+                           segs, nseg, ntiles, opt, arg0, arg1);
+}
+
+void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned ntiles, int opt,
+                  int threads, unsigned slots, int arg0, int arg1) {
+    // persistent: at most the resident workgroups, at most one per tile
+    const unsigned grid = slots ? std::max(1u, std::min(slots, ntiles)) : 0u;
     switch (kind) {
-        case BK_SMOOTH:
-            hipLaunchKernelGGL(kb_smooth, dim3(blocks), dim3(block), 0, s, segs, nseg, colour, picard);
-            break;
-        case BK_RR:
-            hipLaunchKernelGGL(kb_resid_restrict, dim3(blocks), dim3(block), 0, s, segs, nseg);
-            break;
-        case BK_TAU:
-            hipLaunchKernelGGL(kb_tau, dim3(blocks), dim3(block), 0, s, segs, nseg);
-            break;
-        case BK_PROLONG:
-            // colour: 1 when a smoothing sweep follows (colour-0 mu, omega dead)
-            hipLaunchKernelGGL(kb_prolong, dim3(blocks), dim3(block), 0, s, segs, nseg, colour);
-            break;
-        case BK_ERR:
-            hipLaunchKernelGGL(kb_coarse_err, dim3(blocks), dim3(block), 0, s, segs, nseg);
-            break;
+        case BK_SMOOTH: launch_kind<BK_SMOOTH>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
+        case BK_RR: launch_kind<BK_RR>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
+        case BK_TAU: launch_kind<BK_TAU>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
+        case BK_ERR: launch_kind<BK_ERR>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
+        case BK_PROLONG: launch_kind<BK_PROLONG>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
         default: break;
     }
+}
+
+int batch_phase_slots(int kind, int threads, int device) {
+    const void *fn = nullptr;
+    switch (kind) {
+        case BK_SMOOTH: fn = (const void *)kb_phase<BK_SMOOTH, true>; break;
+        case BK_RR: fn = (const void *)kb_phase<BK_RR, true>; break;
+        case BK_TAU: fn = (const void *)kb_phase<BK_TAU, true>; break;
+        case BK_ERR: fn = (const void *)kb_phase<BK_ERR, true>; break;
+        default: fn = (const void *)kb_phase<BK_PROLONG, true>; break;
+    }
+    int occ = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    return occ * cus;
 }
 
 void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg) {
     hipLaunchKernelGGL(kb_coarse, dim3(nseg), dim3(64), 0, s, segs, nseg);
 }
 
-void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned blocks,
+void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles,
                        unsigned long long *partial, BState st, double tol, int max_cycles) {
-    hipLaunchKernelGGL(kb_norm, dim3(blocks), dim3(kBlock), 0, s, segs, nseg, partial);
+    hipLaunchKernelGGL(kb_norm, dim3(std::max(ntiles, 1u)), dim3(kBlock), 0, s, segs, nseg, partial);
     hipLaunchKernelGGL(kb_update, dim3(nseg), dim3(kBlock), 0, s, segs, nseg,
                        (const unsigned long long *)partial, st, tol, max_cycles);
 }

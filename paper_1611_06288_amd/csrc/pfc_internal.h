@@ -230,7 +230,10 @@ void launch_zero(hipStream_t s, float *p, size_t count);
 
 
 // ---- batched form ----
-enum { BK_SMOOTH = 0, BK_RR = 1, BK_TAU = 2, BK_PROLONG = 3, BK_NORM = 4, BK_ERR = 5 };
+enum { BK_SMOOTH = 0, BK_RR = 1, BK_TAU = 2, BK_PROLONG = 3, BK_ERR = 4, BK_NORM = 5, BK_KINDS = 6 };
+// batched tile sizes: kTileMin << opt work items, opt < kTileOpts (64 .. 4096);
+// the stop test's norm uses opt kNormOpt (one workgroup of kBlock points)
+constexpr int kTileMin = 64, kTileOpts = 7, kNormOpt = 2;
 
 // One instance on one level, as seen by a batched launch.
 struct BSeg {
@@ -244,10 +247,11 @@ struct BSeg {
     int *valid, *iters;
     const int *active;           // the instance's convergence flag
     int inst;
-    // first workgroup of this segment in a launch over its list, per launch
-    // kind and workgroup size (64, 128, 256, 512): segments are padded to
-    // whole workgroups, so a workgroup finds its segment by binary search
-    unsigned first[6][4];
+    // first tile of this segment in the work-list of a launch over its list,
+    // per phase kind and tile size (kTileMin << opt work items): segments are
+    // padded to whole tiles, so a workgroup finds a tile's segment by binary
+    // search
+    unsigned first[BK_KINDS][kTileOpts];
 };
 
 // Per-instance state of the batched stop test (device arrays).
@@ -257,12 +261,18 @@ struct BState {
     const unsigned *norm_first, *norm_blocks;  // per finest-level segment
 };
 
-// colour: the half-sweep's colour (BK_SMOOTH); for BK_PROLONG 1 when a
-// smoothing sweep follows, so colour-0 mu, omega are left unwritten
-void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned blocks, int block,
-                  int colour, int picard);
+// One launch of a batched phase over `ntiles` tiles of kTileMin << opt work
+// items, `threads` per workgroup: one tile per workgroup (slots = 0) or
+// persistent, at most `slots` workgroups walking the tiles.  arg0,
+// arg1: the half-sweep's colour and picard flag (BK_SMOOTH); for BK_PROLONG
+// arg0 = 1 when a smoothing sweep follows (colour-0 mu, omega left
+// unwritten).
+void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned ntiles, int opt,
+                  int threads, unsigned slots, int arg0, int arg1);
+// Resident workgroups of a phase kind's kernel at `threads` per workgroup.
+int batch_phase_slots(int kind, int threads, int device);
 void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg);
-void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned blocks,
+void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles,
                        unsigned long long *partial, BState st, double tol, int max_cycles);
 void launch_batch_reset(hipStream_t s, BState st, int count, int **valid);
 

@@ -339,8 +339,10 @@ class Batch:
                  for k in range(steps)] for i in range(self.count)]
 
     def autotune(self, cache_path=None):
-        """Workgroup sizes of (smooth, residual+coarsening, tau, interpolation)."""
-        chosen = (C.c_int32 * 4)()
+        """Schedules and tile shapes of (smooth, residual+coarsening, tau,
+        interpolation, coarse error): a list of five (persistent, threads per
+        workgroup, tile work items) triples."""
+        chosen = (C.c_int32 * 15)()
         path = None if cache_path is None else str(cache_path).encode()
         self._check(self.lib.pfc_batch_autotune(self._b, path, chosen))
-        return list(chosen)
+        return [(bool(chosen[3 * k]), chosen[3 * k + 1], chosen[3 * k + 2]) for k in range(5)]

@@ -53,10 +53,12 @@ def test_batch_instance_matches_oracle_and_autotune_keeps_results(tmp_path):
     from paper_1611_06288_amd.solver import Batch
     ens = small_ensemble()[:5]
     steps = 2
-    b = Batch(ens, tol=1e-10)                          # default workgroup sizes
+    b = Batch(ens, tol=1e-10)                          # default tile shapes
     b2 = Batch(ens, tol=1e-10)
     tiles = b2.autotune(cache_path=tmp_path / "tiles.json")
-    assert all(t in (64, 128, 256, 512) for t in tiles)
+    assert len(tiles) == 5
+    assert all(th in (64, 128, 256, 512) and items in (64 << k for k in range(7)) and items >= th
+               for _, th, items in tiles)
     assert (tmp_path / "tiles.json").exists()
     b3 = Batch(ens, tol=1e-10)
     assert b3.autotune(cache_path=tmp_path / "tiles.json") == tiles   # read back from the cache
