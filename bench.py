@@ -39,12 +39,13 @@ HBM_PEAK_GBS = 8000.0
 # plain without the dead colour-0 writes, and norm-carrying post-sweeps) scaled
 # by what the same counters read for a 1 GiB device copy (FETCH x 2.0,
 # WRITE x 1.0).  Valid only for the smoother sources
-# it was measured on (first 16 hex digits of the sha256 of smooth.hip, smooth.h
-# and device_common.h, concatenated); otherwise reported null.
-SMOOTHER_TRAFFIC = {"sources_sha256_16": "c5d3a19dcacf4126", "n": 256,
-                    "fetch_KiB": 466213, "write_KiB": 351504,
+# it was measured on (first 16 hex digits of the sha256 of smooth.hip, smooth.h,
+# device_common.h and runtime.cpp, which chooses the buffers the sweeps read,
+# concatenated); otherwise reported null.
+SMOOTHER_TRAFFIC = {"sources_sha256_16": "799469a3eeb2535e", "n": 256,
+                    "fetch_KiB": 362280, "write_KiB": 350132,
                     "fetch_scale": 2.0, "write_scale": 1.0}
-SMOOTHER_SOURCES = ("smooth.hip", "smooth.h", "device_common.h")
+SMOOTHER_SOURCES = ("smooth.hip", "smooth.h", "device_common.h", "runtime.cpp")
 METRIC = "time-steps/s & V-cycles/s at 256^3 (FP64 vs mixed); smoother HBM GB/s %peak"
 # (m0, m1, m2, mmin) of the variable-mobility run: M(v) = max(0.05, 1 - v^2)
 MOBILITY = (1.0, 0.0, -1.0, 0.05)

@@ -159,7 +159,7 @@ static pfc_status mixed_step_on(pfc_handle *H, const double *phi_prev, const dou
         int cnt;
         if (A.rt) {
             ResidTileArgs ra;
-            ra.f = cst(A.f);
+            ra.f = frhs(H, 0);
             ra.phk = A.phk;
             ra.r32 = A32.f;
             ra.base32 = A32.base;
@@ -177,7 +177,7 @@ static pfc_status mixed_step_on(pfc_handle *H, const double *phi_prev, const dou
             }
         } else {
             if (pending) launch_add_correction(H->stream, A.P, A.u, cst(A32.e));
-            cnt = launch_resid_cast(H->stream, op_of(H, 0), cst(A.u), cst(A.f), A.phk, A32.f,
+            cnt = launch_resid_cast(H->stream, op_of(H, 0), cst(A.u), frhs(H, 0), A.phk, A32.f,
                                     A32.base, H->partial);
         }
         pending = false;
@@ -248,16 +248,21 @@ static pfc_status mixed_step_on(pfc_handle *H, const double *phi_prev, const dou
 // plus the base).  The mixed form's FP64 defect pass reads u, f, phi^k and
 // writes r and phi in FP32 (72 B); on column-tile levels it also reads the
 // pending FP32 correction and writes u + e (108 B), which is all but the
-// first pass of each step, so 108 is credited there.
+// first pass of each step, so 108 is credited there.  In a time step the
+// first component of f is phi^k itself and is read from phk (f1_phk), so
+// every FP64 pass over the finest level reads 8 B per point of f fewer (4 B
+// per point of the level for a half-sweep, which reads f at its own colour).
 double algorithmic_bytes(const pfc_handle *H, int kernel) {
     const double P = (double)H->lev[0].P;
     const bool mixed = H->cfg.precision == PFC_MIXED;
     // variable mobility (FP64 only) reads phi* once more: 8 B/pt per pass
     const double mob = H->cfg.mobility == PFC_MOBILITY_QUADRATIC ? 8.0 : 0.0;
-    const double smooth = mixed ? 24.0 : (H->lev[0].fused ? 72.0 : 44.0) + mob;
+    const double f1 = H->f1_phk ? 8.0 : 0.0;  // f.a not streamed
+    const double smooth =
+        mixed ? 24.0 : (H->lev[0].fused ? 72.0 - f1 : 44.0 - 0.5 * f1) + mob;
     switch (kernel) {
         case PFC_KERNEL_SMOOTH0: return smooth * P;
-        case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0 + mob) * P;
+        case PFC_KERNEL_RESIDUAL0: return (mixed ? 35.0 : 62.0 - f1 + mob) * P;
         // interpolation: u read and written where it is live after it (all
         // phi, colour-1 mu and omega: 2 x 2 fields' worth when a post-sweep
         // follows, else all three), plus the coarse v and ubar it forms the
@@ -266,9 +271,10 @@ double algorithmic_bytes(const pfc_handle *H, int kernel) {
             const double fine = H->cfg.nu2 >= 1 ? 2.0 : 3.0;
             return (mixed ? 2 * 4.0 * fine + 3.0 : 2 * 8.0 * fine + 6.0) * P;
         }
-        case PFC_KERNEL_NORM0: return (mixed ? (H->lev[0].rt ? 108.0 : 72.0) : 56.0 + mob) * P;
+        case PFC_KERNEL_NORM0:
+            return (mixed ? (H->lev[0].rt ? 108.0 : 72.0) - f1 : 56.0 - f1 + mob) * P;
         // the fused sweep's 72 (80 with phi*) plus old mu and omega of the colour-0 points
-        case PFC_KERNEL_SWEEP_NORM0: return H->split_norm ? (80.0 + mob) * P : 0.0;
+        case PFC_KERNEL_SWEEP_NORM0: return H->split_norm ? (80.0 - f1 + mob) * P : 0.0;
         default: return 0.0;
     }
 }

@@ -230,7 +230,7 @@ void sweep64(pfc_handle *H, int l, int nrm, bool from_ubar, bool then_sweep) {
         // the colour-0 mu, omega writes left out: 8 B/pt fewer
         H->begin_timed(kind, l, skip0 ? algorithmic_bytes(H, kind) - 8.0 * (double)A.P : -1.0);
         launch_sweep_fused<double, false>(H->stream, op, H->cfg.lin == PFC_LIN_PICARD, A.nz,
-                                          from_ubar ? cst(A.ubar) : cst(A.u), A.u2, cst(A.f), A.phk,
+                                          from_ubar ? cst(A.ubar) : cst(A.u), A.u2, frhs(H, l), A.phk,
                                           nullptr, nrm, part, skip0);
         H->end_timed();
         std::swap(A.u, A.u2);
@@ -239,14 +239,14 @@ void sweep64(pfc_handle *H, int l, int nrm, bool from_ubar, bool then_sweep) {
     if (A.n <= kSmallSweepN) {  // both colours in one workgroup
         H->begin_timed(PFC_KERNEL_SMOOTH0, l);
         launch_sweep_small<double, false>(H->stream, op, H->cfg.lin == PFC_LIN_PICARD, A.u,
-                                          cst(A.f), A.phk, nullptr);
+                                          frhs(H, l), A.phk, nullptr);
         H->end_timed();
         return;
     }
     for (int colour = 0; colour < 2; ++colour) {
         H->begin_timed(PFC_KERNEL_SMOOTH0, l);
         launch_smooth<double, false>(H->stream, op, colour, H->cfg.lin == PFC_LIN_PICARD, A.u,
-                                     cst(A.f), A.phk, nullptr);
+                                     frhs(H, l), A.phk, nullptr);
         H->end_timed();
     }
 }
@@ -268,14 +268,14 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
     if (A.rt) {
         ResidTileArgs ra;
         ra.u = cst(A.u);
-        ra.f = cst(A.f);
+        ra.f = frhs(H, l);
         ra.phk = A.phk;
         ra.LC = B.lay;
         ra.ubar = B.ubar;
         ra.rr = B.f;
         launch_resid_tile(H->stream, RT_RESTRICT, op_of(H, l), A.rt_nz[RT_RESTRICT], ra);
     } else {
-        launch_resid_restrict<double, false>(H->stream, op_of(H, l), B.lay, cst(A.u), cst(A.f),
+        launch_resid_restrict<double, false>(H->stream, op_of(H, l), B.lay, cst(A.u), frhs(H, l),
                                              A.phk, nullptr, B.ubar, B.f);
     }
     H->end_timed();
@@ -333,12 +333,12 @@ static int enqueue_norm(pfc_handle *H, Tri<double> r, unsigned long long *dst = 
     if (A.rt && A.n >= kTileNormMinN && !r.a) {
         ResidTileArgs ra;
         ra.u = cst(A.u);
-        ra.f = cst(A.f);
+        ra.f = frhs(H, 0);
         ra.phk = A.phk;
         ra.partial = dst;
         cnt = launch_resid_tile(H->stream, RT_NORM, op_of(H, 0), A.rt_nz[RT_NORM], ra);
     } else {
-        cnt = launch_resid_max<double, false>(H->stream, op_of(H, 0), cst(A.u), cst(A.f), A.phk,
+        cnt = launch_resid_max<double, false>(H->stream, op_of(H, 0), cst(A.u), frhs(H, 0), A.phk,
                                               nullptr, r, dst);
     }
     H->end_timed();
@@ -383,6 +383,7 @@ void step_begin(pfc_handle *H, const double *phi_prev, const double *phi_cur, co
     launch_source(H->stream, op_of(H, 0), phi_cur, phi_prev, A.f);
     to_level0(H, phi_cur, mu, omega);
     launch_to_lay<double, double>(H->stream, A.lay, phi_cur, A.phk, 1);
+    H->f1_phk = true;  // f.a and phk now hold the same phi^k
     restrict_phk(H);
     if (mobility_on(H)) {
         launch_phistar(H->stream, A.lay, phi_cur, phi_prev, A.phs);
@@ -625,6 +626,7 @@ extern "C" {
 pfc_status pfc_fas_vcycle(pfc_handle *h, double *u3, const double *f3, const double *phi_cur,
                           double *res_after) {
     if (!h) return PFC_ERR_INVALID_ARG;
+    h->f1_phk = false;  // the caller's right-hand side goes into f
     if (!u3 || !f3 || !phi_cur) return fail(h, PFC_ERR_INVALID_ARG, "NULL field pointer");
     if (mobility_on(h) && !h->lev[0].phs_set)
         return fail(h, PFC_ERR_INVALID_ARG, "variable mobility: phi* not set at level 0");
@@ -680,6 +682,7 @@ pfc_status pfc_source(pfc_handle *h, const double *phi_prev, const double *phi_c
 pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const double *f3,
                         const double *phk, double *r3, double *maxnorm) {
     if (!h) return PFC_ERR_INVALID_ARG;
+    h->f1_phk = false;  // the caller's right-hand side goes into f
     if (!level_ok(h, level) || !u3 || !f3 || !phk) return fail(h, PFC_ERR_INVALID_ARG, "bad argument");
     if (mobility_on(h) && !h->lev[level].phs_set)
         return fail(h, PFC_ERR_INVALID_ARG, "variable mobility: phi* not set at this level");
@@ -713,6 +716,7 @@ pfc_status pfc_residual(pfc_handle *h, int32_t level, const double *u3, const do
 pfc_status pfc_smooth(pfc_handle *h, int32_t level, int32_t colour, double *u3, const double *f3,
                       const double *phk) {
     if (!h) return PFC_ERR_INVALID_ARG;
+    h->f1_phk = false;  // the caller's right-hand side goes into f
     if (!level_ok(h, level) || colour < 0 || colour > PFC_SWEEP_FULL || !u3 || !f3 || !phk ||
         !h->lev[level].lay.split)
         return fail(h, PFC_ERR_INVALID_ARG, "bad argument (level must be a smoothed level)");

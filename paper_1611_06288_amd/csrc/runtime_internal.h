@@ -80,6 +80,11 @@ struct pfc_handle {
     // pre-sweep, run ahead of the decision, the colour-0 half in
     // partial[0 .. split_blocks)
     bool split_norm = false;
+    // Set by a time step's set-up: the finest level's f.a holds phi^k, a copy
+    // of phk (the first component of S is phi^k itself), so the finest-level
+    // kernels read phk in its place (see frhs).  Cleared by the entry points
+    // that load a caller's right-hand side into the finest level.
+    bool f1_phk = false;
     int split_blocks = 0;
     // graph-driven time loop (pfc_run)
     const int *gate = nullptr;            // cycle gate, set only while its graph is recorded
@@ -119,6 +124,17 @@ constexpr unsigned kCyclePostNorm = 2;  // its last post-sweep leaves the colour
 constexpr unsigned kCycleFromUbar = 4;  // (fused level) the iterate is still in ubar: the
                                         // first pre-sweep reads it there
 void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags = 0);
+// Level l's right-hand side as its kernels read it.  In a time step the
+// first component of the finest level's S is phi^k itself (scheme-PFC-s1),
+// held bitwise in both f.a and phk; reading it from phk spares the kernels a
+// second 8-byte stream per point (the fused sweep, the residual passes and
+// the FP64 defect pass).
+inline Tri<const double> frhs(const pfc_handle *H, int l) {
+    const Level &A = H->lev[l];
+    if (l == 0 && H->f1_phk) return Tri<const double>{A.phk, A.f.b, A.f.c};
+    return Tri<const double>{A.f.a, A.f.b, A.f.c};
+}
+
 // One smoothing sweep of level l; nrm as in launch_sweep_fused (split_norm
 // only); from_ubar: a fused sweep reading its input from the level's ubar;
 // then_sweep: the next operation on the iterate is another sweep of this
