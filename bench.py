@@ -258,9 +258,9 @@ def run_batched(torch, inputs, steps, warmup=1):
         "v_cycles_per_s_summed": round(sum(cyc) / dt, 2),
         "mean_cycles_per_instance_step": round(sum(cyc) / (len(ens) * steps), 2),
         "max_cycles_per_step": max(max(x.cycles for x in row) for row in infos),
-        "autotuned_schedule_threads_items": dict(zip(
+        "autotuned_schedule_threads_w_z": dict(zip(
             ["smooth", "resid_restrict", "tau", "prolong", "coarse_err"],
-            [["persistent" if p else "per-tile", th, it] for p, th, it in tiles])),
+            [["persistent" if p else "per-tile", th, w, z] for p, th, w, z in tiles])),
     }
 
 
@@ -547,7 +547,7 @@ def main():
     sm = fp64["kernels"].get("smooth0", {})
     achieved = sm.get("achieved_GBps")
     roofline = {
-        "kernel": ("finest-level fused red-black sweep (one full sweep per launch; 72 B/pt, 64 "
+        "kernel": ("finest-level fused red-black sweep (one full sweep per launch; 64 B/pt, 56 "
                    "where the next sweep makes colour-0 mu, omega dead; mean over launches)"),
         "bound": "hbm",
         "achieved": achieved,

@@ -327,15 +327,15 @@ pfc_status pfc_batch_run(pfc_batch *b, int32_t steps, pfc_step_info *infos);
 /* Chooses, for each batched phase kind (smoothing, residual+coarsening, tau,
  * interpolation, coarse error), its schedule and tile shape by timing every
  * combination on this batch: one tile per workgroup or persistent (as many
- * workgroups as are resident walk the work-list), 64, 128, 256 or 512
- * threads per workgroup, and tiles of 64 .. 4096 consecutive work items
- * (rows of half-sweep points, coarse cells, fine x-pairs or points: a slab
- * of rows and planes of one instance).  With cache_path (nullable) choices
- * are read from / written to a JSON file keyed by GPU architecture,
- * instance sizes and phase.  chosen (host, nullable): 15 ints, (persistent,
- * threads, tile items) per phase in that order.  Results do not depend on
- * the choice (same per-point arithmetic).  Leaves the state unchanged.
- * Synchronises. */
+ * workgroups as are resident walk the work-list), 64, 128 or 256 threads per
+ * workgroup, and tiles of W = 64 .. 1024 consecutive work items of a plane
+ * (half-sweep points, coarse cells, fine x-pairs or points, in the level's
+ * storage order) over Z = 1 .. 8 consecutive planes, walked plane by plane.
+ * With cache_path (nullable) choices are read from / written to a JSON file
+ * keyed by GPU architecture, instance sizes and phase.  chosen (host,
+ * nullable): 20 ints, (persistent, threads, W, Z) per phase in that order.
+ * Results do not depend on the choice (same per-point arithmetic).  Leaves
+ * the state unchanged.  Synchronises. */
 pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *chosen);
 const char *pfc_batch_last_error(const pfc_batch *b);
 

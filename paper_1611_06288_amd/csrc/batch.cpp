@@ -44,11 +44,11 @@ struct pfc_batch {
     int *h_stats = nullptr; // pinned: cycles, status per instance
     double *h_res = nullptr;  // pinned: res0, res per instance
     // per phase kind (smooth, residual + coarsening, tau, interpolation,
-    // coarse error): threads per workgroup, tile size kTileMin << opt work
-    // items, schedule (persistent or one tile per workgroup) and, when
-    // persistent, the resident workgroups at that size
+    // coarse error): threads per workgroup, tile shape (see kShapes; default
+    // 256 items of one plane), schedule (persistent or one tile per
+    // workgroup) and, when persistent, the resident workgroups at that size
     int threads[5] = {256, 256, 256, 256, 256};
-    int opt[5] = {2, 2, 2, 2, 2};
+    int shape[5] = {2, 2, 2, 2, 2};
     bool persist[5] = {false, false, false, false, false};
     unsigned slots[5] = {0, 0, 0, 0, 0};
     hipGraph_t graph = nullptr;
@@ -96,16 +96,22 @@ unsigned seg_count(const BSeg &g, int kind) {
     }
 }
 
-// Tiles of kTileMin << opt work items in a launch of `kind` over the list v.
-unsigned tiles_of(const std::vector<BSeg> &v, int kind, int opt) {
-    const unsigned items = (unsigned)kTileMin << opt;
+// Tiles of shape `shape` in a launch of `kind` over the list v.
+unsigned seg_tiles(const BSeg &g, int kind, int shape) {
+    const unsigned W = (unsigned)kTileMin << (shape % kWOpts), Z = 1u << (shape / kWOpts);
+    unsigned Q, NPL;
+    bseg_planes_host(g, kind, Q, NPL);
+    return ((Q + W - 1) / W) * ((NPL + Z - 1) / Z);
+}
+
+unsigned tiles_of(const std::vector<BSeg> &v, int kind, int shape) {
     unsigned b = 0;
-    for (const auto &g : v) b += (seg_count(g, kind) + items - 1) / items;
+    for (const auto &g : v) b += seg_tiles(g, kind, shape);
     return b;
 }
 
 void phase(pfc_batch *B, int kind, const std::vector<BSeg> &h, BSeg *d, int arg0, int arg1) {
-    launch_batch(B->stream, kind, d, (int)h.size(), tiles_of(h, kind, B->opt[kind]), B->opt[kind],
+    launch_batch(B->stream, kind, d, (int)h.size(), tiles_of(h, kind, B->shape[kind]), B->shape[kind],
                  B->threads[kind], B->persist[kind] ? B->slots[kind] : 0u, arg0, arg1);
 }
 
@@ -343,12 +349,11 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
         }
         std::vector<BSeg> w = v;  // with this list's first tiles
         for (int kind = 0; kind < BK_KINDS; ++kind)
-            for (int opt = 0; opt < kTileOpts; ++opt) {
-                const unsigned items = (unsigned)kTileMin << opt;
+            for (int sh = 0; sh < kShapes; ++sh) {
                 unsigned acc = 0;
                 for (auto &g : w) {
-                    g.first[kind][opt] = acc;
-                    acc += (seg_count(g, kind) + items - 1) / items;
+                    g.first[kind][sh] = acc;
+                    acc += seg_tiles(g, kind, sh);
                 }
             }
         return balloc(B, d, w.size()) &&
@@ -367,7 +372,7 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
     unsigned acc = 0;
     for (int s = 0; s < count; ++s) {
         first[s] = acc;
-        nblk[s] = (seg_count(B->h_all[0][s], BK_NORM) + kBlock - 1) / kBlock;  // norm tiles
+        nblk[s] = seg_tiles(B->h_all[0][s], BK_NORM, kNormShape);
         acc += nblk[s];
     }
     B->norm_blocks = acc;
@@ -471,27 +476,27 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
     hipEvent_t t0, t1;
     (void)hipEventCreate(&t0);
     (void)hipEventCreate(&t1);
-    // a choice is stored as persistent * 100000 + threads * 10 + opt
-    auto decode = [](int code, bool &ps, int &th, int &o) {
+    // a choice is stored as persistent * 100000 + threads * 100 + shape
+    auto decode = [](int code, bool &ps, int &th, int &sh) {
         ps = code / 100000 != 0;
-        th = (code % 100000) / 10;
-        o = code % 10;
-        return (th == 64 || th == 128 || th == 256 || th == 512) && o < kTileOpts &&
-               (kTileMin << o) >= th;
+        th = (code % 100000) / 100;
+        sh = code % 100;
+        return (th == 64 || th == 128 || th == 256 || th == 512) && sh < kShapes &&
+               (kTileMin << (sh % kWOpts)) >= th;
     };
-    auto apply = [&](int kind, bool ps, int th, int o) {
+    auto apply = [&](int kind, bool ps, int th, int sh) {
         b->persist[kind] = ps;
         b->threads[kind] = th;
-        b->opt[kind] = o;
+        b->shape[kind] = sh;
         b->slots[kind] = ps ? (unsigned)batch_phase_slots(kind, th, dev) : 0u;
     };
     for (int kind = 0; kind < 5; ++kind) {
         const std::string key = sig.str() + "|" + kind_name[kind];
         auto it = cache.find(key);
         bool ps;
-        int th, o;
-        if (it != cache.end() && decode(it->second, ps, th, o)) {
-            apply(kind, ps, th, o);
+        int th, sh;
+        if (it != cache.end() && decode(it->second, ps, th, sh)) {
+            apply(kind, ps, th, sh);
             continue;
         }
         const int d = kind == BK_TAU ? 1 : 0;
@@ -499,18 +504,19 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
         const auto &segs = kind == BK_TAU ? b->h_all[1] : b->h_mid[0];
         BSeg *dsegs = kind == BK_TAU ? b->d_all[1] : b->d_mid[0];
         float best = 1e30f;
-        int best_code = 256 * 10 + 2;
+        int best_code = 256 * 100 + 2;
         // the interpolation is timed in the form the cycle runs
         const int pflag = b->cfg.nu2 >= 1 ? 1 : 0;
         for (int persistent = 0; persistent < 2; ++persistent)
-            for (int thr : {64, 128, 256, 512}) {
+            for (int thr : {64, 128, 256}) {
                 const unsigned sl = persistent ? (unsigned)batch_phase_slots(kind, thr, dev) : 0u;
                 if (persistent && sl == 0) continue;
-                for (int op = 0; op < kTileOpts; ++op) {
-                    if ((kTileMin << op) < thr) continue;
-                    const unsigned nt = tiles_of(segs, kind, op);
+                for (int sp = 0; sp < kShapes; ++sp) {
+                    if ((kTileMin << (sp % kWOpts)) < thr) continue;
+                    if (kind == BK_ERR && sp >= kWOpts) continue;  // one plane: Z is moot
+                    const unsigned nt = tiles_of(segs, kind, sp);
                     auto run = [&](int rep) {
-                        launch_batch(b->stream, kind, dsegs, (int)segs.size(), nt, op, thr, sl,
+                        launch_batch(b->stream, kind, dsegs, (int)segs.size(), nt, sp, thr, sl,
                                      kind == BK_PROLONG ? pflag : rep & 1, 0);
                     };
                     for (int rep = 0; rep < 2; ++rep) run(rep);
@@ -522,12 +528,12 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
                     (void)hipEventElapsedTime(&ms, t0, t1);
                     if (ms < best) {
                         best = ms;
-                        best_code = persistent * 100000 + thr * 10 + op;
+                        best_code = persistent * 100000 + thr * 100 + sp;
                     }
                 }
             }
-        decode(best_code, ps, th, o);
-        apply(kind, ps, th, o);
+        decode(best_code, ps, th, sh);
+        apply(kind, ps, th, sh);
         cache[key] = best_code;
         changed = true;
     }
@@ -539,9 +545,10 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
     b->graph_ready = false;  // recapture with the chosen tiles
     if (chosen)
         for (int k = 0; k < 5; ++k) {
-            chosen[3 * k] = b->persist[k] ? 1 : 0;
-            chosen[3 * k + 1] = b->threads[k];
-            chosen[3 * k + 2] = kTileMin << b->opt[k];
+            chosen[4 * k] = b->persist[k] ? 1 : 0;
+            chosen[4 * k + 1] = b->threads[k];
+            chosen[4 * k + 2] = kTileMin << (b->shape[k] % kWOpts);
+            chosen[4 * k + 3] = 1 << (b->shape[k] / kWOpts);
         }
     return PFC_OK;
 }

@@ -1121,45 +1121,85 @@ void launch_zero(hipStream_t s, float *p, size_t count) {
 //
 // Every multigrid phase of the batched cycle is one launch over all
 // instances that take part in it.  Each instance's part of the phase (its
-// "segment") is cut into tiles of a fixed number of consecutive work items
-// (half-sweep points, coarse cells, fine x-pairs, points: a slab of rows and
-// planes of one instance); the tiles of all segments form one work-list, in
-// segment order.  Two schedules walk it:
+// "segment": half-sweep points of one colour, coarse cells, fine x-pairs or
+// points) is seen as planes of work items in z, and cut into tiles of W
+// consecutive items of a plane in Z consecutive planes, walked plane by
+// plane, so the neighbouring planes a stencil reads are reused while they
+// are still cached; the tiles of all segments form one work-list, in segment
+// order.  Two schedules walk it:
 //   * one tile per workgroup, the hardware dispatcher handing out tiles
 //     (PERSIST = false: grid = tile count);
 //   * persistent: only as many workgroups as are resident at once, each
 //     taking every gridDim.x-th tile (PERSIST = true).
 // A workgroup finds a tile's segment by a binary search over the segments'
-// first tiles (precomputed for every tile size) and skips tiles of instances
-// whose convergence flag is cleared.  Schedule, tile size and workgroup size
-// are per phase kind, chosen by the batch's autotuner.  The per-item
-// arithmetic is that of the single-instance kernels, so the schedule does
-// not change any result.
+// first tiles (precomputed for every tile shape) and skips tiles of
+// instances whose convergence flag is cleared.  Schedule, tile shape and
+// workgroup size are per phase kind, chosen by the batch's autotuner.  The
+// per-item arithmetic is that of the single-instance kernels, so neither
+// changes any result.
 
-__device__ __forceinline__ unsigned bseg_count(const BSeg &g, int kind) {
-    const unsigned n = (unsigned)g.op.lay.n, P = n * n * n;
+// Q items per plane and NPL planes of a segment's work (item = plane * Q +
+// position), in the bodies' own item orders: a half-sweep's points of one
+// colour (planes k), coarse cells and fine x-pairs in natural order (planes
+// K and k), the points of a colour-split level colour-major (2n planes of
+// n * n/2, else n planes of n * n), and the pointwise coarse error as one
+// plane.
+__host__ __device__ __forceinline__ void bseg_planes(const BSeg &g, int kind, unsigned &Q,
+                                                     unsigned &NPL) {
+    const unsigned n = (unsigned)g.op.lay.n, nc = (unsigned)g.lay_c.n;
     switch (kind) {
-        case BK_SMOOTH: return P / 2;
-        case BK_RR:
-        case BK_ERR: return (unsigned)(g.lay_c.n * g.lay_c.n * g.lay_c.n);
-        case BK_PROLONG: return (unsigned)g.lay_c.n * n * n;
-        default: return P;  // BK_TAU, BK_NORM
+        case BK_SMOOTH: Q = n * (n / 2); NPL = n; break;
+        case BK_RR: Q = nc * nc; NPL = nc; break;
+        case BK_PROLONG: Q = nc * n; NPL = n; break;
+        case BK_ERR: Q = nc * nc * nc; NPL = 1; break;
+        default:  // BK_TAU, BK_NORM: the level's storage order
+            if (g.op.lay.split) {
+                Q = n * (n / 2);
+                NPL = 2 * n;
+            } else {
+                Q = n * n;
+                NPL = n;
+            }
     }
 }
 
-// Segment holding work-list tile `tile` (tiles of kTileMin << opt items).
-__device__ __forceinline__ int bseg_of_tile(const BSeg *segs, int nseg, int kind, int opt,
+void bseg_planes_host(const BSeg &g, int kind, unsigned &Q, unsigned &NPL) {
+    bseg_planes(g, kind, Q, NPL);
+}
+
+// Segment holding work-list tile `tile` for tile shape `shape`.
+__device__ __forceinline__ int bseg_of_tile(const BSeg *segs, int nseg, int kind, int shape,
                                             unsigned tile, unsigned &local) {
     int lo = 0, hi = nseg - 1;  // the last segment whose first tile is <= tile
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (segs[mid].first[kind][opt] <= tile)
+        if (segs[mid].first[kind][shape] <= tile)
             lo = mid;
         else
             hi = mid - 1;
     }
-    local = tile - segs[lo].first[kind][opt];
+    local = tile - segs[lo].first[kind][shape];
     return lo;
+}
+
+// Item range of one tile of a segment: planes [z0, z1), positions [w0, w1).
+struct TileSpan {
+    unsigned Q, z0, z1, w0, w1;
+};
+
+__device__ __forceinline__ TileSpan tile_span(const BSeg &g, int kind, int shape, unsigned local) {
+    const unsigned W = (unsigned)kTileMin << (shape % kWOpts), Z = 1u << (shape / kWOpts);
+    unsigned Q, NPL;
+    bseg_planes(g, kind, Q, NPL);
+    const unsigned nw = (Q + W - 1) / W;
+    const unsigned pz = local / nw, pw = local - pz * nw;
+    TileSpan sp;
+    sp.Q = Q;
+    sp.z0 = pz * Z;
+    sp.z1 = min(sp.z0 + Z, NPL);
+    sp.w0 = pw * W;
+    sp.w1 = min(sp.w0 + W, Q);
+    return sp;
 }
 
 template <int KIND>
@@ -1174,24 +1214,24 @@ __device__ __forceinline__ void kb_item(const BSeg &g, unsigned i, int arg0, int
     } else if constexpr (KIND == BK_ERR) {  // coarse error v - I u, stored over I u
         coarse_err_body<double>(npts(g.lay_c), cst(g.uc), g.ubarc, i);
     } else {  // BK_PROLONG: adds the interpolated coarse error
-        prolong_body<double>(g.lay_c, g.op.lay, cst(g.ubarc), Tri<const double>{nullptr, nullptr, nullptr},
-                             g.u, i, arg0 != 0);
+        prolong_body<double>(g.lay_c, g.op.lay, cst(g.ubarc),
+                             Tri<const double>{nullptr, nullptr, nullptr}, g.u, i, arg0 != 0);
     }
 }
 
 // arg0, arg1: colour and picard (BK_SMOOTH); 1 when a smoothing sweep
 // follows (BK_PROLONG: colour-0 mu, omega left unwritten).
 template <int KIND, bool PERSIST>
-__global__ __launch_bounds__(512) void kb_phase(const BSeg *segs, int nseg, unsigned ntiles, int opt,
-                                                int arg0, int arg1) {
-    const unsigned tile_items = (unsigned)kTileMin << opt;
+__global__ __launch_bounds__(512) void kb_phase(const BSeg *segs, int nseg, unsigned ntiles,
+                                                int shape, int arg0, int arg1) {
     for (unsigned t = blockIdx.x; t < ntiles; t += PERSIST ? gridDim.x : ntiles) {
         unsigned local;
-        const BSeg &g = segs[bseg_of_tile(segs, nseg, KIND, opt, t, local)];
+        const BSeg &g = segs[bseg_of_tile(segs, nseg, KIND, shape, t, local)];
         if (!*g.active) continue;
-        const unsigned base = local * tile_items;
-        for (unsigned r = threadIdx.x; r < tile_items; r += blockDim.x)
-            kb_item<KIND>(g, base + r, arg0, arg1);
+        const TileSpan sp = tile_span(g, KIND, shape, local);
+        for (unsigned z = sp.z0; z < sp.z1; ++z)
+            for (unsigned r = sp.w0 + threadIdx.x; r < sp.w1; r += blockDim.x)
+                kb_item<KIND>(g, z * sp.Q + r, arg0, arg1);
     }
 }
 
@@ -1203,19 +1243,22 @@ __global__ __launch_bounds__(64) void kb_coarse(const BSeg *segs, int nseg) {
                                g.iters);
 }
 
-// Residual maxima of every instance's finest level, one per workgroup of
-// kBlock points (norm tiles: opt kNormOpt, so that each instance owns a
-// known range of partial[]); workgroups of finished instances leave 0.
-static_assert(kBlock == (kTileMin << kNormOpt), "a norm tile is one workgroup of kBlock points");
+// Residual maxima of every instance's finest level, one per norm tile
+// (shape kNormShape, one workgroup each, so that each instance owns a known
+// range of partial[]); tiles of finished instances leave 0.
 __global__ __launch_bounds__(kBlock) void kb_norm(const BSeg *segs, int nseg,
                                                   unsigned long long *partial) {
     unsigned local;
-    const BSeg &g = segs[bseg_of_tile(segs, nseg, BK_NORM, kNormOpt, blockIdx.x, local)];
-    const unsigned t = local * kBlock + threadIdx.x;
+    const BSeg &g = segs[bseg_of_tile(segs, nseg, BK_NORM, kNormShape, blockIdx.x, local)];
     unsigned long long m = 0;
-    if (*g.active && t < bseg_count(g, BK_NORM))
-        m = resid_bits<double, false>(g.op, cst(g.u), cst(g.f), g.phk, nullptr,
-                                      Tri<double>{nullptr, nullptr, nullptr}, t);
+    if (*g.active) {
+        const TileSpan sp = tile_span(g, BK_NORM, kNormShape, local);
+        for (unsigned z = sp.z0; z < sp.z1; ++z)
+            for (unsigned r = sp.w0 + threadIdx.x; r < sp.w1; r += blockDim.x)
+                m = umax(m, resid_bits<double, false>(g.op, cst(g.u), cst(g.f), g.phk, nullptr,
+                                                      Tri<double>{nullptr, nullptr, nullptr},
+                                                      z * sp.Q + r));
+    }
     m = block_max_u64(m);
     if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
@@ -1265,26 +1308,26 @@ __global__ __launch_bounds__(kBlock) void kb_reset(BState st, int count, int **v
 }
 
 template <int KIND>
-static void launch_kind(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles, int opt,
+static void launch_kind(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles, int shape,
                         int threads, unsigned grid, int arg0, int arg1) {
     if (grid)
         hipLaunchKernelGGL((kb_phase<KIND, true>), dim3(grid), dim3(threads), 0, s, segs, nseg, ntiles,
-                           opt, arg0, arg1);
+                           shape, arg0, arg1);
     else
         hipLaunchKernelGGL((kb_phase<KIND, false>), dim3(std::max(ntiles, 1u)), dim3(threads), 0, s,
-                           segs, nseg, ntiles, opt, arg0, arg1);
+                           segs, nseg, ntiles, shape, arg0, arg1);
 }
 
-void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned ntiles, int opt,
+void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned ntiles, int shape,
                   int threads, unsigned slots, int arg0, int arg1) {
     // persistent: at most the resident workgroups, at most one per tile
     const unsigned grid = slots ? std::max(1u, std::min(slots, ntiles)) : 0u;
     switch (kind) {
-        case BK_SMOOTH: launch_kind<BK_SMOOTH>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
-        case BK_RR: launch_kind<BK_RR>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
-        case BK_TAU: launch_kind<BK_TAU>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
-        case BK_ERR: launch_kind<BK_ERR>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
-        case BK_PROLONG: launch_kind<BK_PROLONG>(s, segs, nseg, ntiles, opt, threads, grid, arg0, arg1); break;
+        case BK_SMOOTH: launch_kind<BK_SMOOTH>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1); break;
+        case BK_RR: launch_kind<BK_RR>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1); break;
+        case BK_TAU: launch_kind<BK_TAU>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1); break;
+        case BK_ERR: launch_kind<BK_ERR>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1); break;
+        case BK_PROLONG: launch_kind<BK_PROLONG>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1); break;
         default: break;
     }
 }

@@ -231,9 +231,12 @@ void launch_zero(hipStream_t s, float *p, size_t count);
 
 // ---- batched form ----
 enum { BK_SMOOTH = 0, BK_RR = 1, BK_TAU = 2, BK_PROLONG = 3, BK_ERR = 4, BK_NORM = 5, BK_KINDS = 6 };
-// batched tile sizes: kTileMin << opt work items, opt < kTileOpts (64 .. 4096);
-// the stop test's norm uses opt kNormOpt (one workgroup of kBlock points)
-constexpr int kTileMin = 64, kTileOpts = 7, kNormOpt = 2;
+// Batched tile shapes: a tile covers W consecutive work items of a plane
+// (W = kTileMin << (shape % kWOpts): 64 .. 1024) in Z consecutive planes
+// (Z = 1 << (shape / kWOpts): 1 .. 8), walked plane by plane; the stop
+// test's norm uses shape kNormShape (W = 256, Z = 4).
+constexpr int kTileMin = 64, kWOpts = 5, kZOpts = 4, kShapes = kWOpts * kZOpts;
+constexpr int kNormShape = 2 + kWOpts * 2;
 
 // One instance on one level, as seen by a batched launch.
 struct BSeg {
@@ -248,10 +251,9 @@ struct BSeg {
     const int *active;           // the instance's convergence flag
     int inst;
     // first tile of this segment in the work-list of a launch over its list,
-    // per phase kind and tile size (kTileMin << opt work items): segments are
-    // padded to whole tiles, so a workgroup finds a tile's segment by binary
-    // search
-    unsigned first[BK_KINDS][kTileOpts];
+    // per phase kind and tile shape: segments are padded to whole tiles, so
+    // a workgroup finds a tile's segment by binary search
+    unsigned first[BK_KINDS][kShapes];
 };
 
 // Per-instance state of the batched stop test (device arrays).
@@ -261,14 +263,17 @@ struct BState {
     const unsigned *norm_first, *norm_blocks;  // per finest-level segment
 };
 
-// One launch of a batched phase over `ntiles` tiles of kTileMin << opt work
-// items, `threads` per workgroup: one tile per workgroup (slots = 0) or
+// One launch of a batched phase over `ntiles` tiles of shape `shape`,
+// `threads` per workgroup: one tile per workgroup (slots = 0) or
 // persistent, at most `slots` workgroups walking the tiles.  arg0,
 // arg1: the half-sweep's colour and picard flag (BK_SMOOTH); for BK_PROLONG
 // arg0 = 1 when a smoothing sweep follows (colour-0 mu, omega left
 // unwritten).
-void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned ntiles, int opt,
+void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned ntiles, int shape,
                   int threads, unsigned slots, int arg0, int arg1);
+// Work items of one segment as planes: Q items per plane, NPL planes (the
+// item index is plane * Q + position), for the tile shapes.
+void bseg_planes_host(const BSeg &g, int kind, unsigned &Q, unsigned &NPL);
 // Resident workgroups of a phase kind's kernel at `threads` per workgroup.
 int batch_phase_slots(int kind, int threads, int device);
 void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg);

@@ -341,8 +341,9 @@ class Batch:
     def autotune(self, cache_path=None):
         """Schedules and tile shapes of (smooth, residual+coarsening, tau,
         interpolation, coarse error): a list of five (persistent, threads per
-        workgroup, tile work items) triples."""
-        chosen = (C.c_int32 * 15)()
+        workgroup, items per plane W, planes Z) tuples."""
+        chosen = (C.c_int32 * 20)()
         path = None if cache_path is None else str(cache_path).encode()
         self._check(self.lib.pfc_batch_autotune(self._b, path, chosen))
-        return [(bool(chosen[3 * k]), chosen[3 * k + 1], chosen[3 * k + 2]) for k in range(5)]
+        return [(bool(chosen[4 * k]), chosen[4 * k + 1], chosen[4 * k + 2], chosen[4 * k + 3])
+                for k in range(5)]

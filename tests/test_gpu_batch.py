@@ -57,8 +57,8 @@ def test_batch_instance_matches_oracle_and_autotune_keeps_results(tmp_path):
     b2 = Batch(ens, tol=1e-10)
     tiles = b2.autotune(cache_path=tmp_path / "tiles.json")
     assert len(tiles) == 5
-    assert all(th in (64, 128, 256, 512) and items in (64 << k for k in range(7)) and items >= th
-               for _, th, items in tiles)
+    assert all(th in (64, 128, 256) and w in (64, 128, 256, 512, 1024) and w >= th
+               and z in (1, 2, 4, 8) for _, th, w, z in tiles)
     assert (tmp_path / "tiles.json").exists()
     b3 = Batch(ens, tol=1e-10)
     assert b3.autotune(cache_path=tmp_path / "tiles.json") == tiles   # read back from the cache
