@@ -14,7 +14,8 @@ itself settles to ~1e-11 on that floor.  The paper's norm for "residual below
   - the printed counts are compared at 16^3-64^3 with the printed tol 1e-8;
   - the h-independence the table shows is checked at 16^3-128^3 with tol
     1e-7, per step against the oracle's counts (tests/golden/
-    table2_h_independence.json, written by make_table2_h_independence.py);
+    table2_h_independence.json, written by make_table2_h_independence.py):
+    equal at 16^3-64^3, within one at 128^3;
   - the refinement test pins the printed rates.
 """
 import json
@@ -79,7 +80,13 @@ def test_table_complexity_h_independent_to_128():
             want = ref["cycles"][key][str(n)]
             print(f"n={n} V{nu}: {got} (oracle {want})")
             assert all(i.status == 0 and i.res_final <= st["tol"] for i in infos)
-            assert all(abs(a - b) <= 1 for a, b in zip(got, want)), (n, nu, got, want)
+            if n <= 64:
+                # far above the residual's rounding floor: the oracle's counts exactly
+                assert got == want, (n, nu, got, want)
+            else:
+                # at 128^3 the floor (about 4.5e-8) is within a factor of the
+                # tolerance 1e-7, so a last cycle may fall either side of it
+                assert all(abs(a - b) <= 1 for a, b in zip(got, want)), (n, nu, got, want)
             last[(nu, n)] = got[-1]
     for nu in ((1, 1), (2, 2)):
         counts = [last[(nu, n)] for n in (16, 32, 64, 128)]
