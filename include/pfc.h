@@ -108,10 +108,12 @@ typedef struct pfc_handle pfc_handle;
 /* Creates a solver for one grid size.  Allocates the multigrid hierarchy
  * (levels n, n/2, ... down to 3 or 4, Section 5) on the current device.
  * stream: a hipStream_t (may be NULL).  Errors: INVALID_ARG for n not of the
- * form 2^k (k >= 2) or 3*2^k (k >= 1), L <= 0, dt <= 0, tol < 0, nu1 or nu2
- * < 0, nu1+nu2 == 0, max_cycles < 1, unknown enum values, Picard with MIXED,
- * variable mobility with MIXED or with mob_min <= 0, the first-order scheme
- * with MIXED or variable mobility; OOM; HIP. */
+ * form 2^k (k >= 2) or 3*2^k (k >= 1) or above 1024 (at 1024^3 the FP64
+ * hierarchy takes about 120 GiB, the mixed form about 50 GiB more), L <= 0,
+ * dt <= 0, tol < 0, nu1 or nu2 < 0, nu1+nu2 == 0, max_cycles < 1, unknown
+ * enum values, Picard with MIXED, variable mobility with MIXED or with
+ * mob_min <= 0, the first-order scheme with MIXED or variable mobility; OOM;
+ * HIP. */
 pfc_status pfc_create(const pfc_config *cfg, void *stream, pfc_handle **out);
 pfc_status pfc_destroy(pfc_handle *h);
 pfc_status pfc_set_stream(pfc_handle *h, void *stream);
