@@ -30,7 +30,6 @@ message on a device with less free memory.
 import gc
 import math
 
-import numpy as np
 import pytest
 import torch
 
