@@ -85,17 +85,6 @@ bool balloc(pfc_batch *B, T **p, size_t count) {
     return true;
 }
 
-unsigned seg_count(const BSeg &g, int kind) {
-    const unsigned n = (unsigned)g.op.lay.n, P = n * n * n;
-    switch (kind) {
-        case BK_SMOOTH: return P / 2;
-        case BK_RR:
-        case BK_ERR: return (unsigned)(g.lay_c.n * g.lay_c.n * g.lay_c.n);
-        case BK_PROLONG: return (unsigned)g.lay_c.n * n * n;
-        default: return P;
-    }
-}
-
 // Tiles of shape `shape` in a launch of `kind` over the list v.
 unsigned seg_tiles(const BSeg &g, int kind, int shape) {
     const unsigned W = (unsigned)kTileMin << (shape % kWOpts), Z = 1u << (shape / kWOpts);
@@ -121,6 +110,9 @@ BSeg make_seg(pfc_handle *h, int l, int i, const int *active) {
     g.op = op_of(h, l);
     g.u = A.u;
     g.f = A.f;
+    // in a time step the finest level's first source component is phi^k (the
+    // source kernel writes that copy as well): the phases read it from phk
+    if (l == 0) g.f.a = A.phk;
     g.ubar = A.ubar;
     g.phk = A.phk;
     if (l + 1 < h->nlev) {
