@@ -83,6 +83,33 @@ def test_status_strings_and_create_errors_without_gpu_work():
         assert L.pfc_create(ctypes.byref(c), None, ctypes.byref(h)) == _lib.PFC_ERR_INVALID_ARG
         assert why in L.pfc_last_error(None), (field, L.pfc_last_error(None))
     assert L.pfc_step(None, None, None, None, None, None, None) == _lib.PFC_ERR_INVALID_ARG
+    # sizes: 2^k (k >= 2) or 3 * 2^k (k >= 1), at most 1024
+    for bad_n in (0, 2, 6 * 7, 2048, 1536, 1025):
+        c = _lib.PfcConfig.from_buffer_copy(cfg)
+        c.n = bad_n
+        assert L.pfc_create(ctypes.byref(c), None, ctypes.byref(h)) == _lib.PFC_ERR_INVALID_ARG, bad_n
+
+
+def test_batch_create_errors_without_gpu_work():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("HIP library not built")
+    L = _lib.lib()
+    b = ctypes.c_void_p()
+    good = _lib.PfcConfig(n=16, nu1=2, nu2=2, max_cycles=10, cycle=0, lin=0, precision=0, mobility=0,
+                          L=16.0, eps=0.1, dt=0.1, tol=1e-10)
+    # an empty batch, or more instances than the tables hold
+    for count in (0, -1, 4097):
+        assert L.pfc_batch_create(count, ctypes.byref(good), None, ctypes.byref(b)) == \
+            _lib.PFC_ERR_INVALID_ARG, count
+        assert b.value is None
+    assert b"count" in L.pfc_batch_last_error(None)
+    arr = (_lib.PfcConfig * 2)(good, good)
+    for field, bad, why in (("n", 10, b"instance 1"), ("precision", _lib.PFC_MIXED, b"FP64"),
+                            ("nu1", 3, b"must agree")):
+        arr[1] = _lib.PfcConfig.from_buffer_copy(good)
+        setattr(arr[1], field, bad)
+        assert L.pfc_batch_create(2, arr, None, ctypes.byref(b)) == _lib.PFC_ERR_INVALID_ARG, field
+        assert why in L.pfc_batch_last_error(None), (field, L.pfc_batch_last_error(None))
 
 
 def test_config_struct_layout_matches_the_header():
