@@ -236,3 +236,29 @@ def test_run_reports_nonfinite():
     # the handle is still usable afterwards
     prev, cur, mu, om = phi0.clone(), phi0.clone(), mu0.clone(), om0.clone()
     assert all(i.status == 0 for i in s.run(prev, cur, mu, om, 2))
+
+
+def test_zero_steps_leave_the_state_alone():
+    """Empty input: pfc_run and pfc_batch_run over zero steps return at once,
+    report nothing and leave every buffer bit for bit as it was."""
+    from paper_1611_06288_amd import Solver
+    from paper_1611_06288_amd.solver import Batch
+    n = 32
+    s = Solver(n, n * math.pi / 4, 0.25, 0.5, tol=1e-10)
+    phi0, mu0, om0 = start(s, n, 2300)
+    state = [phi0.clone(), (phi0 + 0.01).clone(), mu0.clone(), om0.clone()]
+    before = [t.clone() for t in state]
+    assert s.run(*state, 0) == []
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(state, before))
+    ens = [dict(n=16, L=4 * math.pi, eps=0.25, dt=0.5,
+                phi0=inputs.polycrystal_phi0(16, 4 * math.pi, 1, seed=2301, radius_cells=3)),
+           dict(n=24, L=6 * math.pi, eps=0.2, dt=0.5,
+                phi0=inputs.polycrystal_phi0(24, 6 * math.pi, 1, seed=2302, radius_cells=3))]
+    b = Batch(ens, tol=1e-10)
+    for i, p in enumerate(ens):
+        b.init_state(i, torch.from_numpy(p["phi0"]).cuda())
+    kept = [[t.clone() for t in b.get_state(i)] for i in range(2)]
+    assert b.run(0) == [[], []]
+    for i in range(2):
+        assert all(torch.equal(x, y) for x, y in zip(b.get_state(i), kept[i]))
