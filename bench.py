@@ -407,8 +407,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU (--gpus > 1) is not "
-              "supported (the z-slab decomposition is a design note, not code)", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; more than one (--gpus > 1) is not "
+              "implemented (the z-slab decomposition is a design note, not code)", file=sys.stderr)
         sys.exit(2)
 
     from paper_1611_06288_amd import inputs
