@@ -102,30 +102,42 @@ __global__ __launch_bounds__(kBlock) void k_adj_resid_max(OpParams op, Tri<const
     if (threadIdx.x == 0) partial[blockIdx.x] = mx;
 }
 
-// Coarse right-hand side b_c = I (b - J^T lambda), one thread per coarse cell.
+// Coarse right-hand side b_c = I (b - J^T lambda), eight threads per coarse
+// cell (one per child, child ch = (ch & 1, (ch >> 1) & 1, ch >> 2) in x, y, z),
+// so each thread waits on one child's loads; the cell's eight lanes add
+// their residuals in the order ch = 0..7 and the first stores b_c and clears
+// the coarse iterate lam_c (the coarse problem starts from zero).
 __global__ __launch_bounds__(kBlock) void k_adj_resid_restrict(OpParams op, Lay LC,
                                                                Tri<const double> lam,
                                                                Tri<const double> b,
                                                                const double *__restrict__ D,
-                                                               Tri<double> bc) {
-    const unsigned tn = xcd_block() * kBlock + threadIdx.x;
-    if (tn >= (unsigned)npts(LC)) return;
-    int I, J, K;
-    decode_nat(LC, tn, I, J, K);
-    double s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll 1
-    for (int ch = 0; ch < 8; ++ch) {
+                                                               Tri<double> bc, Tri<double> lamc) {
+    const unsigned g = xcd_block() * kBlock + threadIdx.x;
+    const unsigned tn = g >> 3;
+    const int ch = (int)(g & 7u);
+    const bool act = tn < (unsigned)npts(LC);
+    double r[3] = {0.0, 0.0, 0.0};
+    unsigned t = 0;
+    if (act) {
+        int I, J, K;
+        decode_nat(LC, tn, I, J, K);
+        t = sidx32(LC, I, J, K);
         const Off q = offs(op.lay, 2 * I + (ch & 1), 2 * J + ((ch >> 1) & 1), 2 * K + (ch >> 2));
-        double r1, r2, r3;
-        adj_resid_at(op, lam, b, D, q, r1, r2, r3);
-        s1 += r1;
-        s2 += r2;
-        s3 += r3;
+        adj_resid_at(op, lam, b, D, q, r[0], r[1], r[2]);
     }
-    const unsigned t = sidx32(LC, I, J, K);
-    bc.a[t] = 0.125 * s1;
-    bc.b[t] = 0.125 * s2;
-    bc.c[t] = 0.125 * s3;
+    double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) s[e] += __shfl(r[e], c, 8);
+    if (act && ch == 0) {
+        bc.a[t] = 0.125 * s[0];
+        bc.b[t] = 0.125 * s[1];
+        bc.c[t] = 0.125 * s[2];
+        lamc.a[t] = 0.0;
+        lamc.b[t] = 0.0;
+        lamc.c[t] = 0.0;
+    }
 }
 
 // Exact solve on the coarsest level (natural layout, P <= 64), one wavefront.
@@ -294,9 +306,8 @@ static void adj_cycle(pfc_handle *H, int l, bool fcycle) {
     }
     Level &B = H->lev[l + 1];
     for (int s = 0; s < H->cfg.nu1; ++s) adj_sweep(H, l);
-    hipLaunchKernelGGL(k_adj_resid_restrict, dim3(blocks_for(B.P)), dim3(kBlock), 0, H->stream,
-                       op_of(H, l), B.lay, cst(A.u), cst(A.f), (const double *)A.phk, B.f);
-    fill(H->stream, B.u.a, 3 * B.P, 0.0);
+    hipLaunchKernelGGL(k_adj_resid_restrict, dim3(blocks_for(8 * B.P)), dim3(kBlock), 0, H->stream,
+                       op_of(H, l), B.lay, cst(A.u), cst(A.f), (const double *)A.phk, B.f, B.u);
     adj_cycle(H, l + 1, fcycle);
     if (fcycle) adj_cycle(H, l + 1, false);
     launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u),
