@@ -319,7 +319,12 @@ pfc_status pfc_batch_init_state(pfc_batch *b, int32_t i, const double *phi0);
  * phase of a cycle is one launch over all instances that take part in it
  * (levels aligned from the finest), over a work-list of fixed-size tiles of
  * every instance's part of the phase, in the schedule the autotuner chose
- * (one tile per workgroup by default); an instance stops cycling when its own
+ * (one tile per workgroup by default).  When every instance's finest size is
+ * a multiple of 16, the finest levels' interpolation runs as column tiles
+ * (a 16 x 8 fine column and 4 coarse planes of one instance per workgroup,
+ * the coarse error staged in LDS as it is formed, no coarse-error pass);
+ * otherwise as the coarse-error pass and the interpolation phase, with the
+ * same results.  An instance stops cycling when its own
  * residual meets the tolerance, so it follows exactly the cycle sequence of
  * pfc_step.  One cycle plus the stop test is captured as a hipGraph on the
  * batch's own stream and replayed.  infos (host, nullable): count*steps
@@ -334,8 +339,11 @@ pfc_status pfc_batch_run(pfc_batch *b, int32_t steps, pfc_step_info *infos);
  * (half-sweep points, coarse cells, fine x-pairs or points, in the level's
  * storage order) over Z = 1 .. 8 consecutive planes, walked plane by plane.
  * With cache_path (nullable) choices are read from / written to a JSON file
- * keyed by GPU architecture, instance sizes and phase.  chosen (host,
- * nullable): 20 ints, (persistent, threads, W, Z) per phase in that order.
+ * keyed by GPU architecture, instance sizes and phase.  Where the column
+ * tiles apply it then times them with Z = 1, 2, 4 or 8 coarse planes per
+ * tile against the chosen coarse-error pass plus interpolation and keeps the
+ * faster.  chosen (host, nullable): 20 ints, (persistent, threads, W, Z) per
+ * phase in that order; column tiles read (0, 64, 64, Z).
  * Results do not depend on the choice (same per-point arithmetic).  Leaves
  * the state unchanged.  Synchronises. */
 pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *chosen);

@@ -51,6 +51,10 @@ struct pfc_batch {
     int shape[5] = {2, 2, 2, 2, 2};
     bool persist[5] = {false, false, false, false, false};
     unsigned slots[5] = {0, 0, 0, 0, 0};
+    // the finest depth's interpolation as column tiles (every instance's
+    // finest size a multiple of kBPX), 1 << ptile_zi coarse planes per tile
+    bool ptile = false;
+    int ptile_zi = 2;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool graph_ready = false;
@@ -91,6 +95,16 @@ unsigned seg_tiles(const BSeg &g, int kind, int shape) {
     unsigned Q, NPL;
     bseg_planes_host(g, kind, Q, NPL);
     return ((Q + W - 1) / W) * ((NPL + Z - 1) / Z);
+}
+
+unsigned ptile_tiles(const std::vector<BSeg> &v, int zi) {
+    unsigned b = 0;
+    for (const auto &g : v) b += batch_ptile_count(g, zi);
+    return b;
+}
+
+bool ptile_fits_all(const std::vector<BSeg> &v) {
+    return !v.empty() && std::all_of(v.begin(), v.end(), [](const BSeg &g) { return batch_ptile_fits(g); });
 }
 
 unsigned tiles_of(const std::vector<BSeg> &v, int kind, int shape) {
@@ -157,8 +171,13 @@ void bcycle(pfc_batch *B, int d, bool fcycle) {
     phase(B, BK_TAU, B->h_all[d + 1], B->d_all[d + 1], 0, 0);
     bcycle(B, d + 1, fcycle);
     if (fcycle) bcycle(B, d + 1, false);
-    phase(B, BK_ERR, mid, B->d_mid[d], 0, 0);
-    phase(B, BK_PROLONG, mid, B->d_mid[d], B->cfg.nu2 >= 1 ? 1 : 0, 0);
+    if (d == 0 && B->ptile) {  // forms the coarse error itself
+        launch_batch_ptile(s, B->d_mid[0], (int)mid.size(), ptile_tiles(mid, B->ptile_zi),
+                           B->ptile_zi, B->cfg.nu2 >= 1 ? 1 : 0);
+    } else {
+        phase(B, BK_ERR, mid, B->d_mid[d], 0, 0);
+        phase(B, BK_PROLONG, mid, B->d_mid[d], B->cfg.nu2 >= 1 ? 1 : 0, 0);
+    }
     for (int q = 0; q < B->cfg.nu2; ++q) sweep();
 }
 
@@ -348,6 +367,13 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
                     acc += seg_tiles(g, kind, sh);
                 }
             }
+        for (int zi = 0; zi < kZOpts; ++zi) {
+            unsigned acc = 0;
+            for (auto &g : w) {
+                g.ptf[zi] = acc;
+                acc += batch_ptile_count(g, zi);
+            }
+        }
         return balloc(B, d, w.size()) &&
                hipMemcpy(*d, w.data(), w.size() * sizeof(BSeg), hipMemcpyHostToDevice) == hipSuccess;
     };
@@ -358,6 +384,7 @@ pfc_status pfc_batch_create(int32_t count, const pfc_config *cfgs, void *stream,
         ok = upload(B->h_all[d], &B->d_all[d]) && upload(B->h_mid[d], &B->d_mid[d]) &&
              upload(B->h_bot[d], &B->d_bot[d]);
     // stop test over the finest levels
+    B->ptile = B->maxdepth > 1 && ptile_fits_all(B->h_mid[0]);
     B->d_norm = B->d_all.empty() ? nullptr : B->d_all[0];
     B->n_norm = count;
     std::vector<unsigned> first(n), nblk(n);
@@ -529,6 +556,54 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
         cache[key] = best_code;
         changed = true;
     }
+    // the finest depth's interpolation: the tuned coarse-error pass and
+    // interpolation phase, or the column tiles (no coarse-error pass) with
+    // 1, 2, 4 or 8 coarse planes per tile; stored as 99 or zi
+    if (b->maxdepth > 1 && ptile_fits_all(b->h_mid[0])) {
+        const std::string key = sig.str() + "|prolong_tile";
+        auto it = cache.find(key);
+        if (it != cache.end() && (it->second == 99 || (it->second >= 0 && it->second < kZOpts))) {
+            b->ptile = it->second != 99;
+            if (b->ptile) b->ptile_zi = it->second;
+        } else {
+            const auto &segs = b->h_mid[0];
+            const int nseg = (int)segs.size(), pflag = b->cfg.nu2 >= 1 ? 1 : 0;
+            float best = 1e30f;
+            int best_code = 99;
+            for (int code = -1; code < kZOpts; ++code) {
+                auto run = [&]() {
+                    if (code < 0) {
+                        launch_batch(b->stream, BK_ERR, b->d_mid[0], nseg,
+                                     tiles_of(segs, BK_ERR, b->shape[BK_ERR]), b->shape[BK_ERR],
+                                     b->threads[BK_ERR], b->persist[BK_ERR] ? b->slots[BK_ERR] : 0u,
+                                     0, 0);
+                        launch_batch(b->stream, BK_PROLONG, b->d_mid[0], nseg,
+                                     tiles_of(segs, BK_PROLONG, b->shape[BK_PROLONG]),
+                                     b->shape[BK_PROLONG], b->threads[BK_PROLONG],
+                                     b->persist[BK_PROLONG] ? b->slots[BK_PROLONG] : 0u, pflag, 0);
+                    } else {
+                        launch_batch_ptile(b->stream, b->d_mid[0], nseg, ptile_tiles(segs, code),
+                                           code, pflag);
+                    }
+                };
+                for (int rep = 0; rep < 2; ++rep) run();
+                (void)hipEventRecord(t0, b->stream);
+                for (int rep = 0; rep < 6; ++rep) run();
+                (void)hipEventRecord(t1, b->stream);
+                if (hipEventSynchronize(t1) != hipSuccess) break;
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, t0, t1);
+                if (ms < best) {
+                    best = ms;
+                    best_code = code < 0 ? 99 : code;
+                }
+            }
+            b->ptile = best_code != 99;
+            if (b->ptile) b->ptile_zi = best_code;
+            cache[key] = best_code;
+            changed = true;
+        }
+    }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     hipError_t e = hipStreamSynchronize(b->stream);
@@ -541,6 +616,12 @@ pfc_status pfc_batch_autotune(pfc_batch *b, const char *cache_path, int32_t *cho
             chosen[4 * k + 1] = b->threads[k];
             chosen[4 * k + 2] = kTileMin << (b->shape[k] % kWOpts);
             chosen[4 * k + 3] = 1 << (b->shape[k] / kWOpts);
+            if (k == BK_PROLONG && b->ptile) {  // column tiles: 64 x-pairs of a plane, 2^zi coarse planes
+                chosen[4 * k] = 0;
+                chosen[4 * k + 1] = 4 * kBPX;
+                chosen[4 * k + 2] = 4 * kBPX;
+                chosen[4 * k + 3] = 1 << b->ptile_zi;
+            }
         }
     return PFC_OK;
 }

@@ -1294,6 +1294,145 @@ __global__ __launch_bounds__(kBlock) void kb_update(const BSeg *segs, int nseg,
     }
 }
 
+// Batched column-tiled interpolation: the tile of k_prolong_tile for one
+// instance (segment) per workgroup, a PX x 8 fine column and the coarse
+// planes [K0, K0 + 2^zi) of it, found through the segments' first tiles
+// (BSeg::ptf).  The coarse error v - I u is formed as a coarse plane is
+// staged, rounded as coarse_err_body stores it, and I u is left as it is;
+// same weights and operation order as prolong_body.  phi0: colour-0 mu and
+// omega are neither read nor written (a smoothing sweep follows).
+template <int PX>
+__global__ __launch_bounds__(4 * PX) void kb_prolong_tile(const BSeg *segs, int nseg, int zi,
+                                                          int phi0) {
+    constexpr int HX = PX / 2, CW = HX + 2, CH = 8 / 2 + 2, CN = CW * CH;
+    static_assert(CN <= 4 * PX, "one coarse ring cell per thread");
+    __shared__ double ce[3][3][CH][CW];  // [field][plane slot][Y][X]
+    const unsigned tile = blockIdx.x;
+    int lo = 0, hi = nseg - 1;  // the last segment whose first tile is <= tile
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].ptf[zi] <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BSeg &g = segs[lo];
+    if (!*g.active) return;
+    const Lay &LF = g.op.lay, &LC = g.lay_c;
+    const Tri<const double> v = cst(g.uc), ubar = cst(g.ubarc);
+    const Tri<double> fine = g.u;
+    const int nc = LC.n, nf = LF.n;
+    const unsigned local = tile - g.ptf[zi];
+    const int nbx = nf / PX, nby = nf / 8;
+    const int bx = (int)(local % (unsigned)nbx), by = (int)((local / (unsigned)nbx) % (unsigned)nby);
+    const int bz = (int)(local / (unsigned)(nbx * nby));
+    const int x0 = bx * PX, y0 = by * 8, X0 = x0 / 2, Y0 = y0 / 2;
+    const int K0 = bz << zi, K1 = min(K0 + (1 << zi), nc);
+    const int tid = threadIdx.x, qx = tid % HX, qy = tid / HX;
+    const int y = y0 + qy;
+    auto wc = [nc](int q) { return q < 0 ? q + nc : (q >= nc ? q - nc : q); };
+    auto slot = [K0](int P) { return (P - K0 + 4) % 3; };  // P >= K0 - 1
+    const int cpy = tid / CW, cpx = tid - cpy * CW;
+    double cn[3];
+    auto load_coarse = [&](int P) {
+        if (tid < CN) {
+            const unsigned gi = sidx32(LC, wc(X0 - 1 + cpx), wc(Y0 - 1 + cpy), wc(P));
+            cn[0] = v.a[gi] - ubar.a[gi];
+            cn[1] = v.b[gi] - ubar.b[gi];
+            cn[2] = v.c[gi] - ubar.c[gi];
+        }
+    };
+    auto store_coarse = [&](int P) {
+        if (tid < CN) {
+            const int sl = slot(P);
+            ce[0][sl][cpy][cpx] = cn[0];
+            ce[1][sl][cpy][cpx] = cn[1];
+            ce[2][sl][cpy][cpx] = cn[2];
+        }
+    };
+    double fv[2][2][3];  // [dz][dx][field]
+    auto load_fine = [&](int K, double (&o)[2][2][3]) {
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const unsigned gi = sidx32(LF, x0 + 2 * qx + dx, y, 2 * K + dz);
+                o[dz][dx][0] = fine.a[gi];
+                if (!phi0 || ((dx + y + dz) & 1)) {  // x0, 2 qx and 2 K are even
+                    o[dz][dx][1] = fine.b[gi];
+                    o[dz][dx][2] = fine.c[gi];
+                } else {  // neither read nor written back
+                    o[dz][dx][1] = 0.0;
+                    o[dz][dx][2] = 0.0;
+                }
+            }
+    };
+    load_coarse(K0 - 1);
+    store_coarse(K0 - 1);
+    load_coarse(K0);
+    store_coarse(K0);
+    load_coarse(K0 + 1);
+    load_fine(K0, fv);
+    store_coarse(K0 + 1);
+    __syncthreads();
+    const int cy = (y >> 1) - Y0 + 1, cy1 = (y & 1) ? cy + 1 : cy - 1, cx = qx + 1;
+    for (int K = K0; K < K1; ++K) {
+        double fn[2][2][3];
+        if (K + 1 < K1) {
+            load_coarse(K + 2);
+            load_fine(K + 1, fn);
+        }
+        const int s1 = slot(K);
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz) {
+            const int sz = slot(dz ? K + 1 : K - 1);  // plane K-1 for fine plane 2K, K+1 for 2K+1
+#pragma unroll
+            for (int fl = 0; fl < 3; ++fl) {
+                double w[3];  // y/z-interpolated values at X-1, X, X+1
+#pragma unroll
+                for (int xx = 0; xx < 3; ++xx)
+                    w[xx] = 0.75 * (0.75 * ce[fl][s1][cy][cx - 1 + xx] +
+                                    0.25 * ce[fl][s1][cy1][cx - 1 + xx]) +
+                            0.25 * (0.75 * ce[fl][sz][cy][cx - 1 + xx] +
+                                    0.25 * ce[fl][sz][cy1][cx - 1 + xx]);
+                double *ff = fl == 0 ? fine.a : (fl == 1 ? fine.b : fine.c);
+                const bool c1x0 = ((y + dz) & 1) != 0;  // the pair's even-x point is colour 1
+                const unsigned g0 = sidx32(LF, x0 + 2 * qx, y, 2 * K + dz);
+                const unsigned g1 = sidx32(LF, x0 + 2 * qx + 1, y, 2 * K + dz);
+                if (fl == 0 || !phi0 || c1x0) ff[g0] = fv[dz][0][fl] + (0.75 * w[1] + 0.25 * w[0]);
+                if (fl == 0 || !phi0 || !c1x0) ff[g1] = fv[dz][1][fl] + (0.75 * w[1] + 0.25 * w[2]);
+            }
+        }
+        if (K + 1 < K1) {
+            __syncthreads();  // plane K-1's slot is free
+            store_coarse(K + 2);
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx)
+#pragma unroll
+                    for (int fl = 0; fl < 3; ++fl) fv[dz][dx][fl] = fn[dz][dx][fl];
+            __syncthreads();
+        }
+    }
+}
+
+bool batch_ptile_fits(const BSeg &g) {
+    return g.op.lay.split && g.op.lay.n % kBPX == 0 && g.op.lay.n % 8 == 0 && g.lay_c.n * 2 == g.op.lay.n;
+}
+
+unsigned batch_ptile_count(const BSeg &g, int zi) {
+    if (!batch_ptile_fits(g)) return 0;
+    const unsigned nf = (unsigned)g.op.lay.n, nc = (unsigned)g.lay_c.n, zr = 1u << zi;
+    return (nf / kBPX) * (nf / 8) * ((nc + zr - 1) / zr);
+}
+
+void launch_batch_ptile(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles, int zi,
+                        int phi0) {
+    hipLaunchKernelGGL((kb_prolong_tile<kBPX>), dim3(std::max(ntiles, 1u)), dim3(4 * kBPX), 0, s,
+                       segs, nseg, zi, phi0);
+}
+
 // Start of a time step: every instance active, counters cleared, cached
 // coarsest inverses invalidated.
 __global__ __launch_bounds__(kBlock) void kb_reset(BState st, int count, int **valid) {

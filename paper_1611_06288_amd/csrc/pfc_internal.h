@@ -254,6 +254,9 @@ struct BSeg {
     // per phase kind and tile shape: segments are padded to whole tiles, so
     // a workgroup finds a tile's segment by binary search
     unsigned first[BK_KINDS][kShapes];
+    // the same for the column-tiled interpolation, per coarse planes per
+    // tile (1 << zi); every tile of a segment is a whole column
+    unsigned ptf[kZOpts];
 };
 
 // Per-instance state of the batched stop test (device arrays).
@@ -280,5 +283,15 @@ void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg);
 void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles,
                        unsigned long long *partial, BState st, double tol, int max_cycles);
 void launch_batch_reset(hipStream_t s, BState st, int count, int **valid);
+// Column-tiled interpolation of the batched form (fine levels whose size is a
+// multiple of kBPX): a kBPX x 8 fine column and 1 << zi coarse planes of one
+// instance per workgroup, the coarse error formed while staged (no
+// coarse-error pass before it).  Same results as the coarse-error pass
+// followed by the interpolation phase.
+constexpr int kBPX = 16;
+bool batch_ptile_fits(const BSeg &g);
+unsigned batch_ptile_count(const BSeg &g, int zi);
+void launch_batch_ptile(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles, int zi,
+                        int phi0);
 
 }  // namespace pfc

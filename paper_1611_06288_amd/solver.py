@@ -341,7 +341,8 @@ class Batch:
     def autotune(self, cache_path=None):
         """Schedules and tile shapes of (smooth, residual+coarsening, tau,
         interpolation, coarse error): a list of five (persistent, threads per
-        workgroup, items per plane W, planes Z) tuples."""
+        workgroup, items per plane W, planes Z) tuples; an interpolation run
+        as column tiles reads (False, 64, 64, coarse planes per tile)."""
         chosen = (C.c_int32 * 20)()
         path = None if cache_path is None else str(cache_path).encode()
         self._check(self.lib.pfc_batch_autotune(self._b, path, chosen))

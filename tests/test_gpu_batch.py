@@ -138,3 +138,32 @@ def test_batch_statuses_per_instance():
         s = Solver(p["n"], p["L"], p["eps"], p["dt"], tol=1e-10)
         _, _, _, _, sinfos = s.simulate(dev(p["phi0"]), 1)
         assert infos[i][0].status == 0 and infos[i][0].cycles == sinfos[0].cycles, i
+
+
+def test_batch_column_tiled_interpolation_is_bitwise_the_two_pass_form():
+    """When every instance's finest size is a multiple of 16 the finest
+    interpolation runs as column tiles that form the coarse error themselves;
+    adding one instance of another size (24) sends the whole finest depth
+    through the coarse-error pass and the per-pair interpolation instead.
+    The instances the two batches share must come out bit for bit equal."""
+    from paper_1611_06288_amd.solver import Batch
+    shared = []
+    for i, n in enumerate([16, 32, 48, 32]):
+        g = inputs.rng(5100 + i)
+        shared.append(dict(n=n, L=n * math.pi / 4, eps=float(g.uniform(0.05, 0.3)), dt=0.1,
+                           phi0=0.2 + 0.05 * g.uniform(-1, 1, (n, n, n))))
+    extra = dict(n=24, L=6 * math.pi, eps=0.2, dt=0.1,
+                 phi0=0.2 + 0.05 * inputs.rng(5199).uniform(-1, 1, (24, 24, 24)))
+    results = []
+    for ens in (shared, shared + [extra]):
+        b = Batch(ens, tol=1e-10)
+        for i, p in enumerate(ens):
+            b.init_state(i, dev(p["phi0"]))
+        infos = b.run(2)
+        results.append(([[x.cycles for x in row] for row in infos[:len(shared)]],
+                        [b.get_state(i) for i in range(len(shared))]))
+    (ca, sa), (cb, sb) = results
+    assert ca == cb
+    for i in range(len(shared)):
+        for x, y in zip(sa[i], sb[i]):
+            assert torch.equal(x, y), i
