@@ -71,10 +71,11 @@ def parse():
                     help="steps of that leg's step-by-step comparison run")
     ap.add_argument("--no-fcycle", action="store_true",
                     help="skip the FP64 F(2,2) run of the same steps (reported beside V)")
-    ap.add_argument("--cpu-cycles", type=int, default=8,
-                    help="oracle cycles timed on all threads for the CPU baseline (0 disables it)")
-    ap.add_argument("--cpu-one-core-cycles", type=int, default=1,
-                    help="oracle cycles timed on one thread (child process; 0 skips)")
+    ap.add_argument("--cpu-cycles", type=int, default=24,
+                    help="oracle cycles timed on all threads for the CPU baseline, about 10 s "
+                         "on 16 threads (0 disables it)")
+    ap.add_argument("--cpu-one-core-cycles", type=int, default=3,
+                    help="oracle cycles timed on one thread, about 12 s (child process; 0 skips)")
     ap.add_argument("--cpu-full-step", action="store_true",
                     help="also time the oracle's whole first step on all threads (~1-2 min at 256^3)")
     ap.add_argument("--batch-steps", type=int, default=50,
