@@ -167,3 +167,35 @@ def test_batch_column_tiled_interpolation_is_bitwise_the_two_pass_form():
     for i in range(len(shared)):
         for x, y in zip(sa[i], sb[i]):
             assert torch.equal(x, y), i
+
+
+def test_batch_autotune_column_tiles_cached_and_bitwise(tmp_path):
+    """On sizes that admit the column-tiled interpolation the autotuner also
+    chooses between it and the two-pass form; the choice is cached (a second
+    batch reads it back) and either choice gives the default batch's results
+    bit for bit."""
+    from paper_1611_06288_amd.solver import Batch
+    ens = []
+    for i, n in enumerate([16, 32, 48, 32]):
+        g = inputs.rng(5300 + i)
+        ens.append(dict(n=n, L=n * math.pi / 4, eps=float(g.uniform(0.05, 0.3)), dt=0.1,
+                        phi0=0.2 + 0.05 * g.uniform(-1, 1, (n, n, n))))
+    cache = tmp_path / "tiles.json"
+    b = Batch(ens, tol=1e-10)
+    b2 = Batch(ens, tol=1e-10)
+    tiles = b2.autotune(cache_path=cache)
+    text = cache.read_text()
+    assert "prolong_tile" in text, text
+    b3 = Batch(ens, tol=1e-10)
+    assert b3.autotune(cache_path=cache) == tiles
+    b3.close()
+    _, th, w, z = tiles[3]
+    print(f"interpolation choice: {tiles[3]}", flush=True)
+    assert (th, w) == (64, 64) or z in (1, 2, 4, 8)
+    for bb in (b, b2):
+        for i, p in enumerate(ens):
+            bb.init_state(i, dev(p["phi0"]))
+    i1, i2 = b.run(2), b2.run(2)
+    for i in range(len(ens)):
+        assert [x.cycles for x in i1[i]] == [x.cycles for x in i2[i]]
+        assert all(torch.equal(x, y) for x, y in zip(b.get_state(i), b2.get_state(i))), i
