@@ -35,7 +35,8 @@ constexpr int kRX = 64, kRY = 8, kRT = 256;            // column extents, thread
 constexpr int kRC = kRX + 2, kRR = kRY + 2;            // tile with its ring
 constexpr int kRN = kRC * kRR, kRI = (kRN + kRT - 1) / kRT;  // ring points, per thread
 
-template <int MODE, bool MOB>
+// PK1: the first source component is phi^k itself (one buffer), loaded once.
+template <int MODE, bool MOB, bool PK1 = false>
 __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTileArgs a) {
     constexpr bool F32 = MODE == RT_RESTRICT32;
     constexpr bool DELTA = F32;
@@ -130,10 +131,10 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const unsigned g = own_index(p, e);
-            o[e][0] = f.a[g];
+            o[e][3] = phk[g];
+            o[e][0] = PK1 ? o[e][3] : f.a[g];
             o[e][1] = f.b[g];
             o[e][2] = f.c[g];
-            o[e][3] = phk[g];
             if constexpr (DELTA) o[e][4] = bs[g];
         }
     };
@@ -300,9 +301,15 @@ int launch_resid_tile(hipStream_t s, int mode, const OpParams &op, int nz, const
     const bool mob = op.mob.phs != nullptr;  // FP64 modes only (the FP32 cycle has M = 1)
     switch (mode) {
         case RT_RESTRICT:
-            if (mob)
+            if (mob && a.f.a == a.phk)
+                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, true, true>), dim3(blocks), dim3(kRT),
+                                   0, s, op, nz, a);
+            else if (mob)
                 hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, true>), dim3(blocks), dim3(kRT), 0, s,
                                    op, nz, a);
+            else if (a.f.a == a.phk)
+                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, false, true>), dim3(blocks), dim3(kRT),
+                                   0, s, op, nz, a);
             else
                 hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, false>), dim3(blocks), dim3(kRT), 0,
                                    s, op, nz, a);

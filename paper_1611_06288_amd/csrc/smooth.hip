@@ -121,7 +121,7 @@ constexpr int kFNr = kFSl * kFRw, kFNb = (kFX / 2) * kFY, kFNc = kFCs * kFCr;
 constexpr int kFIr = (kFNr + kFT - 1) / kFT, kFIb = (kFNb + kFT - 1) / kFT,
               kFIc = (kFNc + kFT - 1) / kFT;  // items per thread in each phase
 
-template <typename T, bool DELTA, bool MOB, int NRM>
+template <typename T, bool DELTA, bool MOB, int NRM, bool PK1>
 __global__ __launch_bounds__(kFT) void k_sweep_fused(
     OpParams op, int picard, int nz, const T *__restrict__ ua, const T *__restrict__ ub,
     const T *__restrict__ uc, T *__restrict__ oa, T *__restrict__ ob, T *__restrict__ oc,
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                 ro[i][0] = ua[g];
                 ro[i][1] = phk[g];
                 ro[i][2] = DELTA ? base[g] : (T)0;
-                ro[i][3] = fa[g];
+                ro[i][3] = PK1 ? ro[i][1] : fa[g];
                 ro[i][4] = fb[g];
                 ro[i][5] = fc[g];
                 if constexpr (MOB) ro[i][6] = ps[g];
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kFT) void k_sweep_fused(
                 const unsigned g = H + ((unsigned)kb * un + (unsigned)y) * uhn + (unsigned)(x >> 1);
                 bo[i][0] = phk[g];
                 bo[i][1] = DELTA ? base[g] : (T)0;
-                bo[i][2] = fa[g];
+                bo[i][2] = PK1 ? bo[i][0] : fa[g];
                 bo[i][3] = fb[g];
                 bo[i][4] = fc[g];
             }
@@ -431,8 +431,8 @@ bool fused_fits(int n) { return n % kFX == 0 && n % kFY == 0 && n >= kFusedMinN;
 
 int fused_slots(int device, bool mob) {
     int occ = 0, cus = 0;
-    const void *fn = mob ? (const void *)k_sweep_fused<double, false, true, 0>
-                         : (const void *)k_sweep_fused<double, false, false, 0>;
+    const void *fn = mob ? (const void *)k_sweep_fused<double, false, true, 0, true>
+                         : (const void *)k_sweep_fused<double, false, false, 0, true>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kFT, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
@@ -452,45 +452,46 @@ int fused_nz(int n, int slots) {
 
 int fused_blocks(int n, int nz) { return (n / kFX) * (n / kFY) * nz; }
 
+template <typename T, bool DELTA, bool MOB, int NRM>
+static void launch_fused_inst(hipStream_t s, const OpParams &op, int picard, int nz,
+                              Tri<const T> uin, Tri<T> uout, Tri<const T> f, const T *phk,
+                              const T *base, unsigned long long *part, int sk) {
+    const unsigned blocks = (unsigned)fused_blocks(op.lay.n, nz);
+    if (f.a == phk)  // the first source component is phi^k itself: load it once
+        hipLaunchKernelGGL((k_sweep_fused<T, DELTA, MOB, NRM, true>), dim3(blocks), dim3(kFT), 0, s,
+                           op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b,
+                           f.c, phk, base, part, sk);
+    else
+        hipLaunchKernelGGL((k_sweep_fused<T, DELTA, MOB, NRM, false>), dim3(blocks), dim3(kFT), 0,
+                           s, op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
+                           f.b, f.c, phk, base, part, sk);
+}
+
 template <typename T, bool DELTA>
 void launch_sweep_fused(hipStream_t s, const OpParams &op, int picard, int nz, Tri<const T> uin,
                         Tri<T> uout, Tri<const T> f, const T *phk, const T *base, int nrm,
                         unsigned long long *part, bool skip0) {
     const int sk = skip0 ? 1 : 0;
-    const int n = op.lay.n;
-    const unsigned blocks = (unsigned)fused_blocks(n, nz);
     if constexpr (!DELTA) {
         if (op.mob.phs) {  // variable mobility
             if (nrm == 1)
-                hipLaunchKernelGGL((k_sweep_fused<T, false, true, 1>), dim3(blocks), dim3(kFT), 0,
-                                   s, op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c,
-                                   f.a, f.b, f.c, phk, base, part, sk);
+                launch_fused_inst<T, false, true, 1>(s, op, picard, nz, uin, uout, f, phk, base, part, sk);
             else if (nrm == 2)
-                hipLaunchKernelGGL((k_sweep_fused<T, false, true, 2>), dim3(blocks), dim3(kFT), 0,
-                                   s, op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c,
-                                   f.a, f.b, f.c, phk, base, part, sk);
+                launch_fused_inst<T, false, true, 2>(s, op, picard, nz, uin, uout, f, phk, base, part, sk);
             else
-                hipLaunchKernelGGL((k_sweep_fused<T, false, true, 0>), dim3(blocks), dim3(kFT), 0,
-                                   s, op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c,
-                                   f.a, f.b, f.c, phk, base, nullptr, sk);
+                launch_fused_inst<T, false, true, 0>(s, op, picard, nz, uin, uout, f, phk, base, nullptr, sk);
             return;
         }
         if (nrm == 1) {
-            hipLaunchKernelGGL((k_sweep_fused<T, false, false, 1>), dim3(blocks), dim3(kFT), 0, s,
-                               op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
-                               f.b, f.c, phk, base, part, sk);
+            launch_fused_inst<T, false, false, 1>(s, op, picard, nz, uin, uout, f, phk, base, part, sk);
             return;
         }
         if (nrm == 2) {
-            hipLaunchKernelGGL((k_sweep_fused<T, false, false, 2>), dim3(blocks), dim3(kFT), 0, s,
-                               op, picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a,
-                               f.b, f.c, phk, base, part, sk);
+            launch_fused_inst<T, false, false, 2>(s, op, picard, nz, uin, uout, f, phk, base, part, sk);
             return;
         }
     }
-    hipLaunchKernelGGL((k_sweep_fused<T, DELTA, false, 0>), dim3(blocks), dim3(kFT), 0, s, op,
-                       picard, nz, uin.a, uin.b, uin.c, uout.a, uout.b, uout.c, f.a, f.b, f.c, phk,
-                       base, nullptr, sk);
+    launch_fused_inst<T, DELTA, false, 0>(s, op, picard, nz, uin, uout, f, phk, base, nullptr, sk);
 }
 
 template void launch_smooth<double, false>(hipStream_t, const OpParams &, int, int, Tri<double>,
