@@ -163,8 +163,10 @@ void bcycle(pfc_batch *B, int d, bool fcycle) {
     if (B->h_mid[d].empty()) return;
     const auto &mid = B->h_mid[d];
     const int picard = B->cfg.lin == PFC_LIN_PICARD;
+    // the finest levels' f.a is their phi^k (make_seg): loaded once there
+    const int pk1 = d == 0 ? 2 : 0;
     auto sweep = [&]() {
-        for (int c = 0; c < 2; ++c) phase(B, BK_SMOOTH, mid, B->d_mid[d], c, picard);
+        for (int c = 0; c < 2; ++c) phase(B, BK_SMOOTH, mid, B->d_mid[d], c, picard | pk1);
     };
     for (int q = 0; q < B->cfg.nu1; ++q) sweep();
     phase(B, BK_RR, mid, B->d_mid[d], 0, 0);

@@ -1202,10 +1202,11 @@ __device__ __forceinline__ TileSpan tile_span(const BSeg &g, int kind, int shape
     return sp;
 }
 
-template <int KIND>
+template <int KIND, bool PK1>
 __device__ __forceinline__ void kb_item(const BSeg &g, unsigned i, int arg0, int arg1) {
     if constexpr (KIND == BK_SMOOTH) {
-        smooth_body<double, false>(g.op, arg0, arg1, g.u, cst(g.f), g.phk, nullptr, i);
+        smooth_body<double, false, false, PK1>(g.op, arg0, arg1 & 1, g.u, cst(g.f), g.phk, nullptr,
+                                               i);
     } else if constexpr (KIND == BK_RR) {
         resid_restrict_body<double, false>(g.op, g.lay_c, cst(g.u), cst(g.f), g.phk, nullptr,
                                            g.ubarc, g.fc, i);
@@ -1220,8 +1221,9 @@ __device__ __forceinline__ void kb_item(const BSeg &g, unsigned i, int arg0, int
 }
 
 // arg0, arg1: colour and picard (BK_SMOOTH); 1 when a smoothing sweep
-// follows (BK_PROLONG: colour-0 mu, omega left unwritten).
-template <int KIND, bool PERSIST>
+// follows (BK_PROLONG: colour-0 mu, omega left unwritten).  PK1 (BK_SMOOTH,
+// arg1 | 2): every segment's f.a is its phi^k (the finest levels), loaded once.
+template <int KIND, bool PERSIST, bool PK1 = false>
 __global__ __launch_bounds__(512) void kb_phase(const BSeg *segs, int nseg, unsigned ntiles,
                                                 int shape, int arg0, int arg1) {
     for (unsigned t = blockIdx.x; t < ntiles; t += PERSIST ? gridDim.x : ntiles) {
@@ -1231,7 +1233,7 @@ __global__ __launch_bounds__(512) void kb_phase(const BSeg *segs, int nseg, unsi
         const TileSpan sp = tile_span(g, KIND, shape, local);
         for (unsigned z = sp.z0; z < sp.z1; ++z)
             for (unsigned r = sp.w0 + threadIdx.x; r < sp.w1; r += blockDim.x)
-                kb_item<KIND>(g, z * sp.Q + r, arg0, arg1);
+                kb_item<KIND, PK1>(g, z * sp.Q + r, arg0, arg1);
     }
 }
 
@@ -1446,15 +1448,15 @@ __global__ __launch_bounds__(kBlock) void kb_reset(BState st, int count, int **v
     *valid[i] = 0;
 }
 
-template <int KIND>
+template <int KIND, bool PK1 = false>
 static void launch_kind(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles, int shape,
                         int threads, unsigned grid, int arg0, int arg1) {
     if (grid)
-        hipLaunchKernelGGL((kb_phase<KIND, true>), dim3(grid), dim3(threads), 0, s, segs, nseg, ntiles,
-                           shape, arg0, arg1);
+        hipLaunchKernelGGL((kb_phase<KIND, true, PK1>), dim3(grid), dim3(threads), 0, s, segs, nseg,
+                           ntiles, shape, arg0, arg1);
     else
-        hipLaunchKernelGGL((kb_phase<KIND, false>), dim3(std::max(ntiles, 1u)), dim3(threads), 0, s,
-                           segs, nseg, ntiles, shape, arg0, arg1);
+        hipLaunchKernelGGL((kb_phase<KIND, false, PK1>), dim3(std::max(ntiles, 1u)), dim3(threads), 0,
+                           s, segs, nseg, ntiles, shape, arg0, arg1);
 }
 
 void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned ntiles, int shape,
@@ -1462,7 +1464,12 @@ void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned 
     // persistent: at most the resident workgroups, at most one per tile
     const unsigned grid = slots ? std::max(1u, std::min(slots, ntiles)) : 0u;
     switch (kind) {
-        case BK_SMOOTH: launch_kind<BK_SMOOTH>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1); break;
+        case BK_SMOOTH:
+            if (arg1 & 2)
+                launch_kind<BK_SMOOTH, true>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1);
+            else
+                launch_kind<BK_SMOOTH>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1);
+            break;
         case BK_RR: launch_kind<BK_RR>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1); break;
         case BK_TAU: launch_kind<BK_TAU>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1); break;
         case BK_ERR: launch_kind<BK_ERR>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1); break;

@@ -68,7 +68,8 @@ __device__ __forceinline__ void point_solve_mob(const OpParams &op, int picard, 
     mu = r2 + c * phi - B * om;
 }
 
-template <typename T, bool DELTA, bool MOB = false>
+// PK1: f.a is phi^k itself (one buffer), loaded once.
+template <typename T, bool DELTA, bool MOB = false, bool PK1 = false>
 __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int picard, Tri<T> u,
                                             Tri<const T> f, const T *__restrict__ phk,
                                             const T *__restrict__ base, unsigned t) {
@@ -110,11 +111,13 @@ __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int 
             msum += mf;
             smm += mf * (double)u.b[nb6[q]];
         }
-        point_solve_mob(op, picard, (double)u.a[own], (double)phk[own], (double)f.a[own],
-                        (double)f.b[own], (double)f.c[own], msum, smm, som, sphi, phi, mu, om);
+        point_solve_mob(op, picard, (double)u.a[own], (double)phk[own],
+                        PK1 ? (double)phk[own] : (double)f.a[own], (double)f.b[own],
+                        (double)f.c[own], msum, smm, som, sphi, phi, mu, om);
     } else {
         point_solve<DELTA>(op, picard, (double)u.a[own], (double)phk[own],
-                           DELTA ? (double)base[own] : 0.0, (double)f.a[own], (double)f.b[own],
+                           DELTA ? (double)base[own] : 0.0,
+                           PK1 ? (double)phk[own] : (double)f.a[own], (double)f.b[own],
                            (double)f.c[own], smu, som, sphi, phi, mu, om);
     }
     u.a[own] = (T)phi;

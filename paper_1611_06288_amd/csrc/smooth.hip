@@ -8,13 +8,13 @@
 
 namespace pfc {
 
-template <typename T, bool DELTA, bool MOB>
+template <typename T, bool DELTA, bool MOB, bool PK1 = false>
 __global__ __launch_bounds__(kBlock) void k_smooth(OpParams op, int colour, int picard, Tri<T> u,
                                                    Tri<const T> f, const T *__restrict__ phk,
                                                    const T *__restrict__ base) {
     if (gate_closed(op.gate)) return;
-    smooth_body<T, DELTA, MOB>(op, colour, picard, u, f, phk, base,
-                               xcd_block() * kBlock + threadIdx.x);
+    smooth_body<T, DELTA, MOB, PK1>(op, colour, picard, u, f, phk, base,
+                                    xcd_block() * kBlock + threadIdx.x);
 }
 
 template <typename T, bool DELTA>
@@ -23,8 +23,17 @@ void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tr
     const size_t H = npts_host(op.lay) / 2;
     if constexpr (!DELTA) {
         if (op.mob.phs) {  // variable mobility
-            hipLaunchKernelGGL((k_smooth<T, false, true>), dim3(blocks_for(H)), dim3(kBlock), 0, s,
-                               op, colour, picard, u, f, phk, base);
+            if (f.a == phk)
+                hipLaunchKernelGGL((k_smooth<T, false, true, true>), dim3(blocks_for(H)), dim3(kBlock),
+                                   0, s, op, colour, picard, u, f, phk, base);
+            else
+                hipLaunchKernelGGL((k_smooth<T, false, true>), dim3(blocks_for(H)), dim3(kBlock), 0,
+                                   s, op, colour, picard, u, f, phk, base);
+            return;
+        }
+        if (f.a == phk) {  // the first source component is phi^k itself: load it once
+            hipLaunchKernelGGL((k_smooth<T, false, false, true>), dim3(blocks_for(H)), dim3(kBlock),
+                               0, s, op, colour, picard, u, f, phk, base);
             return;
         }
     }
