@@ -12,6 +12,11 @@ stops.  Everything here is compared with a host loop of single cycles
 fields, cycle counts and both reported norms bit for bit, for V and F
 cycles, several sweep counts, NOT_CONVERGED at small max_cycles and the
 graph-driven loop; the launch counts show that the split path ran.
+
+The same comparison at finest levels below those sizes (half-sweeps, no
+split) checks that the step's kernels, which take the first source
+component from phi^k itself (one buffer, loaded once), give bit for bit
+what the host loop's kernels give with a separate copy of it.
 """
 import math
 
@@ -81,6 +86,10 @@ def check_step(n, seed, tol, max_cycles, **kw):
     assert torch.equal(cur, cur_r)
     prev = phi
     mu_h, om_h = mu.clone(), om.clone()
+    if kw.get("mobility") is not None:
+        # the host loop's pfc_set_phistar clears the coarsest level's cached
+        # Newton inverse, which a step carries over: start both afresh
+        s.reset_coarse_cache()
     s.timing(True)
     s.timing_reset()
     nxt, info = s.step(prev, cur, mu, om, raise_on_error=False)
@@ -120,6 +129,15 @@ def test_step_equals_host_loop_mobility(n, cycle, nu):
     assert counts[PFC_KERNEL_NORM0] == 1
     assert counts[PFC_KERNEL_SWEEP_NORM0] == c
     assert counts[PFC_KERNEL_SMOOTH0] == c * (nu[0] + nu[1]) - (c - 1)
+
+
+@pytest.mark.parametrize("n,mobility", [(32, None), (64, None), (64, MOB)])
+def test_half_sweep_levels_equal_host_loop(n, mobility):
+    s, info, counts = check_step(n, 20 + n, 1e-10, 400, mobility=mobility)
+    assert info.status == 0 and info.cycles >= 3
+    # V(2,2) in half-sweeps: eight finest-level launches per cycle, no split
+    assert counts[PFC_KERNEL_SWEEP_NORM0] == 0
+    assert counts[PFC_KERNEL_SMOOTH0] == 8 * info.cycles
 
 
 @pytest.mark.parametrize("max_cycles", [1, 2, 3])
