@@ -229,6 +229,20 @@ __device__ __forceinline__ void resid_from_lap(const OpParams &op, const double 
     r[2] = f2 - (om - w3 * ls[0]);
 }
 
+// N(u) at one point from u's own values and the discrete Laplacians ls of phi,
+// mu and omega there (ls[1] the flux sum where the mobility varies): the
+// coarse-level term of the tau correction f_c = N_c(I u) + I r (Algorithm
+// algorithm:FAS).  The tau kernel and the sweep that forms the correction as
+// it smooths both call it, so their results agree bit for bit.
+template <bool DELTA>
+__device__ __forceinline__ void n_of_point(const OpParams &op, const double (&ls)[3], double phi,
+                                           double mu, double om, double ak, double bb,
+                                           double (&nv)[3]) {
+    nv[0] = phi - op.tau * ls[1];
+    nv[1] = mu - g_of<DELTA>(op.fo, phi, ak, bb) - lin_of(op) * phi - ls[2];
+    nv[2] = om - w3_of(op) * ls[0];
+}
+
 __device__ __forceinline__ double wave_max(double v) {
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     return v;

@@ -361,16 +361,13 @@ __device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, 
     } else {
         lmu = (nsum(ubar.b, q) - 6.0 * mu) * op.h2inv;
     }
-    const double lom = (nsum(ubar.c, q) - 6.0 * om) * op.h2inv;
-    const double lphi = (nsum(ubar.a, q) - 6.0 * phi) * op.h2inv;
-    const double a = phk[t];
-    const double b = DELTA ? (double)base[t] : 0.0;
-    const double n1 = phi - op.tau * lmu;
-    const double n2 = mu - g_of<DELTA>(op.fo, phi, a, b) - lin_of(op) * phi - lom;
-    const double n3 = om - w3_of(op) * lphi;
-    f.a[t] = (T)((double)f.a[t] + n1);
-    f.b[t] = (T)((double)f.b[t] + n2);
-    f.c[t] = (T)((double)f.c[t] + n3);
+    const double ls[3] = {(nsum(ubar.a, q) - 6.0 * phi) * op.h2inv, lmu,
+                          (nsum(ubar.c, q) - 6.0 * om) * op.h2inv};
+    double nv[3];
+    n_of_point<DELTA>(op, ls, phi, mu, om, (double)phk[t], DELTA ? (double)base[t] : 0.0, nv);
+    f.a[t] = (T)((double)f.a[t] + nv[0]);
+    f.b[t] = (T)((double)f.b[t] + nv[1]);
+    f.c[t] = (T)((double)f.c[t] + nv[2]);
     if (u.a) {
         u.a[t] = ubar.a[t];
         u.b[t] = ubar.b[t];

@@ -53,21 +53,33 @@ pfc_status mixed_init(pfc_handle *H) {
     return PFC_OK;
 }
 
-static void sweep32(pfc_handle *H, int l) {
+// tau: the first sweep of a coarse level, forming the tau correction from
+// I e = ebar as it smooths (launch_smooth_tau).
+static void sweep32(pfc_handle *H, int l, bool tau = false) {
     Level32 &A = H->lev32[l];
     const OpParams op = op_of(H, l);
     if (H->lev[l].n <= kSmallSweepN) {  // both colours in one workgroup
-        launch_sweep_small<float, true>(H->stream, op, 0, A.e, cst(A.f), A.phk, A.base);
+        if (tau)
+            launch_sweep_small_tau<float, true>(H->stream, op, 0, A.e, A.f, cst(A.ebar), A.phk,
+                                                A.base);
+        else
+            launch_sweep_small<float, true>(H->stream, op, 0, A.e, cst(A.f), A.phk, A.base);
         return;
     }
     for (int colour = 0; colour < 2; ++colour) {
         H->begin_timed(PFC_KERNEL_SMOOTH0, l);
-        launch_smooth<float, true>(H->stream, op, colour, 0, A.e, cst(A.f), A.phk, A.base);
+        if (tau)
+            launch_smooth_tau<float, true>(H->stream, op, colour, 0, A.e, A.f, cst(A.ebar), A.phk,
+                                           A.base);
+        else
+            launch_smooth<float, true>(H->stream, op, colour, 0, A.e, cst(A.f), A.phk, A.base);
         H->end_timed();
     }
 }
 
-static void cycle32(pfc_handle *H, int l, bool fcycle) {
+// tau: f of level l holds I r and its iterate is still in ebar (the first
+// pre-sweep forms the tau correction).
+static void cycle32(pfc_handle *H, int l, bool fcycle, bool tau = false) {
     Level32 &A = H->lev32[l];
     if (l == H->nlev - 1) {
         H->begin_timed(PFC_KERNEL_COARSE, l);
@@ -78,7 +90,7 @@ static void cycle32(pfc_handle *H, int l, bool fcycle) {
     }
     Level32 &B = H->lev32[l + 1];
     const Lay &LB = H->lev[l + 1].lay;
-    for (int s = 0; s < H->cfg.nu1; ++s) sweep32(H, l);
+    for (int s = 0; s < H->cfg.nu1; ++s) sweep32(H, l, tau && s == 0);
     H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
     if (H->lev[l].rt) {
         ResidTileArgs ra;
@@ -95,8 +107,12 @@ static void cycle32(pfc_handle *H, int l, bool fcycle) {
                                            A.base, B.ebar, B.f);
     }
     H->end_timed();
-    launch_tau<float, true>(H->stream, op_of(H, l + 1), cst(B.ebar), B.f, B.e, B.phk, B.base);
-    cycle32(H, l + 1, fcycle);
+    // a coarse level other than the coarsest forms the tau correction in its
+    // first pre-sweep
+    const bool tau_sweep = l + 1 < H->nlev - 1 && H->cfg.nu1 >= 1;
+    if (!tau_sweep)
+        launch_tau<float, true>(H->stream, op_of(H, l + 1), cst(B.ebar), B.f, B.e, B.phk, B.base);
+    cycle32(H, l + 1, fcycle, tau_sweep);
     if (fcycle) cycle32(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
     launch_prolong<float>(H->stream, LB, H->lev[l].lay, cst(B.e), cst(B.ebar), A.e, nullptr,

@@ -78,6 +78,15 @@ template <typename T, bool DELTA>
 void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
                    Tri<const T> f, const T *phk, const T *base);
 
+// The first half-sweep of colour `colour` on a coarse level whose iterate
+// starts at I u (ubar), forming the tau correction f += N(I u) at that
+// colour's points as it smooths (f holds I r on entry, I u is not copied into
+// u); two calls (colour 0, then 1) equal launch_tau followed by two
+// launch_smooth calls bit for bit.
+template <typename T, bool DELTA>
+void launch_smooth_tau(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
+                       Tri<T> f, Tri<const T> ubar, const T *phk, const T *base);
+
 // One full red-black sweep in place on a level of at most kSmallSweepN^3
 // points, by a single workgroup (colour 0, barrier, colour 1).  Measured:
 // 3.8 us against two 2.3 us launches at 8^3, but 14 us against two 3.3 us
@@ -86,6 +95,11 @@ constexpr int kSmallSweepN = 8;
 template <typename T, bool DELTA>
 void launch_sweep_small(hipStream_t s, const OpParams &op, int picard, Tri<T> u, Tri<const T> f,
                         const T *phk, const T *base);
+// The same as the first sweep of a coarse level, forming the tau correction
+// (as launch_smooth_tau).
+template <typename T, bool DELTA>
+void launch_sweep_small_tau(hipStream_t s, const OpParams &op, int picard, Tri<T> u, Tri<T> f,
+                            Tri<const T> ubar, const T *phk, const T *base);
 
 // One full red-black sweep (colour 0 then colour 1) from uin into uout
 // (distinct buffers, colour-split storage), bitwise equal to two launch_smooth

@@ -218,7 +218,7 @@ pfc_handle::~pfc_handle() {
 
 namespace pfc {
 
-void sweep64(pfc_handle *H, int l, int nrm, bool from_ubar, bool then_sweep) {
+void sweep64(pfc_handle *H, int l, int nrm, bool from_ubar, bool then_sweep, bool tau) {
     Level &A = H->lev[l];
     const OpParams op = op_of(H, l);
     if (A.fused) {  // one pass, then the two iterate buffers trade places
@@ -236,17 +236,26 @@ void sweep64(pfc_handle *H, int l, int nrm, bool from_ubar, bool then_sweep) {
         std::swap(A.u, A.u2);
         return;
     }
+    const int picard = H->cfg.lin == PFC_LIN_PICARD;
     if (A.n <= kSmallSweepN) {  // both colours in one workgroup
         H->begin_timed(PFC_KERNEL_SMOOTH0, l);
-        launch_sweep_small<double, false>(H->stream, op, H->cfg.lin == PFC_LIN_PICARD, A.u,
-                                          frhs(H, l), A.phk, nullptr);
+        if (tau)
+            launch_sweep_small_tau<double, false>(H->stream, op, picard, A.u, A.f, cst(A.ubar),
+                                                  A.phk, nullptr);
+        else
+            launch_sweep_small<double, false>(H->stream, op, picard, A.u, frhs(H, l), A.phk,
+                                              nullptr);
         H->end_timed();
         return;
     }
     for (int colour = 0; colour < 2; ++colour) {
         H->begin_timed(PFC_KERNEL_SMOOTH0, l);
-        launch_smooth<double, false>(H->stream, op, colour, H->cfg.lin == PFC_LIN_PICARD, A.u,
-                                     frhs(H, l), A.phk, nullptr);
+        if (tau)
+            launch_smooth_tau<double, false>(H->stream, op, colour, picard, A.u, A.f, cst(A.ubar),
+                                             A.phk, nullptr);
+        else
+            launch_smooth<double, false>(H->stream, op, colour, picard, A.u, frhs(H, l), A.phk,
+                                         nullptr);
         H->end_timed();
     }
 }
@@ -263,7 +272,8 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
     }
     Level &B = H->lev[l + 1];
     for (int s = (flags & kCyclePreDone) ? 1 : 0; s < H->cfg.nu1; ++s)
-        sweep64(H, l, 0, s == 0 && (flags & kCycleFromUbar), s + 1 < H->cfg.nu1);
+        sweep64(H, l, 0, s == 0 && (flags & kCycleFromUbar), s + 1 < H->cfg.nu1,
+                s == 0 && (flags & kCycleTauSweep));
     H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
     if (A.rt) {
         ResidTileArgs ra;
@@ -280,12 +290,17 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
     }
     H->end_timed();
     // a fused coarse level with pre-sweeps starts from I u where the
-    // restriction left it, so tau writes no copy into B.u
+    // restriction left it, so tau writes no copy into B.u; a coarse level of
+    // half-sweeps (not the coarsest) forms the tau correction in its first
+    // sweep, which reads I u there
     const bool from_ubar = B.fused && H->cfg.nu1 >= 1;
-    launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f,
-                              from_ubar ? Tri<double>{nullptr, nullptr, nullptr} : B.u, B.phk,
-                              nullptr);
-    cycle64(H, l + 1, fcycle, from_ubar ? kCycleFromUbar : 0u);
+    const bool tau_sweep = !B.fused && l + 1 < H->nlev - 1 && H->cfg.nu1 >= 1;
+    if (!tau_sweep)
+        launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f,
+                                  from_ubar ? Tri<double>{nullptr, nullptr, nullptr} : B.u, B.phk,
+                                  nullptr);
+    cycle64(H, l + 1, fcycle,
+            from_ubar ? kCycleFromUbar : (tau_sweep ? kCycleTauSweep : 0u));
     if (fcycle) cycle64(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
     launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u, H->gate,

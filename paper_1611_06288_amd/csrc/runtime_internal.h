@@ -123,6 +123,9 @@ constexpr unsigned kCyclePreDone = 1;   // its first pre-sweep has already run (
 constexpr unsigned kCyclePostNorm = 2;  // its last post-sweep leaves the colour-1 norm half
 constexpr unsigned kCycleFromUbar = 4;  // (fused level) the iterate is still in ubar: the
                                         // first pre-sweep reads it there
+constexpr unsigned kCycleTauSweep = 8;  // (half-sweep level) f holds I r and the iterate is
+                                        // still in ubar: the first pre-sweep forms the tau
+                                        // correction and reads the old values there
 void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags = 0);
 // Level l's right-hand side as its kernels read it.  In a time step the
 // first component of the finest level's S is phi^k itself (scheme-PFC-s1),
@@ -138,8 +141,11 @@ inline Tri<const double> frhs(const pfc_handle *H, int l) {
 // One smoothing sweep of level l; nrm as in launch_sweep_fused (split_norm
 // only); from_ubar: a fused sweep reading its input from the level's ubar;
 // then_sweep: the next operation on the iterate is another sweep of this
-// level (a fused sweep then leaves the dead colour-0 mu, omega unwritten).
-void sweep64(pfc_handle *H, int l, int nrm = 0, bool from_ubar = false, bool then_sweep = false);
+// level (a fused sweep then leaves the dead colour-0 mu, omega unwritten);
+// tau: a half-sweep level's first sweep forming the tau correction
+// (launch_smooth_tau).
+void sweep64(pfc_handle *H, int l, int nrm = 0, bool from_ubar = false, bool then_sweep = false,
+             bool tau = false);
 void restrict_phk(pfc_handle *H);
 pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out);
 int enqueue_norm64(pfc_handle *H, unsigned long long *dst = nullptr);

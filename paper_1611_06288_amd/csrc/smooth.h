@@ -69,10 +69,20 @@ __device__ __forceinline__ void point_solve_mob(const OpParams &op, int picard, 
 }
 
 // PK1: f.a is phi^k itself (one buffer), loaded once.
-template <typename T, bool DELTA, bool MOB = false, bool PK1 = false>
+// TAU (the first sweep on a coarse level): the point's right-hand side first
+// takes the tau correction, f + N(I u) with I u = uo, written back through
+// fw, and the old values come from uo since the level's iterate u has not been
+// started at I u: colour 0 reads every neighbour and its own value there,
+// colour 1 its own value and, for N(I u), its old colour-0 neighbours, while
+// its solve takes the new colour-0 neighbours from u.  Same arithmetic and
+// order as the tau kernel (copying I u into u) followed by two plain
+// half-sweeps, so the results agree bit for bit.
+template <typename T, bool DELTA, bool MOB = false, bool PK1 = false, bool TAU = false>
 __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int picard, Tri<T> u,
                                             Tri<const T> f, const T *__restrict__ phk,
-                                            const T *__restrict__ base, unsigned t) {
+                                            const T *__restrict__ base, unsigned t,
+                                            Tri<const T> uo = Tri<const T>{nullptr, nullptr, nullptr},
+                                            Tri<T> fw = Tri<T>{nullptr, nullptr, nullptr}) {
     const Lay &L = op.lay;
     const int n = L.n, hn = n >> 1;
     const unsigned H = (unsigned)((size_t)n * n * n / 2);
@@ -92,6 +102,73 @@ __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int 
     const size_t yp = oc + ((size_t)k * n + wrap_p(j, n)) * hn + m;
     const size_t zm = oc + ((size_t)wrap_m(k, n) * n + j) * hn + m;
     const size_t zp = oc + ((size_t)wrap_p(k, n) * n + j) * hn + m;
+
+    if constexpr (TAU) {
+        static_assert(!PK1, "coarse levels only");
+        const bool c0 = colour == 0;
+        // the solve's neighbours: old ones (uo) for colour 0, new colour 0 (u) for colour 1
+        const T *na = c0 ? uo.a : u.a, *nb = c0 ? uo.b : u.b, *nc = c0 ? uo.c : u.c;
+        const double smu = ((double)nb[xp] + (double)nb[xm]) + ((double)nb[yp] + (double)nb[ym]) +
+                           ((double)nb[zp] + (double)nb[zm]);
+        const double som = ((double)nc[xp] + (double)nc[xm]) + ((double)nc[yp] + (double)nc[ym]) +
+                           ((double)nc[zp] + (double)nc[zm]);
+        const double sphi = ((double)na[xp] + (double)na[xm]) + ((double)na[yp] + (double)na[ym]) +
+                            ((double)na[zp] + (double)na[zm]);
+        // neighbour sums of I u for N(I u): the same values for colour 0
+        double tmu = smu, tom = som, tphi = sphi;
+        if (!c0) {
+            tmu = ((double)uo.b[xp] + (double)uo.b[xm]) + ((double)uo.b[yp] + (double)uo.b[ym]) +
+                  ((double)uo.b[zp] + (double)uo.b[zm]);
+            tom = ((double)uo.c[xp] + (double)uo.c[xm]) + ((double)uo.c[yp] + (double)uo.c[ym]) +
+                  ((double)uo.c[zp] + (double)uo.c[zm]);
+            tphi = ((double)uo.a[xp] + (double)uo.a[xm]) + ((double)uo.a[yp] + (double)uo.a[ym]) +
+                   ((double)uo.a[zp] + (double)uo.a[zm]);
+        }
+        const double p0 = (double)uo.a[own], m0 = (double)uo.b[own], w0 = (double)uo.c[own];
+        const double ak = (double)phk[own], bb = DELTA ? (double)base[own] : 0.0;
+        double ls[3] = {(tphi - 6.0 * p0) * op.h2inv, 0.0, (tom - 6.0 * w0) * op.h2inv};
+        const size_t nb6[6] = {xp, xm, yp, ym, zp, zm};
+        if constexpr (MOB) {  // flux sums of the tau term (old mu) and of the solve (nb)
+            const double *ps = op.mob.phs;
+            const double pc = ps[own];
+            double sm = 0.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                sm += face_mob(op.mob, pc, ps[nb6[q]]) * ((double)uo.b[nb6[q]] - m0);
+            ls[1] = sm * op.h2inv;
+        } else {
+            ls[1] = (tmu - 6.0 * m0) * op.h2inv;
+        }
+        double nv[3];
+        n_of_point<DELTA>(op, ls, p0, m0, w0, ak, bb, nv);
+        const T fa = (T)((double)f.a[own] + nv[0]);
+        const T fb = (T)((double)f.b[own] + nv[1]);
+        const T fc = (T)((double)f.c[own] + nv[2]);
+        fw.a[own] = fa;
+        fw.b[own] = fb;
+        fw.c[own] = fc;
+        double phi, mu, om;
+        if constexpr (MOB) {
+            const double *ps = op.mob.phs;
+            const double pc = ps[own];
+            double msum = 0.0, smm = 0.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const double mf = face_mob(op.mob, pc, ps[nb6[q]]);
+                msum += mf;
+                smm += mf * (double)nb[nb6[q]];
+            }
+            point_solve_mob(op, picard, p0, ak, (double)fa, (double)fb, (double)fc, msum, smm, som,
+                            sphi, phi, mu, om);
+        } else {
+            point_solve<DELTA>(op, picard, p0, ak, bb, (double)fa, (double)fb, (double)fc, smu, som,
+                               sphi, phi, mu, om);
+        }
+        u.a[own] = (T)phi;
+        u.b[own] = (T)mu;
+        u.c[own] = (T)om;
+        return;
+    }
 
     const double smu = ((double)u.b[xp] + (double)u.b[xm]) + ((double)u.b[yp] + (double)u.b[ym]) +
                        ((double)u.b[zp] + (double)u.b[zm]);

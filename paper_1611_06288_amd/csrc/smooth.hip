@@ -41,6 +41,42 @@ void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tr
                        colour, picard, u, f, phk, base);
 }
 
+// One half-sweep of the first sweep on a coarse level, forming the tau
+// correction as it goes (smooth_body, TAU): f += N(I u) at the colour's
+// points, the old values read from ubar = I u.
+template <typename T, bool DELTA, bool MOB>
+__global__ __launch_bounds__(kBlock) void k_smooth_tau(OpParams op, int colour, int picard,
+                                                       Tri<T> u, Tri<T> f, Tri<const T> ubar,
+                                                       const T *__restrict__ phk,
+                                                       const T *__restrict__ base) {
+    if (gate_closed(op.gate)) return;
+    smooth_body<T, DELTA, MOB, false, true>(op, colour, picard, u,
+                                            Tri<const T>{f.a, f.b, f.c}, phk, base,
+                                            xcd_block() * kBlock + threadIdx.x, ubar, f);
+}
+
+template <typename T, bool DELTA>
+void launch_smooth_tau(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
+                       Tri<T> f, Tri<const T> ubar, const T *phk, const T *base) {
+    const size_t H = npts_host(op.lay) / 2;
+    if constexpr (!DELTA) {
+        if (op.mob.phs) {
+            hipLaunchKernelGGL((k_smooth_tau<T, false, true>), dim3(blocks_for(H)), dim3(kBlock), 0,
+                               s, op, colour, picard, u, f, ubar, phk, base);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_smooth_tau<T, DELTA, false>), dim3(blocks_for(H)), dim3(kBlock), 0, s,
+                       op, colour, picard, u, f, ubar, phk, base);
+}
+
+template void launch_smooth_tau<double, false>(hipStream_t, const OpParams &, int, int,
+                                               Tri<double>, Tri<double>, Tri<const double>,
+                                               const double *, const double *);
+template void launch_smooth_tau<float, true>(hipStream_t, const OpParams &, int, int, Tri<float>,
+                                             Tri<float>, Tri<const float>, const float *,
+                                             const float *);
+
 // ------------------------------------------------ small-level full sweep
 //
 // Levels of at most kSmallSweepN^3 points: one workgroup runs both colours,
@@ -84,6 +120,47 @@ template void launch_sweep_small<double, false>(hipStream_t, const OpParams &, i
                                                 Tri<const double>, const double *, const double *);
 template void launch_sweep_small<float, true>(hipStream_t, const OpParams &, int, Tri<float>,
                                               Tri<const float>, const float *, const float *);
+
+// The same, as the first sweep of a coarse level forming the tau correction
+// (smooth_body, TAU).
+template <typename T, bool DELTA, bool MOB>
+__global__ __launch_bounds__(kSmallSweepThreads) void k_sweep_small_tau(
+    OpParams op, int picard, Tri<T> u, Tri<T> f, Tri<const T> ubar, const T *__restrict__ phk,
+    const T *__restrict__ base) {
+    if (gate_closed(op.gate)) return;
+    const unsigned H = (unsigned)(npts(op.lay) / 2);
+    for (int colour = 0; colour < 2; ++colour) {
+        for (unsigned t = threadIdx.x; t < H; t += blockDim.x)
+            smooth_body<T, DELTA, MOB, false, true>(op, colour, picard, u,
+                                                    Tri<const T>{f.a, f.b, f.c}, phk, base, t,
+                                                    ubar, f);
+        __syncthreads();
+    }
+}
+
+template <typename T, bool DELTA>
+void launch_sweep_small_tau(hipStream_t s, const OpParams &op, int picard, Tri<T> u, Tri<T> f,
+                            Tri<const T> ubar, const T *phk, const T *base) {
+    const size_t H = npts_host(op.lay) / 2;
+    const unsigned threads =
+        (unsigned)std::min<size_t>(kSmallSweepThreads, (H + 63) / 64 * 64);
+    if constexpr (!DELTA) {
+        if (op.mob.phs) {
+            hipLaunchKernelGGL((k_sweep_small_tau<T, false, true>), dim3(1), dim3(threads), 0, s, op,
+                               picard, u, f, ubar, phk, base);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_sweep_small_tau<T, DELTA, false>), dim3(1), dim3(threads), 0, s, op,
+                       picard, u, f, ubar, phk, base);
+}
+
+template void launch_sweep_small_tau<double, false>(hipStream_t, const OpParams &, int,
+                                                    Tri<double>, Tri<double>, Tri<const double>,
+                                                    const double *, const double *);
+template void launch_sweep_small_tau<float, true>(hipStream_t, const OpParams &, int, Tri<float>,
+                                                  Tri<float>, Tri<const float>, const float *,
+                                                  const float *);
 
 // ------------------------------------------------- fused red-black sweep
 //
