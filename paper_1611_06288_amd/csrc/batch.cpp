@@ -157,21 +157,29 @@ pfc_status bfail(pfc_batch *B, pfc_status s, const std::string &m) {
 }
 
 // One cycle of every active instance, aligned by depth from the finest level.
-void bcycle(pfc_batch *B, int d, bool fcycle) {
+// tau: the levels at depth d still hold I r in f and I u in ubar (the middle
+// levels' first pre-sweep, the coarsest levels' solve launch forms the tau
+// correction).
+void bcycle(pfc_batch *B, int d, bool fcycle, bool tau = false) {
     const hipStream_t s = B->stream;
-    if (!B->h_bot[d].empty()) launch_batch_coarse(s, B->d_bot[d], (int)B->h_bot[d].size());
+    if (!B->h_bot[d].empty())
+        launch_batch_coarse(s, B->d_bot[d], (int)B->h_bot[d].size(), tau ? 1 : 0);
     if (B->h_mid[d].empty()) return;
     const auto &mid = B->h_mid[d];
     const int picard = B->cfg.lin == PFC_LIN_PICARD;
     // the finest levels' f.a is their phi^k (make_seg): loaded once there
     const int pk1 = d == 0 ? 2 : 0;
-    auto sweep = [&]() {
-        for (int c = 0; c < 2; ++c) phase(B, BK_SMOOTH, mid, B->d_mid[d], c, picard | pk1);
+    auto sweep = [&](int flags) {
+        for (int c = 0; c < 2; ++c) phase(B, BK_SMOOTH, mid, B->d_mid[d], c, picard | pk1 | flags);
     };
-    for (int q = 0; q < B->cfg.nu1; ++q) sweep();
+    for (int q = 0; q < B->cfg.nu1; ++q) sweep(q == 0 && tau ? 4 : 0);
     phase(B, BK_RR, mid, B->d_mid[d], 0, 0);
-    phase(B, BK_TAU, B->h_all[d + 1], B->d_all[d + 1], 0, 0);
-    bcycle(B, d + 1, fcycle);
+    // with pre-sweeps the next depth's levels form the tau correction
+    // themselves: the middle ones in their first sweep, the coarsest ones in
+    // their solve's launch
+    const bool tau_sweep = B->cfg.nu1 >= 1;
+    if (!tau_sweep) phase(B, BK_TAU, B->h_all[d + 1], B->d_all[d + 1], 0, 0);
+    bcycle(B, d + 1, fcycle, tau_sweep);
     if (fcycle) bcycle(B, d + 1, false);
     if (d == 0 && B->ptile) {  // forms the coarse error itself
         launch_batch_ptile(s, B->d_mid[0], (int)mid.size(), ptile_tiles(mid, B->ptile_zi),
@@ -180,7 +188,7 @@ void bcycle(pfc_batch *B, int d, bool fcycle) {
         phase(B, BK_ERR, mid, B->d_mid[d], 0, 0);
         phase(B, BK_PROLONG, mid, B->d_mid[d], B->cfg.nu2 >= 1 ? 1 : 0, 0);
     }
-    for (int q = 0; q < B->cfg.nu2; ++q) sweep();
+    for (int q = 0; q < B->cfg.nu2; ++q) sweep(0);
 }
 
 void record_cycle(pfc_batch *B) {

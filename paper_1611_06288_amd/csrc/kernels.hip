@@ -835,6 +835,9 @@ __device__ __forceinline__ void coarse_body(const OpParams &op, Tri<T> u, Tri<co
     }
 }
 
+// With ubar.a set, the level's tau correction comes first: f += N(I u) with
+// I u = ubar (f holds I r; written through fw, the same buffer as f) and the
+// iterate starts at I u, as the tau kernel does, then a barrier.
 template <typename T, bool DELTA, bool MOB>
 __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const T> f,
                                                const T *__restrict__ phk,
@@ -842,24 +845,30 @@ __global__ __launch_bounds__(64) void k_coarse(OpParams op, Tri<T> u, Tri<const 
                                                const double *__restrict__ lap1,
                                                const double *__restrict__ lap3, double *minv,
                                                int *valid, int *iters,
-                                               const double *__restrict__ lap2) {
+                                               const double *__restrict__ lap2, Tri<const T> ubar,
+                                               Tri<T> fw) {
     if (gate_closed(op.gate)) return;
+    if (ubar.a) {
+        for (unsigned t = threadIdx.x; t < (unsigned)npts(op.lay); t += blockDim.x)
+            tau_body<T, DELTA, MOB>(op, ubar, fw, u, phk, base, t);
+        __syncthreads();
+    }
     coarse_body<T, DELTA, MOB>(op, u, f, phk, base, lap1, lap3, minv, valid, iters, lap2);
 }
 
 template <typename T, bool DELTA>
 void launch_coarse(hipStream_t s, const OpParams &op, Tri<T> u, Tri<const T> f, const T *phk,
                    const T *base, const double *lap1, const double *lap3, double *minv, int *,
-                   int *valid, int *iters, const double *lap2) {
+                   int *valid, int *iters, const double *lap2, Tri<const T> ubar, Tri<T> fw) {
     if constexpr (!DELTA) {
         if (op.mob.phs) {
             hipLaunchKernelGGL((k_coarse<T, false, true>), dim3(1), dim3(64), 0, s, op, u, f, phk,
-                               base, lap1, lap3, minv, valid, iters, lap2);
+                               base, lap1, lap3, minv, valid, iters, lap2, ubar, fw);
             return;
         }
     }
     hipLaunchKernelGGL((k_coarse<T, DELTA, false>), dim3(1), dim3(64), 0, s, op, u, f, phk, base,
-                       lap1, lap3, minv, valid, iters, lap2);
+                       lap1, lap3, minv, valid, iters, lap2, ubar, fw);
 }
 
 // --------------------------------------------------------------- source
@@ -1199,11 +1208,11 @@ __device__ __forceinline__ TileSpan tile_span(const BSeg &g, int kind, int shape
     return sp;
 }
 
-template <int KIND, bool PK1>
+template <int KIND, bool PK1, bool TAU>
 __device__ __forceinline__ void kb_item(const BSeg &g, unsigned i, int arg0, int arg1) {
     if constexpr (KIND == BK_SMOOTH) {
-        smooth_body<double, false, false, PK1>(g.op, arg0, arg1 & 1, g.u, cst(g.f), g.phk, nullptr,
-                                               i);
+        smooth_body<double, false, false, PK1, TAU>(g.op, arg0, arg1 & 1, g.u, cst(g.f), g.phk,
+                                                    nullptr, i, cst(g.ubar), g.f);
     } else if constexpr (KIND == BK_RR) {
         resid_restrict_body<double, false>(g.op, g.lay_c, cst(g.u), cst(g.f), g.phk, nullptr,
                                            g.ubarc, g.fc, i);
@@ -1220,7 +1229,9 @@ __device__ __forceinline__ void kb_item(const BSeg &g, unsigned i, int arg0, int
 // arg0, arg1: colour and picard (BK_SMOOTH); 1 when a smoothing sweep
 // follows (BK_PROLONG: colour-0 mu, omega left unwritten).  PK1 (BK_SMOOTH,
 // arg1 | 2): every segment's f.a is its phi^k (the finest levels), loaded once.
-template <int KIND, bool PERSIST, bool PK1 = false>
+// TAU (BK_SMOOTH, arg1 | 4): the first sweep of coarse levels, forming the tau
+// correction from I u as it smooths (smooth_body).
+template <int KIND, bool PERSIST, bool PK1 = false, bool TAU = false>
 __global__ __launch_bounds__(512) void kb_phase(const BSeg *segs, int nseg, unsigned ntiles,
                                                 int shape, int arg0, int arg1) {
     for (unsigned t = blockIdx.x; t < ntiles; t += PERSIST ? gridDim.x : ntiles) {
@@ -1230,14 +1241,20 @@ __global__ __launch_bounds__(512) void kb_phase(const BSeg *segs, int nseg, unsi
         const TileSpan sp = tile_span(g, KIND, shape, local);
         for (unsigned z = sp.z0; z < sp.z1; ++z)
             for (unsigned r = sp.w0 + threadIdx.x; r < sp.w1; r += blockDim.x)
-                kb_item<KIND, PK1>(g, z * sp.Q + r, arg0, arg1);
+                kb_item<KIND, PK1, TAU>(g, z * sp.Q + r, arg0, arg1);
     }
 }
 
-__global__ __launch_bounds__(64) void kb_coarse(const BSeg *segs, int nseg) {
+// tau: each segment's tau correction first (as k_coarse with ubar set).
+__global__ __launch_bounds__(64) void kb_coarse(const BSeg *segs, int nseg, int tau) {
     const int s = blockIdx.x;
     if (s >= nseg || !*segs[s].active) return;
     const BSeg &g = segs[s];
+    if (tau) {
+        for (unsigned t = threadIdx.x; t < (unsigned)npts(g.op.lay); t += blockDim.x)
+            tau_body<double, false>(g.op, cst(g.ubar), g.f, g.u, g.phk, nullptr, t);
+        __syncthreads();
+    }
     coarse_body<double, false>(g.op, g.u, cst(g.f), g.phk, nullptr, g.lap1, g.lap3, g.minv, g.valid,
                                g.iters);
 }
@@ -1445,15 +1462,15 @@ __global__ __launch_bounds__(kBlock) void kb_reset(BState st, int count, int **v
     *valid[i] = 0;
 }
 
-template <int KIND, bool PK1 = false>
+template <int KIND, bool PK1 = false, bool TAU = false>
 static void launch_kind(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles, int shape,
                         int threads, unsigned grid, int arg0, int arg1) {
     if (grid)
-        hipLaunchKernelGGL((kb_phase<KIND, true, PK1>), dim3(grid), dim3(threads), 0, s, segs, nseg,
-                           ntiles, shape, arg0, arg1);
+        hipLaunchKernelGGL((kb_phase<KIND, true, PK1, TAU>), dim3(grid), dim3(threads), 0, s, segs,
+                           nseg, ntiles, shape, arg0, arg1);
     else
-        hipLaunchKernelGGL((kb_phase<KIND, false, PK1>), dim3(std::max(ntiles, 1u)), dim3(threads), 0,
-                           s, segs, nseg, ntiles, shape, arg0, arg1);
+        hipLaunchKernelGGL((kb_phase<KIND, false, PK1, TAU>), dim3(std::max(ntiles, 1u)),
+                           dim3(threads), 0, s, segs, nseg, ntiles, shape, arg0, arg1);
 }
 
 void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned ntiles, int shape,
@@ -1464,6 +1481,9 @@ void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned 
         case BK_SMOOTH:
             if (arg1 & 2)
                 launch_kind<BK_SMOOTH, true>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1);
+            else if (arg1 & 4)
+                launch_kind<BK_SMOOTH, false, true>(s, segs, nseg, ntiles, shape, threads, grid, arg0,
+                                                    arg1);
             else
                 launch_kind<BK_SMOOTH>(s, segs, nseg, ntiles, shape, threads, grid, arg0, arg1);
             break;
@@ -1491,8 +1511,8 @@ int batch_phase_slots(int kind, int threads, int device) {
     return occ * cus;
 }
 
-void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg) {
-    hipLaunchKernelGGL(kb_coarse, dim3(nseg), dim3(64), 0, s, segs, nseg);
+void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg, int tau) {
+    hipLaunchKernelGGL(kb_coarse, dim3(nseg), dim3(64), 0, s, segs, nseg, tau);
 }
 
 void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles,
@@ -1520,7 +1540,8 @@ void launch_batch_reset(hipStream_t s, BState st, int count, int **valid) {
                                             unsigned long long *);                                \
     template void launch_coarse<T, DELTA>(hipStream_t, const OpParams &, Tri<T>, Tri<const T>,    \
                                           const T *, const T *, const double *, const double *,   \
-                                          double *, int *, int *, int *, const double *);
+                                          double *, int *, int *, int *, const double *,          \
+                                          Tri<const T>, Tri<T>);
 
 PFC_INST(double, false)
 PFC_INST(float, true)

@@ -78,13 +78,15 @@ static void sweep32(pfc_handle *H, int l, bool tau = false) {
 }
 
 // tau: f of level l holds I r and its iterate is still in ebar (the first
-// pre-sweep forms the tau correction).
+// pre-sweep, on the coarsest the solve's launch, forms the tau correction).
 static void cycle32(pfc_handle *H, int l, bool fcycle, bool tau = false) {
     Level32 &A = H->lev32[l];
     if (l == H->nlev - 1) {
         H->begin_timed(PFC_KERNEL_COARSE, l);
-        launch_coarse<float, true>(H->stream, op_of(H, l), A.e, cst(A.f), A.phk, A.base, H->lap1,
-                                   H->lap3, H->minv32, nullptr, H->valid32, H->d_iters);
+        launch_coarse<float, true>(
+            H->stream, op_of(H, l), A.e, cst(A.f), A.phk, A.base, H->lap1, H->lap3, H->minv32,
+            nullptr, H->valid32, H->d_iters, nullptr,
+            tau ? cst(A.ebar) : Tri<const float>{nullptr, nullptr, nullptr}, A.f);
         H->end_timed();
         return;
     }
@@ -107,9 +109,9 @@ static void cycle32(pfc_handle *H, int l, bool fcycle, bool tau = false) {
                                            A.base, B.ebar, B.f);
     }
     H->end_timed();
-    // a coarse level other than the coarsest forms the tau correction in its
-    // first pre-sweep
-    const bool tau_sweep = l + 1 < H->nlev - 1 && H->cfg.nu1 >= 1;
+    // a coarse level forms the tau correction in its first pre-sweep, the
+    // coarsest in its solve's launch
+    const bool tau_sweep = l + 1 == H->nlev - 1 || H->cfg.nu1 >= 1;
     if (!tau_sweep)
         launch_tau<float, true>(H->stream, op_of(H, l + 1), cst(B.ebar), B.f, B.e, B.phk, B.base);
     cycle32(H, l + 1, fcycle, tau_sweep);

@@ -203,11 +203,15 @@ void launch_stop_test(hipStream_t s, const unsigned long long *partial, int coun
 
 // Coarsest level (natural layout, n = 3 or 4).  lu/piv: cached factorisation
 // of the Newton matrix (device scratch of 64*64 doubles and 64 ints), reused
-// across calls while *lu_valid is set.
+// across calls while *lu_valid is set.  With ubar.a set the launch first
+// applies the level's tau correction (f holds I r; fw is f writable) and
+// starts u at I u = ubar, as launch_tau does.
 template <typename T, bool DELTA>
 void launch_coarse(hipStream_t s, const OpParams &op, Tri<T> u, Tri<const T> f, const T *phk,
                    const T *base, const double *lap1, const double *lap3, double *lu, int *piv,
-                   int *lu_valid, int *iters, const double *lap2 = nullptr);
+                   int *lu_valid, int *iters, const double *lap2 = nullptr,
+                   Tri<const T> ubar = Tri<const T>{nullptr, nullptr, nullptr},
+                   Tri<T> fw = Tri<T>{nullptr, nullptr, nullptr});
 
 // phi* = 3/2 phi^k - 1/2 phi^{k-1} from natural-layout inputs into layout L.
 void launch_phistar(hipStream_t s, const Lay &L, const double *phk, const double *phkm1,
@@ -293,7 +297,7 @@ void launch_batch(hipStream_t s, int kind, const BSeg *segs, int nseg, unsigned 
 void bseg_planes_host(const BSeg &g, int kind, unsigned &Q, unsigned &NPL);
 // Resident workgroups of a phase kind's kernel at `threads` per workgroup.
 int batch_phase_slots(int kind, int threads, int device);
-void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg);
+void launch_batch_coarse(hipStream_t s, const BSeg *segs, int nseg, int tau);
 void launch_batch_norm(hipStream_t s, const BSeg *segs, int nseg, unsigned ntiles,
                        unsigned long long *partial, BState st, double tol, int max_cycles);
 void launch_batch_reset(hipStream_t s, BState st, int count, int **valid);

@@ -264,9 +264,12 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
     Level &A = H->lev[l];
     if (l == H->nlev - 1) {
         H->begin_timed(PFC_KERNEL_COARSE, l);
-        launch_coarse<double, false>(H->stream, op_of(H, l), A.u, cst(A.f), A.phk, nullptr,
-                                     H->lap1, H->lap3, H->minv64, nullptr, H->valid64, H->d_iters,
-                                     H->lap2);
+        // kCycleTauSweep: the solve applies the level's tau correction first
+        launch_coarse<double, false>(
+            H->stream, op_of(H, l), A.u, cst(A.f), A.phk, nullptr, H->lap1, H->lap3, H->minv64,
+            nullptr, H->valid64, H->d_iters, H->lap2,
+            (flags & kCycleTauSweep) ? cst(A.ubar) : Tri<const double>{nullptr, nullptr, nullptr},
+            A.f);
         H->end_timed();
         return;
     }
@@ -291,10 +294,10 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
     H->end_timed();
     // a fused coarse level with pre-sweeps starts from I u where the
     // restriction left it, so tau writes no copy into B.u; a coarse level of
-    // half-sweeps (not the coarsest) forms the tau correction in its first
-    // sweep, which reads I u there
+    // half-sweeps forms the tau correction in its first sweep, which reads
+    // I u there, and the coarsest in its solve's launch
     const bool from_ubar = B.fused && H->cfg.nu1 >= 1;
-    const bool tau_sweep = !B.fused && l + 1 < H->nlev - 1 && H->cfg.nu1 >= 1;
+    const bool tau_sweep = l + 1 == H->nlev - 1 || (!B.fused && H->cfg.nu1 >= 1);
     if (!tau_sweep)
         launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f,
                                   from_ubar ? Tri<double>{nullptr, nullptr, nullptr} : B.u, B.phk,

@@ -123,9 +123,10 @@ constexpr unsigned kCyclePreDone = 1;   // its first pre-sweep has already run (
 constexpr unsigned kCyclePostNorm = 2;  // its last post-sweep leaves the colour-1 norm half
 constexpr unsigned kCycleFromUbar = 4;  // (fused level) the iterate is still in ubar: the
                                         // first pre-sweep reads it there
-constexpr unsigned kCycleTauSweep = 8;  // (half-sweep level) f holds I r and the iterate is
-                                        // still in ubar: the first pre-sweep forms the tau
-                                        // correction and reads the old values there
+constexpr unsigned kCycleTauSweep = 8;  // (half-sweep or coarsest level) f holds I r and the
+                                        // iterate is still in ubar: the first pre-sweep (the
+                                        // coarsest: its solve) forms the tau correction and
+                                        // reads the old values there
 void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags = 0);
 // Level l's right-hand side as its kernels read it.  In a time step the
 // first component of the finest level's S is phi^k itself (scheme-PFC-s1),
