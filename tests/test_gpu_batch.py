@@ -29,17 +29,18 @@ def small_ensemble():
     return out
 
 
-@pytest.mark.parametrize("cycle", ["V", "F"])
-def test_batch_matches_single_instances(cycle):
+@pytest.mark.parametrize("cycle,nu", [("V", (2, 2)), ("F", (2, 2)), ("V", (0, 2)), ("V", (1, 1))])
+def test_batch_matches_single_instances(cycle, nu):
     from paper_1611_06288_amd.solver import Batch, Solver
     ens = small_ensemble()
     steps = 3
-    b = Batch(ens, tol=1e-10, cycle=cycle)
+    b = Batch(ens, tol=1e-10, cycle=cycle, nu1=nu[0], nu2=nu[1])
     for i, p in enumerate(ens):
         b.init_state(i, dev(p["phi0"]))
     infos = b.run(steps)
     for i, p in enumerate(ens):
-        s = Solver(p["n"], p["L"], p["eps"], p["dt"], tol=1e-10, cycle=cycle)
+        s = Solver(p["n"], p["L"], p["eps"], p["dt"], tol=1e-10, cycle=cycle, nu1=nu[0],
+                   nu2=nu[1])
         prev, cur, mu, om, sinfos = s.simulate(dev(p["phi0"]), steps)
         bprev, bcur, bmu, bom = b.get_state(i)
         assert [x.cycles for x in infos[i]] == [x.cycles for x in sinfos], i

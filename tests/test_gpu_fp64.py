@@ -235,6 +235,28 @@ def test_one_cycle_matches_oracle(n, cycle):
         assert res == pytest.approx(res_o, rel=1e-9)
 
 
+@pytest.mark.parametrize("n,nu", [(32, (0, 2)), (32, (1, 1)), (32, (2, 1)), (128, (0, 2)),
+                                  (128, (1, 3))])
+def test_cycles_with_other_sweep_counts_match_oracle(n, nu):
+    """V(nu1, nu2): without pre-sweeps every coarse level takes the tau
+    kernel (and its copy of I u) before the coarsest solve; with them the
+    coarse levels of half-sweeps form the correction in their first sweep."""
+    s = make(n, nu1=nu[0], nu2=nu[1])
+    phk = inputs.polycrystal_phi0(n, s.L, 2, seed=650 + n, radius_cells=4)
+    phkm1 = phk + 0.005 * inputs.random_field(n, 651 + n)
+    f = cfas.source(phk, phkm1, s.h, s.eps)
+    mu, om = cfas.initial_guess(phk, s.h, s.eps)
+    u = np.stack([phk, mu, om])
+    o = cfas.Solver(n, s.L, s.eps, s.dt, nu1=nu[0], nu2=nu[1])
+    ud, fd, pd = dev(u), dev(f), dev(phk)
+    for _ in range(2):
+        res = s.vcycle(ud, fd, pd)
+        u, res_o = o.cycle(u, f, phk)
+        for c in range(3):
+            assert rel(host(ud)[c], u[c]) < CYCLE_RTOL
+        assert res == pytest.approx(res_o, rel=1e-9)
+
+
 # ------------------------------------------------------------ step level
 
 def run_both(n, L, eps, dt, phi0, steps, tol=1e-10, **kw):

@@ -30,13 +30,13 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def oracle_trajectory(phi0, L, eps, dt, steps, tol, cycle):
+def oracle_trajectory(phi0, L, eps, dt, steps, tol, cycle, nu=(2, 2)):
     """The oracle's states (phi^{k-1}, phi^k, mu, omega) before each step,
     and its step results (phi^{k+1}, mu, omega, cycles)."""
     n = phi0.shape[0]
     mu, om = cfas.initial_guess(phi0, L / n, eps)
     ins, outs = [], []
-    o = cfas.Solver(n, L, eps, dt, tol=tol, cycle=cycle)
+    o = cfas.Solver(n, L, eps, dt, tol=tol, cycle=cycle, nu1=nu[0], nu2=nu[1])
     prev, cur = phi0, phi0
     for _ in range(steps):
         ins.append((prev, cur, mu.copy(), om.copy()))
@@ -48,10 +48,10 @@ def oracle_trajectory(phi0, L, eps, dt, steps, tol, cycle):
     return ins, outs
 
 
-def check_mixed_steps(n, L, eps, dt, phi0, steps, tol, cycle):
+def check_mixed_steps(n, L, eps, dt, phi0, steps, tol, cycle, nu=(2, 2), bar=BAR):
     from paper_1611_06288_amd import Solver
-    ins, outs = oracle_trajectory(phi0, L, eps, dt, steps, tol, cycle)
-    s = Solver(n, L, eps, dt, tol=tol, precision="mixed", cycle=cycle)
+    ins, outs = oracle_trajectory(phi0, L, eps, dt, steps, tol, cycle, nu)
+    s = Solver(n, L, eps, dt, tol=tol, precision="mixed", cycle=cycle, nu1=nu[0], nu2=nu[1])
     errs = []
     for k, ((prev, cur, mu0, om0), (o_phi, o_mu, o_om, o_cyc)) in enumerate(zip(ins, outs)):
         mu, om = dev(mu0), dev(om0)
@@ -62,7 +62,8 @@ def check_mixed_steps(n, L, eps, dt, phi0, steps, tol, cycle):
             want = (o_phi, o_mu, o_om)
         else:
             # the oracle's iterate after the mixed form's cycle count
-            o = cfas.Solver(n, L, eps, dt, tol=1e-300, cycle=cycle, max_cycles=info.cycles)
+            o = cfas.Solver(n, L, eps, dt, tol=1e-300, cycle=cycle, max_cycles=info.cycles,
+                            nu1=nu[0], nu2=nu[1])
             w_phi, w_mu, w_om, w_info = o.step(prev, cur, mu0, om0)
             o.close()
             assert w_info.cycles == info.cycles
@@ -74,7 +75,7 @@ def check_mixed_steps(n, L, eps, dt, phi0, steps, tol, cycle):
               f"{info.cycles} cycles {err_same:.2e}")
         assert info.status == 0 and info.res_final <= tol
         assert o_cyc <= info.cycles <= o_cyc + 2
-        assert err_same <= BAR, (k, err_same)
+        assert err_same <= bar, (k, err_same)
     return errs
 
 
@@ -83,6 +84,20 @@ def test_mixed_matches_fp64_oracle_polycrystal(n, cycle, steps):
     L, eps, dt, tol = n * math.pi / 4, 0.25, 0.5, 1e-10
     phi0 = inputs.polycrystal_phi0(n, L, 2, seed=900 + n, radius_cells=4)
     check_mixed_steps(n, L, eps, dt, phi0, steps, tol, cycle)
+
+
+@pytest.mark.parametrize("nu,bar", [((0, 2), 1e-11), ((1, 1), BAR)])
+def test_mixed_other_sweep_counts(nu, bar):
+    """Without pre-sweeps the FP32 cycle's coarse levels take the tau kernel;
+    with one they form the correction in that sweep.  Without pre-sweeps the
+    correction is formed from an unsmoothed residual and its FP32 rounding
+    reaches 2.5e-12 against the oracle's iterate after the same 17 cycles
+    (measured, also before the coarse levels formed the correction in their
+    sweeps), hence a bar of 1e-11 there."""
+    n = 32
+    L, eps, dt, tol = n * math.pi / 4, 0.25, 0.5, 1e-10
+    phi0 = inputs.polycrystal_phi0(n, L, 2, seed=950 + nu[0], radius_cells=4)
+    check_mixed_steps(n, L, eps, dt, phi0, 2, tol, "V", nu, bar)
 
 
 def test_mixed_smooth_mode_32():
