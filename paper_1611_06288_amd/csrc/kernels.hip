@@ -431,19 +431,30 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
     const unsigned f0 = sidx32(LF, 2 * I, j, k), f1 = sidx32(LF, 2 * I + 1, j, k);
     // one component; all three are issued together when there are three
     auto comp_add = [&](const T *vv, const T *uu, T *ff, bool w0, bool w1) {
+        // the 12 coarse values, loaded in one block (the test on uu is taken
+        // once, so that the loads are issued together)
+        double e[3][2][2];
+        if (uu) {
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+                for (int z = 0; z < 2; ++z)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)  // v - ubar rounded to T: what coarse_err_body stores
+                        e[x][z][y] = (double)(T)((double)vv[o[z][y][x]] - (double)uu[o[z][y][x]]);
+        } else {
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+                for (int z = 0; z < 2; ++z)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) e[x][z][y] = (double)vv[o[z][y][x]];
+        }
         double w[3];  // y/z-interpolated values at x = I-1, I, I+1
 #pragma unroll
-        for (int x = 0; x < 3; ++x) {
-            double e[2][2];
-#pragma unroll
-            for (int z = 0; z < 2; ++z)
-#pragma unroll
-                for (int y = 0; y < 2; ++y)
-                    // v - ubar rounded to T: the value coarse_err_body stores
-                    e[z][y] = uu ? (double)(T)((double)vv[o[z][y][x]] - (double)uu[o[z][y][x]])
-                                 : (double)vv[o[z][y][x]];
-            w[x] = 0.75 * (0.75 * e[0][0] + 0.25 * e[0][1]) + 0.25 * (0.75 * e[1][0] + 0.25 * e[1][1]);
-        }
+        for (int x = 0; x < 3; ++x)
+            w[x] = 0.75 * (0.75 * e[x][0][0] + 0.25 * e[x][0][1]) +
+                   0.25 * (0.75 * e[x][1][0] + 0.25 * e[x][1][1]);
         if (w0) ff[f0] = (T)((double)ff[f0] + (0.75 * w[1] + 0.25 * w[0]));
         if (w1) ff[f1] = (T)((double)ff[f1] + (0.75 * w[1] + 0.25 * w[2]));
     };
@@ -459,9 +470,13 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
 template <typename T>
 __device__ __forceinline__ void coarse_err_body(size_t P, Tri<const T> v, Tri<T> ubar, unsigned t) {
     if (t >= P) return;
-    ubar.a[t] = (T)((double)v.a[t] - (double)ubar.a[t]);
-    ubar.b[t] = (T)((double)v.b[t] - (double)ubar.b[t]);
-    ubar.c[t] = (T)((double)v.c[t] - (double)ubar.c[t]);
+    // all six loads ahead of the first store, which may alias them as far as
+    // the compiler knows
+    const double va = v.a[t], vb = v.b[t], vc = v.c[t];
+    const double ua = ubar.a[t], ub = ubar.b[t], uc = ubar.c[t];
+    ubar.a[t] = (T)(va - ua);
+    ubar.b[t] = (T)(vb - ub);
+    ubar.c[t] = (T)(vc - uc);
 }
 
 template <typename T>
