@@ -363,15 +363,18 @@ __device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, 
     }
     const double ls[3] = {(nsum(ubar.a, q) - 6.0 * phi) * op.h2inv, lmu,
                           (nsum(ubar.c, q) - 6.0 * om) * op.h2inv};
+    // every load ahead of the first store (which may alias them as far as the
+    // compiler knows); I u's own values are copied from phi, mu, om (exact)
+    const double f0 = f.a[t], f1 = f.b[t], f2 = f.c[t];
     double nv[3];
     n_of_point<DELTA>(op, ls, phi, mu, om, (double)phk[t], DELTA ? (double)base[t] : 0.0, nv);
-    f.a[t] = (T)((double)f.a[t] + nv[0]);
-    f.b[t] = (T)((double)f.b[t] + nv[1]);
-    f.c[t] = (T)((double)f.c[t] + nv[2]);
+    f.a[t] = (T)(f0 + nv[0]);
+    f.b[t] = (T)(f1 + nv[1]);
+    f.c[t] = (T)(f2 + nv[2]);
     if (u.a) {
-        u.a[t] = ubar.a[t];
-        u.b[t] = ubar.b[t];
-        u.c[t] = ubar.c[t];
+        u.a[t] = (T)phi;
+        u.b[t] = (T)mu;
+        u.c[t] = (T)om;
     }
 }
 
@@ -1225,9 +1228,16 @@ __device__ __forceinline__ TileSpan tile_span(const BSeg &g, int kind, int shape
 
 template <int KIND, bool PK1, bool TAU>
 __device__ __forceinline__ void kb_item(const BSeg &g, unsigned i, int arg0, int arg1) {
-    if constexpr (KIND == BK_SMOOTH) {
-        smooth_body<double, false, false, PK1, TAU>(g.op, arg0, arg1 & 1, g.u, cst(g.f), g.phk,
-                                                    nullptr, i, cst(g.ubar), g.f);
+    if constexpr (KIND == BK_SMOOTH && TAU) {  // colour as a constant: loads in one block
+        if (arg0 == 0)
+            smooth_body<double, false, false, false, true, 0>(g.op, 0, arg1 & 1, g.u, cst(g.f),
+                                                              g.phk, nullptr, i, cst(g.ubar), g.f);
+        else
+            smooth_body<double, false, false, false, true, 1>(g.op, 1, arg1 & 1, g.u, cst(g.f),
+                                                              g.phk, nullptr, i, cst(g.ubar), g.f);
+    } else if constexpr (KIND == BK_SMOOTH) {
+        smooth_body<double, false, false, PK1>(g.op, arg0, arg1 & 1, g.u, cst(g.f), g.phk, nullptr,
+                                               i);
     } else if constexpr (KIND == BK_RR) {
         resid_restrict_body<double, false>(g.op, g.lay_c, cst(g.u), cst(g.f), g.phk, nullptr,
                                            g.ubarc, g.fc, i);

@@ -76,8 +76,11 @@ __device__ __forceinline__ void point_solve_mob(const OpParams &op, int picard, 
 // colour 1 its own value and, for N(I u), its old colour-0 neighbours, while
 // its solve takes the new colour-0 neighbours from u.  Same arithmetic and
 // order as the tau kernel (copying I u into u) followed by two plain
-// half-sweeps, so the results agree bit for bit.
-template <typename T, bool DELTA, bool MOB = false, bool PK1 = false, bool TAU = false>
+// half-sweeps, so the results agree bit for bit.  TCOL: the colour as a
+// compile-time constant (TAU only), so that all of a point's loads are issued
+// in one block.
+template <typename T, bool DELTA, bool MOB = false, bool PK1 = false, bool TAU = false,
+          int TCOL = -1>
 __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int picard, Tri<T> u,
                                             Tri<const T> f, const T *__restrict__ phk,
                                             const T *__restrict__ base, unsigned t,
@@ -104,8 +107,12 @@ __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int 
     const size_t zp = oc + ((size_t)wrap_p(k, n) * n + j) * hn + m;
 
     if constexpr (TAU) {
-        static_assert(!PK1, "coarse levels only");
-        const bool c0 = colour == 0;
+        static_assert(!PK1 && (TCOL == 0 || TCOL == 1), "coarse levels, colour fixed");
+        constexpr bool c0 = TCOL == 0;
+        // own old values, phi^k, base and right-hand side, loaded ahead
+        const double p0 = (double)uo.a[own], m0 = (double)uo.b[own], w0 = (double)uo.c[own];
+        const double ak = (double)phk[own], bb = DELTA ? (double)base[own] : 0.0;
+        const double f0 = (double)f.a[own], f1 = (double)f.b[own], f2 = (double)f.c[own];
         // the solve's neighbours: old ones (uo) for colour 0, new colour 0 (u) for colour 1
         const T *na = c0 ? uo.a : u.a, *nb = c0 ? uo.b : u.b, *nc = c0 ? uo.c : u.c;
         const double smu = ((double)nb[xp] + (double)nb[xm]) + ((double)nb[yp] + (double)nb[ym]) +
@@ -116,7 +123,7 @@ __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int 
                             ((double)na[zp] + (double)na[zm]);
         // neighbour sums of I u for N(I u): the same values for colour 0
         double tmu = smu, tom = som, tphi = sphi;
-        if (!c0) {
+        if constexpr (!c0) {
             tmu = ((double)uo.b[xp] + (double)uo.b[xm]) + ((double)uo.b[yp] + (double)uo.b[ym]) +
                   ((double)uo.b[zp] + (double)uo.b[zm]);
             tom = ((double)uo.c[xp] + (double)uo.c[xm]) + ((double)uo.c[yp] + (double)uo.c[ym]) +
@@ -124,8 +131,6 @@ __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int 
             tphi = ((double)uo.a[xp] + (double)uo.a[xm]) + ((double)uo.a[yp] + (double)uo.a[ym]) +
                    ((double)uo.a[zp] + (double)uo.a[zm]);
         }
-        const double p0 = (double)uo.a[own], m0 = (double)uo.b[own], w0 = (double)uo.c[own];
-        const double ak = (double)phk[own], bb = DELTA ? (double)base[own] : 0.0;
         double ls[3] = {(tphi - 6.0 * p0) * op.h2inv, 0.0, (tom - 6.0 * w0) * op.h2inv};
         const size_t nb6[6] = {xp, xm, yp, ym, zp, zm};
         if constexpr (MOB) {  // flux sums of the tau term (old mu) and of the solve (nb)
@@ -141,12 +146,9 @@ __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int 
         }
         double nv[3];
         n_of_point<DELTA>(op, ls, p0, m0, w0, ak, bb, nv);
-        const T fa = (T)((double)f.a[own] + nv[0]);
-        const T fb = (T)((double)f.b[own] + nv[1]);
-        const T fc = (T)((double)f.c[own] + nv[2]);
-        fw.a[own] = fa;
-        fw.b[own] = fb;
-        fw.c[own] = fc;
+        const T fa = (T)(f0 + nv[0]);
+        const T fb = (T)(f1 + nv[1]);
+        const T fc = (T)(f2 + nv[2]);
         double phi, mu, om;
         if constexpr (MOB) {
             const double *ps = op.mob.phs;
@@ -164,6 +166,9 @@ __device__ __forceinline__ void smooth_body(const OpParams &op, int colour, int 
             point_solve<DELTA>(op, picard, p0, ak, bb, (double)fa, (double)fb, (double)fc, smu, som,
                                sphi, phi, mu, om);
         }
+        fw.a[own] = fa;  // stores after every load
+        fw.b[own] = fb;
+        fw.c[own] = fc;
         u.a[own] = (T)phi;
         u.b[own] = (T)mu;
         u.c[own] = (T)om;

@@ -44,30 +44,39 @@ void launch_smooth(hipStream_t s, const OpParams &op, int colour, int picard, Tr
 // One half-sweep of the first sweep on a coarse level, forming the tau
 // correction as it goes (smooth_body, TAU): f += N(I u) at the colour's
 // points, the old values read from ubar = I u.
-template <typename T, bool DELTA, bool MOB>
-__global__ __launch_bounds__(kBlock) void k_smooth_tau(OpParams op, int colour, int picard,
-                                                       Tri<T> u, Tri<T> f, Tri<const T> ubar,
+template <typename T, bool DELTA, bool MOB, int COL>
+__global__ __launch_bounds__(kBlock) void k_smooth_tau(OpParams op, int picard, Tri<T> u, Tri<T> f,
+                                                       Tri<const T> ubar,
                                                        const T *__restrict__ phk,
                                                        const T *__restrict__ base) {
     if (gate_closed(op.gate)) return;
-    smooth_body<T, DELTA, MOB, false, true>(op, colour, picard, u,
-                                            Tri<const T>{f.a, f.b, f.c}, phk, base,
-                                            xcd_block() * kBlock + threadIdx.x, ubar, f);
+    smooth_body<T, DELTA, MOB, false, true, COL>(op, COL, picard, u,
+                                                 Tri<const T>{f.a, f.b, f.c}, phk, base,
+                                                 xcd_block() * kBlock + threadIdx.x, ubar, f);
 }
 
 template <typename T, bool DELTA>
 void launch_smooth_tau(hipStream_t s, const OpParams &op, int colour, int picard, Tri<T> u,
                        Tri<T> f, Tri<const T> ubar, const T *phk, const T *base) {
     const size_t H = npts_host(op.lay) / 2;
+    const dim3 grid(blocks_for(H)), block(kBlock);
     if constexpr (!DELTA) {
         if (op.mob.phs) {
-            hipLaunchKernelGGL((k_smooth_tau<T, false, true>), dim3(blocks_for(H)), dim3(kBlock), 0,
-                               s, op, colour, picard, u, f, ubar, phk, base);
+            if (colour == 0)
+                hipLaunchKernelGGL((k_smooth_tau<T, false, true, 0>), grid, block, 0, s, op, picard,
+                                   u, f, ubar, phk, base);
+            else
+                hipLaunchKernelGGL((k_smooth_tau<T, false, true, 1>), grid, block, 0, s, op, picard,
+                                   u, f, ubar, phk, base);
             return;
         }
     }
-    hipLaunchKernelGGL((k_smooth_tau<T, DELTA, false>), dim3(blocks_for(H)), dim3(kBlock), 0, s,
-                       op, colour, picard, u, f, ubar, phk, base);
+    if (colour == 0)
+        hipLaunchKernelGGL((k_smooth_tau<T, DELTA, false, 0>), grid, block, 0, s, op, picard, u, f,
+                           ubar, phk, base);
+    else
+        hipLaunchKernelGGL((k_smooth_tau<T, DELTA, false, 1>), grid, block, 0, s, op, picard, u, f,
+                           ubar, phk, base);
 }
 
 template void launch_smooth_tau<double, false>(hipStream_t, const OpParams &, int, int,
@@ -129,13 +138,13 @@ __global__ __launch_bounds__(kSmallSweepThreads) void k_sweep_small_tau(
     const T *__restrict__ base) {
     if (gate_closed(op.gate)) return;
     const unsigned H = (unsigned)(npts(op.lay) / 2);
-    for (int colour = 0; colour < 2; ++colour) {
-        for (unsigned t = threadIdx.x; t < H; t += blockDim.x)
-            smooth_body<T, DELTA, MOB, false, true>(op, colour, picard, u,
-                                                    Tri<const T>{f.a, f.b, f.c}, phk, base, t,
-                                                    ubar, f);
-        __syncthreads();
-    }
+    const Tri<const T> fc{f.a, f.b, f.c};
+    for (unsigned t = threadIdx.x; t < H; t += blockDim.x)
+        smooth_body<T, DELTA, MOB, false, true, 0>(op, 0, picard, u, fc, phk, base, t, ubar, f);
+    __syncthreads();
+    for (unsigned t = threadIdx.x; t < H; t += blockDim.x)
+        smooth_body<T, DELTA, MOB, false, true, 1>(op, 1, picard, u, fc, phk, base, t, ubar, f);
+    __syncthreads();
 }
 
 template <typename T, bool DELTA>
