@@ -402,6 +402,47 @@ void launch_tau(hipStream_t s, const OpParams &opc, Tri<const T> ubar, Tri<T> f,
 
 // ------------------------------------------------- interpolation + correction
 //
+// The fine x-pair of prolong_body: NC components (1: phi only, 3: all),
+// UB: the coarse error is v - ubar (formed and rounded to T here) or v
+// itself.  All coarse and fine values are loaded first, then added and
+// stored; fine values whose store is skipped (phi0) are loaded all the same.
+template <typename T, int NC, bool UB>
+__device__ __forceinline__ void prolong_pair(Tri<const T> v, Tri<const T> ubar, Tri<T> fine,
+                                             const unsigned (&o)[2][2][3], unsigned f0,
+                                             unsigned f1, bool phi0, bool c1) {
+    const T *vv[3] = {v.a, v.b, v.c};
+    const T *uu[3] = {ubar.a, ubar.b, ubar.c};
+    T *ff[3] = {fine.a, fine.b, fine.c};
+    double e[NC][3][2][2], g0[NC], g1[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int z = 0; z < 2; ++z)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    const unsigned q = o[z][y][x];
+                    // v - ubar rounded to T: what coarse_err_body stores
+                    e[c][x][z][y] = UB ? (double)(T)((double)vv[c][q] - (double)uu[c][q])
+                                       : (double)vv[c][q];
+                }
+        g0[c] = (double)ff[c][f0];
+        g1[c] = (double)ff[c][f1];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double w[3];  // y/z-interpolated values at x = I-1, I, I+1
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+            w[x] = 0.75 * (0.75 * e[c][x][0][0] + 0.25 * e[c][x][0][1]) +
+                   0.25 * (0.75 * e[c][x][1][0] + 0.25 * e[c][x][1][1]);
+        const bool w0 = c == 0 || !phi0 || c1, w1 = c == 0 || !phi0 || !c1;
+        if (w0) ff[c][f0] = (T)(g0[c] + (0.75 * w[1] + 0.25 * w[0]));
+        if (w1) ff[c][f1] = (T)(g1[c] + (0.75 * w[1] + 0.25 * w[2]));
+    }
+}
+
 // fine += P (v - ubar), cell-centred trilinear: along one axis fine cell 2I+d
 // (d = 0, 1) takes 3/4 of coarse cell I and 1/4 of cell I-1 (d = 0) or I+1
 // (d = 1), periodic; 3D weights are products.  One thread per pair of fine
@@ -432,40 +473,19 @@ __device__ __forceinline__ void prolong_body(const Lay &LC, const Lay &LF, Tri<c
 #pragma unroll
             for (int x = 0; x < 3; ++x) o[z][y][x] = sidx32(LC, Ix[x], y ? J1 : J0, z ? K1 : K0);
     const unsigned f0 = sidx32(LF, 2 * I, j, k), f1 = sidx32(LF, 2 * I + 1, j, k);
-    // one component; all three are issued together when there are three
-    auto comp_add = [&](const T *vv, const T *uu, T *ff, bool w0, bool w1) {
-        // the 12 coarse values, loaded in one block (the test on uu is taken
-        // once, so that the loads are issued together)
-        double e[3][2][2];
-        if (uu) {
-#pragma unroll
-            for (int x = 0; x < 3; ++x)
-#pragma unroll
-                for (int z = 0; z < 2; ++z)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y)  // v - ubar rounded to T: what coarse_err_body stores
-                        e[x][z][y] = (double)(T)((double)vv[o[z][y][x]] - (double)uu[o[z][y][x]]);
-        } else {
-#pragma unroll
-            for (int x = 0; x < 3; ++x)
-#pragma unroll
-                for (int z = 0; z < 2; ++z)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) e[x][z][y] = (double)vv[o[z][y][x]];
-        }
-        double w[3];  // y/z-interpolated values at x = I-1, I, I+1
-#pragma unroll
-        for (int x = 0; x < 3; ++x)
-            w[x] = 0.75 * (0.75 * e[x][0][0] + 0.25 * e[x][0][1]) +
-                   0.25 * (0.75 * e[x][1][0] + 0.25 * e[x][1][1]);
-        if (w0) ff[f0] = (T)((double)ff[f0] + (0.75 * w[1] + 0.25 * w[0]));
-        if (w1) ff[f1] = (T)((double)ff[f1] + (0.75 * w[1] + 0.25 * w[2]));
-    };
-    comp_add(v.a, ubar.a, fine.a, true, true);
+    const bool c1 = ((j + k) & 1) != 0;  // (2I, j, k) is colour 1
+    // the uniform tests are taken once, so that every load of a form comes in
+    // one block, ahead of the stores (which may alias them for the compiler)
     if (fine.b) {
-        const bool c1 = ((j + k) & 1) != 0;  // (2I, j, k) is colour 1
-        comp_add(v.b, ubar.b, fine.b, !phi0 || c1, !phi0 || !c1);
-        comp_add(v.c, ubar.c, fine.c, !phi0 || c1, !phi0 || !c1);
+        if (ubar.a)
+            prolong_pair<T, 3, true>(v, ubar, fine, o, f0, f1, phi0, c1);
+        else
+            prolong_pair<T, 3, false>(v, ubar, fine, o, f0, f1, phi0, c1);
+    } else {
+        if (ubar.a)
+            prolong_pair<T, 1, true>(v, ubar, fine, o, f0, f1, phi0, c1);
+        else
+            prolong_pair<T, 1, false>(v, ubar, fine, o, f0, f1, phi0, c1);
     }
 }
 
