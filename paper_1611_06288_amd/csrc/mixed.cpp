@@ -39,6 +39,8 @@ constexpr double kTolMargin = 1.5;
 constexpr double kFloorQ = 0.5;
 
 pfc_status mixed_init(pfc_handle *H) {
+    if (hipEventCreateWithFlags(&H->norm_ev, hipEventDisableTiming) != hipSuccess)
+        return fail(H, PFC_ERR_HIP, "event creation failed");
     for (int l = 0; l < H->nlev; ++l) {
         Level32 &A = H->lev32[l];
         const size_t P = H->lev[l].P;
@@ -200,8 +202,22 @@ static pfc_status mixed_step_on(pfc_handle *H, const double *phi_prev, const dou
         }
         pending = false;
         H->end_timed();
-        const pfc_status st = read_norm(H, cnt, &rho);
-        if (st != PFC_OK) return st;
+        // the norm to the host behind an event; then the next FP32 cycles'
+        // base on every level and their zero start, queued ahead of the
+        // host's wait so that the device works while the host decides
+        // (wasted once per step, after the last defect pass)
+        launch_max_final(H->stream, H->partial, cnt, H->d_scal);
+        HIP_TRY(H, hipMemcpyAsync(H->h_pin, H->d_scal, sizeof(double), hipMemcpyDeviceToHost,
+                                  H->stream));
+        HIP_TRY(H, hipEventRecord(H->norm_ev, H->stream));
+        for (int l = 0; l + 1 < H->nlev; ++l)
+            launch_restrict<float>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev32[l].base,
+                                   H->lev32[l + 1].base);
+        launch_zero(H->stream, A32.e.a, 3 * A.P);
+        HIP_TRY(H, hipGetLastError());
+        HIP_TRY(H, hipEventSynchronize(H->norm_ev));
+        H->collect_timings();
+        rho = H->h_pin[0];
         if (c == 0) rho0 = rho;
         if (!std::isfinite(rho)) {
             status = PFC_ERR_NONFINITE;
@@ -228,10 +244,6 @@ static pfc_status mixed_step_on(pfc_handle *H, const double *phi_prev, const dou
                 predf *= qf;
             }
         }
-        for (int l = 0; l + 1 < H->nlev; ++l)
-            launch_restrict<float>(H->stream, H->lev[l].lay, H->lev[l + 1].lay, H->lev32[l].base,
-                                   H->lev32[l + 1].base);
-        launch_zero(H->stream, A32.e.a, 3 * A.P);
         HIP_TRY(H, hipGetLastError());
         if (!H->mix_exec) {
             const pfc_status st2 = record_cycle32(H);

@@ -209,6 +209,7 @@ pfc_handle::~pfc_handle() {
     if (run_exec) (void)hipGraphExecDestroy(run_exec);
     if (run_graph) (void)hipGraphDestroy(run_graph);
     if (run_ev) (void)hipEventDestroy(run_ev);
+    if (norm_ev) (void)hipEventDestroy(norm_ev);
     if (run_stream) (void)hipStreamDestroy(run_stream);
     for (void *p : allocs) (void)hipFree(p);
     if (h_pin) (void)hipHostFree(h_pin);

@@ -90,6 +90,7 @@ struct pfc_handle {
     const int *gate = nullptr;            // cycle gate, set only while its graph is recorded
     hipStream_t run_stream = nullptr;     // the loop's own stream (capturable)
     hipEvent_t run_ev = nullptr;
+    hipEvent_t norm_ev = nullptr;         // the mixed form's norm copied to the host
     int *d_run = nullptr;                 // active, cycles, status of the current step
     double *d_runres = nullptr;           // res0, res of the current step
     hipGraph_t run_graph = nullptr;       // norm, stop test, one gated cycle
