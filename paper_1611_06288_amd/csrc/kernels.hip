@@ -336,8 +336,7 @@ void launch_restrict(hipStream_t s, const Lay &fine, const Lay &coarse, const T 
 // ------------------------------------------------------- tau correction
 //
 // Coarse right-hand side of the FAS: f_c = N_c(I u) + I r (f holds I r on
-// entry); also starts the coarse iterate at I u, unless u.a is null (a fused
-// coarse level whose first sweep reads I u directly).
+// entry); also starts the coarse iterate at I u, unless u.a is null.
 template <typename T, bool DELTA, bool MOB = false>
 __device__ __forceinline__ void tau_body(const OpParams &op, Tri<const T> ubar, Tri<T> f, Tri<T> u,
                                          const T *__restrict__ phk, const T *__restrict__ base,

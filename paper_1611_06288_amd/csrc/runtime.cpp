@@ -219,9 +219,17 @@ pfc_handle::~pfc_handle() {
 
 namespace pfc {
 
-void sweep64(pfc_handle *H, int l, int nrm, bool from_ubar, bool then_sweep, bool tau) {
+void sweep64(pfc_handle *H, int l, int nrm, bool then_sweep, bool tau) {
     Level &A = H->lev[l];
     const OpParams op = op_of(H, l);
+    if (A.fused && tau) {  // a coarse level's first sweep: two tau-forming half-sweeps from
+                           // I u into the second buffer, which then becomes the iterate
+        for (int colour = 0; colour < 2; ++colour)
+            launch_smooth_tau<double, false>(H->stream, op, colour, H->cfg.lin == PFC_LIN_PICARD,
+                                             A.u2, A.f, cst(A.ubar), A.phk, nullptr);
+        std::swap(A.u, A.u2);
+        return;
+    }
     if (A.fused) {  // one pass, then the two iterate buffers trade places
         if (!H->split_norm || l != 0) nrm = 0;
         unsigned long long *part =
@@ -231,7 +239,7 @@ void sweep64(pfc_handle *H, int l, int nrm, bool from_ubar, bool then_sweep, boo
         // the colour-0 mu, omega writes left out: 8 B/pt fewer
         H->begin_timed(kind, l, skip0 ? algorithmic_bytes(H, kind) - 8.0 * (double)A.P : -1.0);
         launch_sweep_fused<double, false>(H->stream, op, H->cfg.lin == PFC_LIN_PICARD, A.nz,
-                                          from_ubar ? cst(A.ubar) : cst(A.u), A.u2, frhs(H, l), A.phk,
+                                          cst(A.u), A.u2, frhs(H, l), A.phk,
                                           nullptr, nrm, part, skip0);
         H->end_timed();
         std::swap(A.u, A.u2);
@@ -276,8 +284,7 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
     }
     Level &B = H->lev[l + 1];
     for (int s = (flags & kCyclePreDone) ? 1 : 0; s < H->cfg.nu1; ++s)
-        sweep64(H, l, 0, s == 0 && (flags & kCycleFromUbar), s + 1 < H->cfg.nu1,
-                s == 0 && (flags & kCycleTauSweep));
+        sweep64(H, l, 0, s + 1 < H->cfg.nu1, s == 0 && (flags & kCycleTauSweep));
     H->begin_timed(PFC_KERNEL_RESIDUAL0, l);
     if (A.rt) {
         ResidTileArgs ra;
@@ -293,25 +300,22 @@ void cycle64(pfc_handle *H, int l, bool fcycle, unsigned flags) {
                                              A.phk, nullptr, B.ubar, B.f);
     }
     H->end_timed();
-    // a fused coarse level with pre-sweeps starts from I u where the
-    // restriction left it, so tau writes no copy into B.u; a coarse level of
-    // half-sweeps forms the tau correction in its first sweep, which reads
-    // I u there, and the coarsest in its solve's launch
-    const bool from_ubar = B.fused && H->cfg.nu1 >= 1;
-    const bool tau_sweep = l + 1 == H->nlev - 1 || (!B.fused && H->cfg.nu1 >= 1);
+    // with pre-sweeps a coarse level forms the tau correction in its first
+    // sweep (two tau-forming half-sweeps, also on a fused level), which reads
+    // I u where the restriction left it; the coarsest forms it in its solve's
+    // launch
+    const bool tau_sweep = l + 1 == H->nlev - 1 || H->cfg.nu1 >= 1;
     if (!tau_sweep)
-        launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f,
-                                  from_ubar ? Tri<double>{nullptr, nullptr, nullptr} : B.u, B.phk,
+        launch_tau<double, false>(H->stream, op_of(H, l + 1), cst(B.ubar), B.f, B.u, B.phk,
                                   nullptr);
-    cycle64(H, l + 1, fcycle,
-            from_ubar ? kCycleFromUbar : (tau_sweep ? kCycleTauSweep : 0u));
+    cycle64(H, l + 1, fcycle, tau_sweep ? kCycleTauSweep : 0u);
     if (fcycle) cycle64(H, l + 1, false);
     H->begin_timed(PFC_KERNEL_PROLONG0, l);
     launch_prolong<double>(H->stream, B.lay, A.lay, cst(B.u), cst(B.ubar), A.u, H->gate,
                            H->cfg.nu2 >= 1, A.pz[0]);
     H->end_timed();
     for (int s = 0; s < H->cfg.nu2; ++s)
-        sweep64(H, l, (flags & kCyclePostNorm) && s == H->cfg.nu2 - 1 ? 2 : 0, false,
+        sweep64(H, l, (flags & kCyclePostNorm) && s == H->cfg.nu2 - 1 ? 2 : 0,
                 s + 1 < H->cfg.nu2);
 }
 
@@ -616,7 +620,7 @@ pfc_status step64(pfc_handle *h, const double *phi_prev, const double *phi_cur, 
         if (split) {
             // the first pre-sweep of the next cycle; a second pre-sweep follows it
             // when nu1 >= 2 (and if the loop stops its output is dropped)
-            sweep64(h, 0, 1, false, h->cfg.nu1 >= 2);
+            sweep64(h, 0, 1, h->cfg.nu1 >= 2);
             ahead = true;
             st = read_norm(h, 2 * h->split_blocks, &rho);
         } else {

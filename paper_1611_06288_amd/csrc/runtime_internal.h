@@ -119,12 +119,10 @@ struct pfc_handle {
 
 namespace pfc {
 OpParams op_of(const pfc_handle *H, int l);
-// flags of cycle64 at the finest level
+// flags of cycle64 (the first two at the finest level)
 constexpr unsigned kCyclePreDone = 1;   // its first pre-sweep has already run (sweep64 nrm 1)
 constexpr unsigned kCyclePostNorm = 2;  // its last post-sweep leaves the colour-1 norm half
-constexpr unsigned kCycleFromUbar = 4;  // (fused level) the iterate is still in ubar: the
-                                        // first pre-sweep reads it there
-constexpr unsigned kCycleTauSweep = 8;  // (half-sweep or coarsest level) f holds I r and the
+constexpr unsigned kCycleTauSweep = 8;  // (coarse level) f holds I r and the
                                         // iterate is still in ubar: the first pre-sweep (the
                                         // coarsest: its solve) forms the tau correction and
                                         // reads the old values there
@@ -141,12 +139,12 @@ inline Tri<const double> frhs(const pfc_handle *H, int l) {
 }
 
 // One smoothing sweep of level l; nrm as in launch_sweep_fused (split_norm
-// only); from_ubar: a fused sweep reading its input from the level's ubar;
-// then_sweep: the next operation on the iterate is another sweep of this
-// level (a fused sweep then leaves the dead colour-0 mu, omega unwritten);
-// tau: a half-sweep level's first sweep forming the tau correction
-// (launch_smooth_tau).
-void sweep64(pfc_handle *H, int l, int nrm = 0, bool from_ubar = false, bool then_sweep = false,
+// only); then_sweep: the next operation on the iterate is another sweep of
+// this level (a fused sweep then leaves the dead colour-0 mu, omega
+// unwritten); tau: a coarse level's first sweep forming the tau correction
+// (launch_smooth_tau; on a fused level into the second buffer, which then
+// becomes the iterate).
+void sweep64(pfc_handle *H, int l, int nrm = 0, bool then_sweep = false,
              bool tau = false);
 void restrict_phk(pfc_handle *H);
 pfc_status resid_norm64(pfc_handle *H, Tri<double> r, double *out);

@@ -74,7 +74,7 @@ pfc_status record_graph(pfc_handle *H) {
     H->gate = H->d_run;  // every launch below reads the active flag
     const bool fcycle = H->cfg.cycle == PFC_CYCLE_F;
     if (H->split_norm) {
-        sweep64(H, 0, 1, false, H->cfg.nu1 >= 2);
+        sweep64(H, 0, 1, H->cfg.nu1 >= 2);
         launch_stop_test(H->stream, H->partial, 2 * H->split_blocks, H->cfg.tol,
                          H->cfg.max_cycles, run_state(H));
         cycle64(H, 0, fcycle, kCyclePreDone | kCyclePostNorm);
