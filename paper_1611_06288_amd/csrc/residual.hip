@@ -12,7 +12,7 @@
 //                  written to a second buffer (other columns read this one's
 //                  u as their ring in the same launch),
 //   RT_RESTRICT32  RT_RESTRICT for the FP32 correction operator.
-// A workgroup owns an x-y column of kRX x kRY points and a range of planes and
+// A workgroup owns an x-y column of kRX x rt_rows points and a range of planes and
 // walks it in z.  Three planes of u (box plus a one-cell ring, all three
 // fields) sit in an LDS ring; the next plane and the next step's f and phi^k
 // are loaded into registers while the current plane computes, so every value
@@ -31,13 +31,20 @@
 
 namespace pfc {
 
-constexpr int kRX = 64, kRY = 8, kRT = 256;            // column extents, threads
-constexpr int kRC = kRX + 2, kRR = kRY + 2;            // tile with its ring
-constexpr int kRN = kRC * kRR, kRI = (kRN + kRT - 1) / kRT;  // ring points, per thread
+constexpr int kRX = 64, kRC = kRX + 2;  // column x-extent, with its ring
+// Column rows and threads per workgroup: the FP32 restriction takes 16-row
+// columns (its 4-byte rows are short, so the ring rows are the larger share
+// of its fetches), every other mode 8 rows; one thread per x-pair of a row.
+constexpr int rt_rows(int mode) { return mode == RT_RESTRICT32 ? 16 : 8; }
+constexpr int rt_threads(int mode) { return 32 * rt_rows(mode); }
 
 // PK1: the first source component is phi^k itself (one buffer), loaded once.
 template <int MODE, bool MOB, bool PK1 = false>
-__global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTileArgs a) {
+__global__ __launch_bounds__(rt_threads(MODE)) void k_resid_tile(OpParams op, int nz,
+                                                                 ResidTileArgs a) {
+    constexpr int kRY = rt_rows(MODE), kRT = rt_threads(MODE);
+    constexpr int kRR = kRY + 2;                                 // rows with the ring
+    constexpr int kRN = kRC * kRR, kRI = (kRN + kRT - 1) / kRT;  // ring points, per thread
     constexpr bool F32 = MODE == RT_RESTRICT32;
     constexpr bool DELTA = F32;
     constexpr bool RESTRICT = MODE == RT_RESTRICT || MODE == RT_RESTRICT32;
@@ -256,7 +263,9 @@ __global__ __launch_bounds__(kRT) void k_resid_tile(OpParams op, int nz, ResidTi
     }
 }
 
-bool resid_tile_fits(const Lay &L) { return L.split && L.n % kRX == 0 && L.n % kRY == 0; }
+bool resid_tile_fits(const Lay &L) {
+    return L.split && L.n % kRX == 0 && L.n % rt_rows(RT_RESTRICT32) == 0;
+}
 
 static const void *resid_tile_fn(int mode, bool mob) {
     switch (mode) {
@@ -274,7 +283,8 @@ static const void *resid_tile_fn(int mode, bool mob) {
 
 int resid_tile_slots(int device, int mode, bool mob) {
     int occ = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, resid_tile_fn(mode, mob), kRT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, resid_tile_fn(mode, mob),
+                                                     rt_threads(mode), 0) !=
             hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
@@ -285,7 +295,7 @@ int resid_tile_slots(int device, int mode, bool mob) {
 // whole number of resident waves with at least 4 planes (2 plane pairs for
 // the restriction) per range, within the partial-result buffer.
 int resid_tile_nz(int n, int slots, int mode) {
-    const int cols = (n / kRX) * (n / kRY);
+    const int cols = (n / kRX) * (n / rt_rows(mode));
     const bool pairs = mode == RT_RESTRICT || mode == RT_RESTRICT32;
     const int units = pairs ? n / 2 : n;  // plane pairs or planes
     const int minu = pairs ? 2 : 4;
@@ -297,41 +307,42 @@ int resid_tile_nz(int n, int slots, int mode) {
 
 int launch_resid_tile(hipStream_t s, int mode, const OpParams &op, int nz, const ResidTileArgs &a) {
     const int n = op.lay.n;
-    const unsigned blocks = (unsigned)((n / kRX) * (n / kRY) * nz);
+    const unsigned blocks = (unsigned)((n / kRX) * (n / rt_rows(mode)) * nz);
+    const dim3 block(rt_threads(mode));
     const bool mob = op.mob.phs != nullptr;  // FP64 modes only (the FP32 cycle has M = 1)
     switch (mode) {
         case RT_RESTRICT:
             if (mob && a.f.a == a.phk)
-                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, true, true>), dim3(blocks), dim3(kRT),
+                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, true, true>), dim3(blocks), block,
                                    0, s, op, nz, a);
             else if (mob)
-                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, true>), dim3(blocks), dim3(kRT), 0, s,
+                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, true>), dim3(blocks), block, 0, s,
                                    op, nz, a);
             else if (a.f.a == a.phk)
-                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, false, true>), dim3(blocks), dim3(kRT),
+                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, false, true>), dim3(blocks), block,
                                    0, s, op, nz, a);
             else
-                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, false>), dim3(blocks), dim3(kRT), 0,
+                hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT, false>), dim3(blocks), block, 0,
                                    s, op, nz, a);
             break;
         case RT_CAST:
-            hipLaunchKernelGGL((k_resid_tile<RT_CAST, false>), dim3(blocks), dim3(kRT), 0, s, op, nz,
+            hipLaunchKernelGGL((k_resid_tile<RT_CAST, false>), dim3(blocks), block, 0, s, op, nz,
                                a);
             break;
         case RT_CAST_CORR:
-            hipLaunchKernelGGL((k_resid_tile<RT_CAST_CORR, false>), dim3(blocks), dim3(kRT), 0, s, op,
+            hipLaunchKernelGGL((k_resid_tile<RT_CAST_CORR, false>), dim3(blocks), block, 0, s, op,
                                nz, a);
             break;
         case RT_RESTRICT32:
-            hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT32, false>), dim3(blocks), dim3(kRT), 0, s,
+            hipLaunchKernelGGL((k_resid_tile<RT_RESTRICT32, false>), dim3(blocks), block, 0, s,
                                op, nz, a);
             break;
         default:
             if (mob)
-                hipLaunchKernelGGL((k_resid_tile<RT_NORM, true>), dim3(blocks), dim3(kRT), 0, s, op,
+                hipLaunchKernelGGL((k_resid_tile<RT_NORM, true>), dim3(blocks), block, 0, s, op,
                                    nz, a);
             else
-                hipLaunchKernelGGL((k_resid_tile<RT_NORM, false>), dim3(blocks), dim3(kRT), 0, s, op,
+                hipLaunchKernelGGL((k_resid_tile<RT_NORM, false>), dim3(blocks), block, 0, s, op,
                                    nz, a);
     }
     return (int)blocks;
